@@ -1,0 +1,492 @@
+/*
+ * Sequential CPU oracle for the linear-probing hash table of Maier, Sanders and
+ * Dementiev, "Concurrent Hash Tables: Fast and General(?)!" (arXiv 1601.04017).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no source, header or table with the HIP path.
+ *
+ * It is deliberately plain: one table, no atomics, no blocking, every bulk call
+ * applies its operations one after another in index order.  The paper's own
+ * "sequential variants" are tables of exactly this kind (Sec. 8.1), and since
+ * the concurrent table is linearizable (Sec. 4) a bulk call of the concurrent
+ * table has the same outcome as this one up to the order of operations.
+ *
+ * Cell layouts (same bytes as the device table so exported arrays compare
+ * directly):
+ *   PACKED32 (layout 0): one u64 word per cell, key in bits 0..31, value in
+ *                        bits 32..63; the all-zero word is an empty cell.
+ *   KV64     (layout 1): two u64 words per cell, key then value.
+ * Reserved keys: 0 = empty_key, 1 = del_key (tombstone) (Sec. 4 "Deletions",
+ * Sec. 5.6 names the two special keys).
+ *
+ * Per-operation result codes: 1 = true, 0 = false, 0xFE = reserved key,
+ * 0xFF = bounded table full.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PACKED32 0
+#define ORC_KV64 1
+
+#define ORC_EMPTY 0ull
+#define ORC_TOMB 1ull
+
+#define ORC_ASSIGN 0
+#define ORC_ADD 1
+
+#define ORC_FLAG_RESERVED 0xFE
+#define ORC_FLAG_FULL 0xFF
+
+#define ORC_STICKY_FULL 1
+#define ORC_STICKY_RESERVED 2
+
+/* ------------------------------------------------------------------------- */
+/* Hash (Sec. 8.3): two CRC-32C computations with different seeds give the    */
+/* upper and lower 32 bits of the 64-bit hash value.                          */
+/* ------------------------------------------------------------------------- */
+
+/* CRC-32C register update over a byte string, bit by bit from the
+ * Castagnoli polynomial in reflected form (0x82F63B78).  No initial or final
+ * inversion: this is the register update that the x86 crc32 instruction the
+ * paper uses performs, starting from the register value `reg`. */
+uint32_t orc_crc32c_bytes(uint32_t reg, const uint8_t *buf, uint64_t len) {
+  for (uint64_t i = 0; i < len; ++i) {
+    reg ^= (uint32_t)buf[i];
+    for (int bit = 0; bit < 8; ++bit) {
+      if (reg & 1u)
+        reg = (reg >> 1) ^ 0x82F63B78u;
+      else
+        reg = reg >> 1;
+    }
+  }
+  return reg;
+}
+
+/* CRC-32C update over the `nbytes` little-endian bytes of a key word. */
+uint32_t orc_crc32c_word(uint32_t reg, uint64_t x, int nbytes) {
+  uint8_t b[8];
+  for (int i = 0; i < nbytes; ++i) b[i] = (uint8_t)(x >> (8 * i));
+  return orc_crc32c_bytes(reg, b, (uint64_t)nbytes);
+}
+
+/* h(x) = CRC(seed_hi, x) * 2^32 + CRC(seed_lo, x). */
+uint64_t orc_hash(uint64_t key, int key_bytes, uint32_t seed_hi, uint32_t seed_lo) {
+  uint64_t hi = orc_crc32c_word(seed_hi, key, key_bytes);
+  uint64_t lo = orc_crc32c_word(seed_lo, key, key_bytes);
+  return (hi << 32) | lo;
+}
+
+/* Scaling map of Sec. 5.3.1: h_c(x) = floor(h(x) * c / U) with U = 2^64 and
+ * c = 2^log2c, i.e. the top log2c bits of h. */
+uint64_t orc_home(uint64_t h, uint32_t log2c) {
+  if (log2c == 0) return 0;
+  return h >> (64 - log2c);
+}
+
+/* ------------------------------------------------------------------------- */
+/* The table                                                                  */
+/* ------------------------------------------------------------------------- */
+
+typedef struct orc_table {
+  int layout;
+  uint32_t log2c;
+  uint64_t cap;
+  uint64_t *cells;
+  uint32_t seed_hi, seed_lo;
+  uint32_t alpha_num, alpha_den;
+  int auto_grow;
+  uint64_t used; /* non-empty cells (live keys and tombstones) */
+  uint64_t live; /* live keys */
+  int sticky;
+  uint64_t migrations;
+} orc_table;
+
+static int key_bytes(const orc_table *t) { return t->layout == ORC_PACKED32 ? 4 : 8; }
+
+static uint64_t key_at(const orc_table *t, const uint64_t *cells, uint64_t i) {
+  if (t->layout == ORC_PACKED32) return cells[i] & 0xFFFFFFFFull;
+  return cells[2 * i];
+}
+
+static uint64_t val_at(const orc_table *t, const uint64_t *cells, uint64_t i) {
+  if (t->layout == ORC_PACKED32) return cells[i] >> 32;
+  return cells[2 * i + 1];
+}
+
+static void set_cell(const orc_table *t, uint64_t *cells, uint64_t i, uint64_t k, uint64_t v) {
+  if (t->layout == ORC_PACKED32) {
+    cells[i] = (k & 0xFFFFFFFFull) | ((v & 0xFFFFFFFFull) << 32);
+  } else {
+    cells[2 * i] = k;
+    cells[2 * i + 1] = v;
+  }
+}
+
+static uint64_t words_per_cell(const orc_table *t) { return t->layout == ORC_PACKED32 ? 1 : 2; }
+
+static uint64_t home_of(const orc_table *t, uint64_t k, uint32_t log2c) {
+  return orc_home(orc_hash(k, key_bytes(t), t->seed_hi, t->seed_lo), log2c);
+}
+
+/* Wrapping update function `up` of Algorithm 1: overwrite or add (modulo the
+ * value width). */
+static uint64_t apply_up(const orc_table *t, uint64_t cur, uint64_t d, int op) {
+  uint64_t r = (op == ORC_ADD) ? cur + d : d;
+  if (t->layout == ORC_PACKED32) r &= 0xFFFFFFFFull;
+  return r;
+}
+
+orc_table *orc_create(int layout, uint32_t log2c, uint32_t seed_hi, uint32_t seed_lo,
+                      uint32_t alpha_num, uint32_t alpha_den, int auto_grow) {
+  if (layout != ORC_PACKED32 && layout != ORC_KV64) return NULL;
+  if (log2c < 1 || log2c > 40) return NULL;
+  if (alpha_num == 0 || alpha_den == 0 || alpha_num > alpha_den) return NULL;
+  orc_table *t = (orc_table *)calloc(1, sizeof(orc_table));
+  if (!t) return NULL;
+  t->layout = layout;
+  t->log2c = log2c;
+  t->cap = 1ull << log2c;
+  t->seed_hi = seed_hi;
+  t->seed_lo = seed_lo;
+  t->alpha_num = alpha_num;
+  t->alpha_den = alpha_den;
+  t->auto_grow = auto_grow;
+  /* Sec. 4 "Initialization": every key starts as empty_key; values start 0. */
+  t->cells = (uint64_t *)calloc(t->cap * words_per_cell(t), sizeof(uint64_t));
+  if (!t->cells) {
+    free(t);
+    return NULL;
+  }
+  return t;
+}
+
+void orc_destroy(orc_table *t) {
+  if (!t) return;
+  free(t->cells);
+  free(t);
+}
+
+uint64_t orc_capacity(const orc_table *t) { return t->cap; }
+uint32_t orc_log2_capacity(const orc_table *t) { return t->log2c; }
+uint64_t orc_migrations(const orc_table *t) { return t->migrations; }
+
+void orc_counts(const orc_table *t, uint64_t *used, uint64_t *live) {
+  *used = t->used;
+  *live = t->live;
+}
+
+/* Returns the sticky error bits and clears them. */
+int orc_status(orc_table *t) {
+  int s = t->sticky;
+  t->sticky = 0;
+  return s;
+}
+
+void orc_export(const orc_table *t, uint64_t *dst) {
+  memcpy(dst, t->cells, t->cap * words_per_cell(t) * sizeof(uint64_t));
+}
+
+/* Replaces the cell array by a copy of `src` (2^log2c cells) and recounts. */
+int orc_import(orc_table *t, const uint64_t *src, uint32_t log2c) {
+  if (log2c < 1 || log2c > 40) return -1;
+  uint64_t cap = 1ull << log2c;
+  uint64_t *cells = (uint64_t *)malloc(cap * words_per_cell(t) * sizeof(uint64_t));
+  if (!cells) return -2;
+  memcpy(cells, src, cap * words_per_cell(t) * sizeof(uint64_t));
+  free(t->cells);
+  t->cells = cells;
+  t->log2c = log2c;
+  t->cap = cap;
+  t->used = 0;
+  t->live = 0;
+  for (uint64_t i = 0; i < cap; ++i) {
+    uint64_t k = key_at(t, cells, i);
+    if (k != ORC_EMPTY) t->used++;
+    if (k != ORC_EMPTY && k != ORC_TOMB) t->live++;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Single operations (Sec. 4; Algorithm 1 and its insert/update variants;    */
+/* tombstone deletion of Sec. 5.4).                                           */
+/* ------------------------------------------------------------------------- */
+
+/* insert(k,d): scan from h_c(k); an empty cell receives the element (true);
+ * an equal key means the key is present (false).  Tombstones and other keys
+ * are skipped, so tombstones are never reused. */
+static uint8_t op_insert(orc_table *t, uint64_t k, uint64_t v) {
+  if (k == ORC_EMPTY || k == ORC_TOMB) {
+    t->sticky |= ORC_STICKY_RESERVED;
+    return ORC_FLAG_RESERVED;
+  }
+  uint64_t i = home_of(t, k, t->log2c);
+  for (uint64_t probes = 0; probes < t->cap; ++probes) {
+    uint64_t cur = key_at(t, t->cells, i);
+    if (cur == ORC_EMPTY) {
+      set_cell(t, t->cells, i, k, v);
+      t->used++;
+      t->live++;
+      return 1;
+    }
+    if (cur == k) return 0;
+    i = (i + 1) & (t->cap - 1);
+  }
+  t->sticky |= ORC_STICKY_FULL;
+  return ORC_FLAG_FULL;
+}
+
+/* insertOrUpdate(k,d,up): as insert, but an equal key gets
+ * value := up(value, d); returns true iff a new key was inserted. */
+static uint8_t op_insert_or_update(orc_table *t, uint64_t k, uint64_t d, int op) {
+  if (k == ORC_EMPTY || k == ORC_TOMB) {
+    t->sticky |= ORC_STICKY_RESERVED;
+    return ORC_FLAG_RESERVED;
+  }
+  uint64_t i = home_of(t, k, t->log2c);
+  for (uint64_t probes = 0; probes < t->cap; ++probes) {
+    uint64_t cur = key_at(t, t->cells, i);
+    if (cur == ORC_EMPTY) {
+      set_cell(t, t->cells, i, k, apply_up(t, 0, d, ORC_ASSIGN));
+      t->used++;
+      t->live++;
+      return 1;
+    }
+    if (cur == k) {
+      set_cell(t, t->cells, i, k, apply_up(t, val_at(t, t->cells, i), d, op));
+      return 0;
+    }
+    i = (i + 1) & (t->cap - 1);
+  }
+  t->sticky |= ORC_STICKY_FULL;
+  return ORC_FLAG_FULL;
+}
+
+/* update(k,d,up): false if the key is absent, else value := up(value, d). */
+static uint8_t op_update(orc_table *t, uint64_t k, uint64_t d, int op) {
+  if (k == ORC_EMPTY || k == ORC_TOMB) {
+    t->sticky |= ORC_STICKY_RESERVED;
+    return ORC_FLAG_RESERVED;
+  }
+  uint64_t i = home_of(t, k, t->log2c);
+  for (uint64_t probes = 0; probes < t->cap; ++probes) {
+    uint64_t cur = key_at(t, t->cells, i);
+    if (cur == ORC_EMPTY) return 0;
+    if (cur == k) {
+      set_cell(t, t->cells, i, k, apply_up(t, val_at(t, t->cells, i), d, op));
+      return 1;
+    }
+    i = (i + 1) & (t->cap - 1);
+  }
+  return 0;
+}
+
+/* find(k): a copy of the stored value if the key is present. */
+static uint8_t op_find(orc_table *t, uint64_t k, uint64_t *val) {
+  *val = 0;
+  if (k == ORC_EMPTY || k == ORC_TOMB) {
+    t->sticky |= ORC_STICKY_RESERVED;
+    return ORC_FLAG_RESERVED;
+  }
+  uint64_t i = home_of(t, k, t->log2c);
+  for (uint64_t probes = 0; probes < t->cap; ++probes) {
+    uint64_t cur = key_at(t, t->cells, i);
+    if (cur == ORC_EMPTY) return 0;
+    if (cur == k) {
+      *val = val_at(t, t->cells, i);
+      return 1;
+    }
+    i = (i + 1) & (t->cap - 1);
+  }
+  return 0;
+}
+
+/* Tombstone delete: the key becomes del_key, the value stays. */
+static uint8_t op_erase(orc_table *t, uint64_t k) {
+  if (k == ORC_EMPTY || k == ORC_TOMB) {
+    t->sticky |= ORC_STICKY_RESERVED;
+    return ORC_FLAG_RESERVED;
+  }
+  uint64_t i = home_of(t, k, t->log2c);
+  for (uint64_t probes = 0; probes < t->cap; ++probes) {
+    uint64_t cur = key_at(t, t->cells, i);
+    if (cur == ORC_EMPTY) return 0;
+    if (cur == k) {
+      set_cell(t, t->cells, i, ORC_TOMB, val_at(t, t->cells, i));
+      t->live--;
+      return 1;
+    }
+    i = (i + 1) & (t->cap - 1);
+  }
+  return 0;
+}
+
+/* Number of cells a find for k inspects, the terminating cell included. */
+uint64_t orc_probe_count(const orc_table *t, uint64_t k) {
+  uint64_t i = home_of(t, k, t->log2c);
+  uint64_t probes = 0;
+  while (probes < t->cap) {
+    uint64_t cur = key_at(t, t->cells, i);
+    probes++;
+    if (cur == ORC_EMPTY || cur == k) break;
+    i = (i + 1) & (t->cap - 1);
+  }
+  return probes;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Migration (Sec. 5.3.1, growing with factor gamma = new/old >= 1) and      */
+/* cleanup of tombstones by migration (Sec. 5.4).                             */
+/* ------------------------------------------------------------------------- */
+
+/* The sequential migration: scan the old table once, starting just after an
+ * empty cell so that every cluster (the one that wraps from the last cell to
+ * cell 0 included) is visited contiguously in old-array order, and insert
+ * every live element into the new table with the ordinary linear-probing
+ * rule.  Tombstones are dropped.  A table without any empty cell is scanned
+ * from cell 0.  This is the sequential order whose placement the
+ * block-parallel migration reproduces (Lemma 1). */
+int orc_migrate(orc_table *t, uint32_t log2_new) {
+  if (log2_new < t->log2c || log2_new > 40) return -1;
+  uint64_t newcap = 1ull << log2_new;
+  uint64_t *nc = (uint64_t *)calloc(newcap * words_per_cell(t), sizeof(uint64_t));
+  if (!nc) return -2;
+  uint64_t e = t->cap - 1;
+  for (uint64_t i = 0; i < t->cap; ++i) {
+    if (key_at(t, t->cells, i) == ORC_EMPTY) {
+      e = i;
+      break;
+    }
+  }
+  uint64_t moved = 0;
+  for (uint64_t j = 1; j <= t->cap; ++j) {
+    uint64_t i = (e + j) & (t->cap - 1);
+    uint64_t k = key_at(t, t->cells, i);
+    if (k == ORC_EMPTY || k == ORC_TOMB) continue;
+    uint64_t v = val_at(t, t->cells, i);
+    uint64_t p = home_of(t, k, log2_new);
+    while (key_at(t, nc, p) != ORC_EMPTY) p = (p + 1) & (newcap - 1);
+    set_cell(t, nc, p, k, v);
+    moved++;
+  }
+  free(t->cells);
+  t->cells = nc;
+  t->log2c = log2_new;
+  t->cap = newcap;
+  t->used = moved;
+  t->live = moved;
+  t->migrations++;
+  return 0;
+}
+
+/* x <= alpha * c, with alpha = num/den, in exact integer arithmetic. */
+static int within_fill(const orc_table *t, uint64_t x, uint64_t c) {
+  return (unsigned __int128)x * t->alpha_den <= (unsigned __int128)c * t->alpha_num;
+}
+
+/* Growth rule applied before a batch of b operations that may insert
+ * (bulk insertion by pre-growing, Sec. 5.5; trigger at fill factor alpha,
+ * doubling, Sec. 5.3.2 and Sec. 7; cleanup decided on non-empty cells and on
+ * live elements, Sec. 5.4):
+ *   used + b <= alpha*c            -> nothing;
+ *   live + b <= alpha*c/2          -> migrate with gamma = 1 (drop tombstones);
+ *   otherwise                      -> migrate with gamma = 2, repeated while
+ *                                     live + b > alpha*c. */
+static int grow_before_batch(orc_table *t, uint64_t b) {
+  if (!t->auto_grow || b == 0) return 0;
+  if (within_fill(t, t->used + b, t->cap)) return 0;
+  if ((unsigned __int128)(t->live + b) * 2 * t->alpha_den <= (unsigned __int128)t->cap * t->alpha_num)
+    return orc_migrate(t, t->log2c);
+  do {
+    if (t->log2c >= 40) return -1;
+    int rc = orc_migrate(t, t->log2c + 1);
+    if (rc) return rc;
+  } while (!within_fill(t, t->live + b, t->cap));
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Bulk calls: index order.  Keys and values are u32 for PACKED32 and u64    */
+/* for KV64.  `vals` may be NULL, meaning every operation carries value 1.   */
+/* `flags` may be NULL.                                                       */
+/* ------------------------------------------------------------------------- */
+
+static uint64_t load_word(const orc_table *t, const void *a, uint64_t i) {
+  if (t->layout == ORC_PACKED32) return ((const uint32_t *)a)[i];
+  return ((const uint64_t *)a)[i];
+}
+
+static void store_word(const orc_table *t, void *a, uint64_t i, uint64_t v) {
+  if (t->layout == ORC_PACKED32)
+    ((uint32_t *)a)[i] = (uint32_t)v;
+  else
+    ((uint64_t *)a)[i] = v;
+}
+
+int orc_insert(orc_table *t, const void *keys, const void *vals, uint64_t n, uint8_t *flags) {
+  int rc = grow_before_batch(t, n);
+  if (rc) return rc;
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t v = vals ? load_word(t, vals, i) : 1;
+    uint8_t f = op_insert(t, load_word(t, keys, i), v);
+    if (flags) flags[i] = f;
+  }
+  return 0;
+}
+
+int orc_insert_or_update(orc_table *t, const void *keys, const void *vals, uint64_t n, int op,
+                         uint8_t *flags) {
+  int rc = grow_before_batch(t, n);
+  if (rc) return rc;
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t d = vals ? load_word(t, vals, i) : 1;
+    uint8_t f = op_insert_or_update(t, load_word(t, keys, i), d, op);
+    if (flags) flags[i] = f;
+  }
+  return 0;
+}
+
+int orc_update(orc_table *t, const void *keys, const void *vals, uint64_t n, int op, uint8_t *flags) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t d = vals ? load_word(t, vals, i) : 1;
+    uint8_t f = op_update(t, load_word(t, keys, i), d, op);
+    if (flags) flags[i] = f;
+  }
+  return 0;
+}
+
+int orc_find(orc_table *t, const void *keys, uint64_t n, void *vals_out, uint8_t *found) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t v;
+    uint8_t f = op_find(t, load_word(t, keys, i), &v);
+    if (vals_out) store_word(t, vals_out, i, v);
+    if (found) found[i] = f;
+  }
+  return 0;
+}
+
+int orc_erase(orc_table *t, const void *keys, uint64_t n, uint8_t *flags) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint8_t f = op_erase(t, load_word(t, keys, i));
+    if (flags) flags[i] = f;
+  }
+  return 0;
+}
+
+/* Explicit resize entry (gamma = 2^(log2_new - log2c) >= 1; equal size is
+ * the tombstone cleanup with gamma = 1). */
+int orc_grow(orc_table *t, uint32_t log2_new) {
+  if (log2_new < t->log2c) return -1;
+  return orc_migrate(t, log2_new);
+}
+
+/* Hash of many keys at once (for test comparisons). */
+void orc_hash_bulk(const void *keys, uint64_t n, int key_bytes, uint32_t seed_hi, uint32_t seed_lo,
+                   uint64_t *out) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t k = key_bytes == 4 ? ((const uint32_t *)keys)[i] : ((const uint64_t *)keys)[i];
+    out[i] = orc_hash(k, key_bytes, seed_hi, seed_lo);
+  }
+}

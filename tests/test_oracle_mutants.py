@@ -1,0 +1,91 @@
+"""The oracle's pins must catch plausible mistakes.  Each case plants one
+mistake in a private copy of the oracle's C source (on the CPU), builds it,
+points the oracle binding at it, and requires that at least one of the pin
+checks fails.  The real oracle is restored afterwards."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_hash as TH
+from tests import test_oracle_migration as TM
+from tests import test_oracle_table as TT
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "lpht_oracle.c")
+
+# (name, function the mistake is planted in or None for whole file, old, new)
+MUTANTS = [
+    ("crc32_poly_instead_of_crc32c", None, "0x82F63B78u", "0xEDB88320u"),
+    ("hash_seeds_swapped", "orc_hash", "orc_crc32c_word(seed_hi, key", "orc_crc32c_word(seed_lo, key"),
+    ("position_low_bits", "orc_home", "return h >> (64 - log2c);",
+     "return h & ((1ull << log2c) - 1);"),
+    ("insert_reuses_tombstones", "op_insert", "if (cur == ORC_EMPTY) {",
+     "if (cur == ORC_EMPTY || cur == ORC_TOMB) {"),
+    ("find_stops_at_tombstone", "op_find", "if (cur == ORC_EMPTY) return 0;",
+     "if (cur == ORC_EMPTY || cur == ORC_TOMB) return 0;"),
+    ("erase_keeps_live_count", "op_erase", "t->live--;", ";"),
+    ("upsert_add_assigns", "apply_up", "(op == ORC_ADD) ? cur + d : d", "d"),
+    ("probe_wrap_wrong", "op_insert", "i = (i + 1) & (t->cap - 1);", "i = (i + 1) % (t->cap - 1);"),
+    ("migrate_scan_from_zero", "orc_migrate", "e = i;\n      break;", "break;"),
+    ("migrate_keeps_tombstones", "orc_migrate", "if (k == ORC_EMPTY || k == ORC_TOMB) continue;",
+     "if (k == ORC_EMPTY) continue;"),
+    ("growth_single_doubling", "grow_before_batch", "} while (!within_fill(t, t->live + b, t->cap));",
+     "} while (0);"),
+    ("growth_never_cleans", "grow_before_batch", "return orc_migrate(t, t->log2c);",
+     "return orc_migrate(t, t->log2c + 1);"),
+]
+
+
+def _plant(src, func, old, new):
+    if func is None:
+        assert old in src
+        return src.replace(old, new)
+    start = src.index(func + "(")
+    # the function body: from its name to the next line that is a lone "}"
+    end = src.index("\n}\n", start)
+    body = src[start:end]
+    assert old in body, (func, old)
+    return src[:start] + body.replace(old, new, 1) + src[end:]
+
+
+def _pins():
+    """Quick versions of the pin checks; each raises on a violation."""
+    yield lambda: [TH.test_crc32c_published_vectors(*v) for v in TH._golden_vectors()]
+    yield TH.test_crc32c_matches_sse42_instruction_bytes_and_words
+    yield TH.test_scaling_map_closed_form
+    yield lambda: TH.test_hash_matches_sse42_on_1e6_keys(8)
+    yield lambda: TH.test_hash_matches_sse42_on_1e6_keys(4)
+    for layout in TT.LAYOUTS:
+        yield lambda layout=layout: TT.test_random_sequences_match_dict_model(layout, 4)
+        yield lambda layout=layout: TT.test_brute_force_histogram_of_upserts(layout)
+        yield lambda layout=layout: TM.test_wraparound_cluster_migrates_in_order(layout)
+        yield lambda layout=layout: TM.test_migration_equals_insert_in_scan_order(layout, 1, 0.5, 0.2)
+        yield lambda layout=layout: TM.test_growth_insert_only_final_capacity_closed_form(layout)
+        yield lambda layout=layout: TM.test_tombstone_cleanup_same_size(layout)
+
+
+@pytest.mark.parametrize("name,func,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, name, func, old, new):
+    src = open(SRC).read()
+    bad = _plant(src, func, old, new)
+    assert bad != src
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(bad)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", str(so), str(c)], check=True)
+    saved = oracle._lib
+    oracle._lib = oracle.load(str(so))
+    caught = []
+    try:
+        for pin in _pins():
+            try:
+                with np.errstate(all="ignore"):
+                    pin()
+            except Exception as e:  # noqa: BLE001 - any failure counts as caught
+                caught.append(type(e).__name__)
+                break
+    finally:
+        oracle._lib = saved
+    assert caught, f"planted mistake '{name}' passed every pin"
