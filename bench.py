@@ -1,0 +1,235 @@
+"""Throughput benchmark of the hash table's hot path on one MI355X.
+
+One step = one pass over the presized 16-byte-cell workload at the paper's
+headline size (Sec. 8.4: 10^8 operations): clear a 2^28-cell table, insert
+10^8 distinct uniform u64 keys (value = index), find 10^8 present keys, find
+10^8 absent keys, then clear a second 2^28-cell table and insert-or-increment
+10^8 Zipf(s = 1.0) keys over a universe of 10^8.  The value printed is
+4 * 10^8 operations divided by the step time, in Mops/s.  Inputs are
+generated on the host before timing and are resident in HBM when the timed
+region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_OPS = 10 ** 8
+LOG2C = 28
+ZIPF_S = 1.0
+ZIPF_N = 10 ** 8
+HBM_PEAK_GBS = 8000.0
+LINE = 128
+CELLS_PER_LINE = 8  # 16-byte cells
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def knuth(alpha):
+    ls = 0.5 * (1 + 1 / (1 - alpha))
+    lu = 0.5 * (1 + 1 / (1 - alpha) ** 2)
+    return ls, lu
+
+
+def algorithmic_bytes_per_op(alpha):
+    """Bytes the method must move per operation at fill alpha, counting the
+    random table accesses in 128-byte lines: a probe run of L cells starting
+    at a uniformly random cell touches 1 + (L-1)/8 lines on average."""
+    ls, lu = knuth(alpha)
+    lines_s = 1 + (ls - 1) / CELLS_PER_LINE
+    lines_u = 1 + (lu - 1) / CELLS_PER_LINE
+    return {
+        # key in + value out + flag out
+        "find_hit": lines_s * LINE + 17,
+        "find_miss": lines_u * LINE + 17,
+        # average insertion cost over the fill from 0 to alpha equals the
+        # successful-search cost; the line is read and written back
+        "insert": 2 * lines_s * LINE + 17,
+    }
+
+
+def cpu_baseline(keys, fkeys_hit, fkeys_miss, zipf, budget_s=25.0):
+    """The oracle, single-threaded, on a bounded sample of the same workload:
+    the first n keys of each stream into a 2^25-cell table (same fill as
+    10^8 in 2^28)."""
+    import oracle
+
+    log2c = 25
+    n = int(N_OPS * (1 << log2c) / (1 << LOG2C))
+    t0 = time.perf_counter()
+    o = oracle.OracleTable(oracle.KV64, log2c)
+    o.insert(keys[:n], np.arange(n, dtype=np.uint64))
+    present = keys[:n]
+    o.find(present[np.random.default_rng(0).permutation(n)])
+    o.find(fkeys_miss[:n])
+    o2 = oracle.OracleTable(oracle.KV64, log2c)
+    o2.insert_or_update(zipf[:n], None, oracle.ADD)
+    el = time.perf_counter() - t0
+    return {
+        "value": round(4 * n / el / 1e6, 3),
+        "unit": "Mops/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n} inserts + {n} hit finds + {n} miss finds + {n} Zipf(1.0) increments, "
+                  f"2^{log2c}-cell tables (same fill as the 2^{LOG2C} workload), {el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--group-width", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (tables shard by hash "
+              "prefix in the design only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1601_04017_amd import inputs, lpht
+
+    lpht.load()
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log("generating inputs")
+    keys = inputs.distinct_keys_u64(N_OPS, 201)
+    miss = inputs.distinct_keys_u64(N_OPS, 201, absent=True)
+    perm = inputs.permutation(N_OPS, 203)
+    hit = keys[perm]
+    zipf = inputs.zipf_keys_u64(N_OPS, ZIPF_N, ZIPF_S, seed=402)
+    log("uploading")
+
+    def up(a):
+        return torch.from_numpy(a.view(np.int64)).to(dev)
+
+    d_keys, d_vals = up(keys), torch.arange(N_OPS, dtype=torch.int64, device=dev)
+    d_hit, d_miss, d_zipf = up(hit), up(miss), up(zipf)
+    d_out = torch.empty(N_OPS, dtype=torch.int64, device=dev)
+    d_flags = torch.empty(N_OPS, dtype=torch.uint8, device=dev)
+    d_found = torch.empty(N_OPS, dtype=torch.uint8, device=dev)
+
+    t1 = lpht.Table(layout=lpht.KV64, log2_capacity=LOG2C)
+    t2 = lpht.Table(layout=lpht.KV64, log2_capacity=LOG2C)
+    if args.group_width:
+        t1.set_tuning(group_width=args.group_width)
+        t2.set_tuning(group_width=args.group_width)
+    stream = torch.cuda.current_stream()
+    phases = ["clear1", "insert", "find_hit", "find_miss", "clear2", "upsert_zipf"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record(stream)
+        mark(0)
+        t1.clear()
+        mark(1)
+        t1.insert(d_keys, d_vals, flags=False)
+        mark(2)
+        t1.find(d_hit, d_out, d_found)
+        mark(3)
+        t1.find(d_miss, d_out, d_found)
+        mark(4)
+        t2.clear()
+        mark(5)
+        t2.insert_or_update(d_zipf, None, op=lpht.ADD, flags=False)
+        mark(6)
+
+    log(f"warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # correctness spot check of the last warmup pass (full arrays, on device)
+    hv, hf = t1.find(d_hit[:1 << 20])
+    assert bool((hf == 1).all()), "present keys not found"
+    assert bool((hv == torch.from_numpy(perm[:1 << 20].astype(np.int64)).to(dev)).all()), "values"
+    mv, mf = t1.find(d_miss[:1 << 20])
+    assert not bool(mf.any()), "absent keys found"
+    del perm
+    used, live = t1.count()
+    assert used == live == N_OPS, (used, live)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    log(f"timed x{args.steps}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1000 / args.steps
+    ph_ms = {p: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
+             for i, p in enumerate(phases)}
+    ops_per_step = 4 * N_OPS
+    value = ops_per_step / (wall / args.steps) / 1e6
+
+    alpha = N_OPS / (1 << LOG2C)
+    bpo = algorithmic_bytes_per_op(alpha)
+    ach = {
+        "insert": bpo["insert"] * N_OPS / (ph_ms["insert"] / 1e3) / 1e9,
+        "find_hit": bpo["find_hit"] * N_OPS / (ph_ms["find_hit"] / 1e3) / 1e9,
+        "find_miss": bpo["find_miss"] * N_OPS / (ph_ms["find_miss"] / 1e3) / 1e9,
+    }
+    dominant = max(("insert", "find_hit", "find_miss"), key=lambda p: ph_ms[p])
+    roofline = {
+        "bound": "hbm",
+        "kernel": f"k_bulk<KV64,{dominant}>",
+        "achieved": round(ach[dominant], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(ach[dominant] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+    }
+
+    out = {
+        "metric": "Mops/s insert/find/Zipf-increment at 1e8 ops; % HBM roofline; batch p99",
+        "value": round(value, 2),
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "presized 2^28 KV64 table: 1e8 uniform inserts, 1e8 hit finds, "
+                        "1e8 miss finds; 2^28 table: 1e8 Zipf(1.0) insert-or-increment",
+            "capacity": 1 << LOG2C,
+            "ops": N_OPS,
+            "fill": round(alpha, 4),
+            "zipf_s": ZIPF_S,
+            "group_width": t1.get_tuning()["group_width"],
+        },
+        "phases_ms": {k: round(v, 3) for k, v in ph_ms.items()},
+        "phase_mops": {p: round(N_OPS / (ph_ms[p] / 1e3) / 1e6, 1)
+                       for p in ("insert", "find_hit", "find_miss", "upsert_zipf")},
+        "phase_gbs_algorithmic": {k: round(v, 1) for k, v in ach.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, 1 thread)")
+        out["cpu_baseline"] = cpu_baseline(keys, hit, miss, zipf)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

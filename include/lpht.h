@@ -1,0 +1,221 @@
+/*
+ * lpht: lock-free linear-probing hash tables on AMD MI355X (gfx950).
+ *
+ * C ABI of the device library liblpht.so.  Every operation of the table runs
+ * in hand-written HIP kernels; this header exposes plain pointers and sizes
+ * only.  The method is the bounded "folklore" table of Maier, Sanders and
+ * Dementiev, "Concurrent Hash Tables: Fast and General(?)!" (arXiv 1601.04017),
+ * Sec. 4 and Algorithm 1, with tombstone deletion (Sec. 5.4), growth by
+ * block-parallel cluster migration into a table of double size (Sec. 5.3.1,
+ * Lemma 1), bulk insertion by pre-growing (Sec. 5.5) and the paper's hash
+ * function (two CRC-32C with different seeds, Sec. 8.3).
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * - Return value: LPHT_OK (0) or a negative LPHT_ERR_* code.  No call throws
+ *   or aborts across this boundary.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Calls are stream-ordered: a call returns once its work is enqueued; device
+ *   arrays passed in must stay valid until the stream has passed that work.
+ *   A table must be used from one stream at a time.  Within one call the
+ *   operations run concurrently; a call behaves as if its operations were
+ *   applied one by one in some order (linearizability, Sec. 4).
+ * - Keys and values: u32 for LPHT_PACKED32, u64 for LPHT_KV64.  Key 0 is
+ *   empty_key and key 1 is del_key (the tombstone); both are reserved
+ *   (Sec. 5.6).  An operation on a reserved key changes nothing, gets flag
+ *   LPHT_FLAG_RESERVED and sets the sticky error LPHT_ERR_RESERVED_KEY.
+ * - Device arrays (`keys`, `vals`, `flags`, `vals_out`, `found`) are owned by
+ *   the caller and live in device memory of the table's GPU.  Key and value
+ *   arrays must be aligned to their element size.  `flags`/`found` hold one
+ *   byte per operation and may be NULL (not written).
+ * - Per-operation flags: 1 = true, 0 = false, LPHT_FLAG_RESERVED (0xFE) for a
+ *   reserved key, LPHT_FLAG_FULL (0xFF) when a bounded table had no empty cell
+ *   left for an inserting operation (sticky error LPHT_ERR_FULL).
+ * - The table's cells and its status block are owned by the library and
+ *   allocated through the configured allocator (default: stream-ordered
+ *   hipMallocAsync / hipFreeAsync on the call's stream).
+ */
+#ifndef LPHT_H
+#define LPHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define LPHT_OK 0
+#define LPHT_ERR_INVALID (-1)      /* bad argument (NULL table, misaligned pointer, range) */
+#define LPHT_ERR_OOM (-2)          /* allocation failed */
+#define LPHT_ERR_FULL (-3)         /* sticky: an insertion found no empty cell */
+#define LPHT_ERR_RESERVED_KEY (-4) /* sticky: an operation used key 0 or 1 */
+#define LPHT_ERR_DEVICE (-5)       /* a HIP runtime call failed */
+#define LPHT_ERR_UNSUPPORTED (-6)  /* valid request the library does not implement */
+
+/* ---- per-operation flag bytes ---- */
+#define LPHT_FLAG_FALSE 0
+#define LPHT_FLAG_TRUE 1
+#define LPHT_FLAG_RESERVED 0xFE
+#define LPHT_FLAG_FULL 0xFF
+
+/* ---- cell layouts ----
+ * LPHT_PACKED32: one 8-byte word per cell, key in bits 0..31, value in bits
+ *   32..63; the whole cell is claimed by one 64-bit CAS, so key and value are
+ *   published together as with the paper's 2-word CAS (Sec. 4).
+ * LPHT_KV64: 16-byte cell {u64 key at byte 0, u64 value at byte 8}, 16-byte
+ *   aligned.  gfx950 has no 128-bit CAS: the key is claimed with a 64-bit CAS
+ *   and the value is then written by a separate store (the paper's fallback
+ *   "variant which does not use 2-word CAS", Sec. 4).  Therefore finds must
+ *   not run concurrently with modifications of the same table, which the
+ *   per-table stream order guarantees. */
+#define LPHT_PACKED32 0u
+#define LPHT_KV64 1u
+
+/* ---- update functions `up` of Algorithm 1 ----
+ * LPHT_ASSIGN: value := d (overwrite by a single store, Sec. 4).
+ * LPHT_ADD:    value := value + d modulo 2^32 (PACKED32) or 2^64 (KV64),
+ *              by fetch-and-add (Sec. 4). */
+#define LPHT_ASSIGN 0u
+#define LPHT_ADD 1u
+
+/* Allocator hook: returns device memory of `bytes` bytes (256-byte aligned)
+ * usable in stream order on `stream`, or NULL.  `free` releases it in stream
+ * order.  Both NULL selects hipMallocAsync / hipFreeAsync. */
+typedef void *(*lpht_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*lpht_free_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+
+typedef struct lpht_config {
+  uint32_t layout;        /* LPHT_PACKED32 or LPHT_KV64 */
+  uint32_t log2_capacity; /* capacity c = 2^log2_capacity cells, 6..34 (Sec. 7: powers of two) */
+  uint32_t seed_hi;       /* CRC-32C seed of the upper 32 hash bits (Sec. 8.3) */
+  uint32_t seed_lo;       /* CRC-32C seed of the lower 32 hash bits */
+  uint32_t max_fill_num;  /* growth trigger alpha = num/den, 0 < alpha <= 1 (Sec. 5.3.2) */
+  uint32_t max_fill_den;
+  uint32_t auto_grow;     /* 0: bounded folklore table; 1: grow before batches (Sec. 5.5) */
+  uint32_t reserved0;     /* must be 0 */
+  lpht_alloc_fn alloc;
+  lpht_free_fn free;
+  void *alloc_ctx;
+} lpht_config;
+
+/* Launch parameters of the kernels; see lpht_set_tuning. */
+typedef struct lpht_tuning {
+  uint32_t block_threads; /* workgroup size, a multiple of 64 in 64..1024 */
+  uint32_t group_width;   /* lanes that probe one operation together: 1, 2, 4, 8 or 16 */
+  uint32_t blocks_per_cu; /* resident workgroups per compute unit the grid is sized for, 1..32 */
+  uint32_t migrate_block; /* old cells per migration workgroup, power of two 256..8192 */
+  uint32_t aggregate;     /* 1: combine equal keys inside a workgroup before LPHT_ADD upserts */
+  uint32_t reserved[3];
+} lpht_tuning;
+
+typedef struct lpht_stats {
+  uint64_t migrations;     /* migrations that moved data (empty-table resizes excluded) */
+  uint64_t resizes;        /* all capacity changes and gamma = 1 cleanups */
+  uint64_t cells_migrated; /* sum of old capacities over data migrations */
+  uint64_t host_syncs;     /* count synchronisations the growth rule needed */
+  double migrate_ms;       /* device time of data migrations (when timing is on) */
+} lpht_stats;
+
+typedef struct lpht_table lpht_table; /* opaque; owned by the library */
+
+/* Fills `cfg` with: KV64, log2_capacity 12, seeds 0x9E3779B9 / 0xFFFFFFFF,
+ * alpha = 1/2, auto_grow 0, default allocator. */
+void lpht_config_default(lpht_config *cfg);
+
+/* Creates an empty table on the current HIP device: every cell is set to
+ * empty_key with value 0 (Sec. 4, "Initialization").  Errors: INVALID, OOM,
+ * DEVICE.  On error *out is NULL. */
+int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out);
+
+/* Empties the table in place: every cell becomes empty_key with value 0,
+ * counts and sticky errors are reset, the capacity stays. */
+int lpht_clear(lpht_table *t, void *stream);
+
+/* Releases the table's memory in stream order on `stream` and frees the
+ * handle.  NULL is accepted. */
+int lpht_destroy(lpht_table *t, void *stream);
+
+/* insert(k, d) (Sec. 4): flag true iff k was absent and is now stored with
+ * value d; if several operations of the call carry the same absent key exactly
+ * one of them succeeds and the stored value is the value of that operation.
+ * `vals` NULL means every value is 1.  With auto_grow the table first grows so
+ * that used + n <= alpha * c (bulk pre-growth, Sec. 5.5). */
+int lpht_insert(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint8_t *flags,
+                void *stream);
+
+/* find(k) (Sec. 4): found[i] = 1 and vals_out[i] = stored value, or found[i]
+ * = 0 and vals_out[i] = 0.  Never writes the table.  `vals_out` may be NULL. */
+int lpht_find(lpht_table *t, const void *keys, uint64_t n, void *vals_out, uint8_t *found,
+              void *stream);
+
+/* insertOrUpdate(k, d, up) (Algorithm 1): inserts (k, d) if k is absent
+ * (flag true), else value := up(value, d) (flag false).  With LPHT_ADD the
+ * result is exact whatever the order; with LPHT_ASSIGN and repeated keys in
+ * one call the final value is the `d` of one of that key's operations.
+ * `vals` NULL means d = 1 (insert-or-increment).  Grows like lpht_insert. */
+int lpht_insert_or_update(lpht_table *t, const void *keys, const void *vals, uint64_t n,
+                          uint32_t op, uint8_t *inserted, void *stream);
+
+/* update(k, d, up) (Sec. 4): flag false if k is absent, else value :=
+ * up(value, d) and flag true.  Never inserts, never grows. */
+int lpht_update(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op,
+                uint8_t *flags, void *stream);
+
+/* Deletion by tombstone (Sec. 4 and 5.4): a live key k becomes del_key (its
+ * value stays, the cell is never reused); flag true iff this operation did
+ * it.  Tombstones are removed only by migration. */
+int lpht_erase(lpht_table *t, const void *keys, uint64_t n, uint8_t *flags, void *stream);
+
+/* Migrates the table into a new table of 2^log2_new_capacity cells
+ * (gamma = 2^(log2_new - log2_old) >= 1; equal sizes drop tombstones,
+ * Sec. 5.4) by block-parallel cluster migration (Sec. 5.3.1).  The placement
+ * equals the sequential migration's exactly (Lemma 1).  Errors: INVALID
+ * (shrinking), OOM. */
+int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream);
+
+/* Exact counts: `used` non-empty cells (live keys and tombstones), `live`
+ * keys.  Synchronises `stream`.  Either pointer may be NULL. */
+int lpht_count(lpht_table *t, uint64_t *used, uint64_t *live, void *stream);
+
+/* Current capacity in cells and its log2 (host-side, no synchronisation). */
+int lpht_capacity(const lpht_table *t, uint64_t *cells, uint32_t *log2_capacity);
+
+/* Bytes of one cell: 8 (PACKED32) or 16 (KV64). */
+uint32_t lpht_cell_bytes(uint32_t layout);
+
+/* Copies the raw cell array (capacity * cell bytes) to device memory `dst`. */
+int lpht_export_cells(lpht_table *t, void *dst_device, void *stream);
+
+/* Replaces the table's cells by a copy of `src_device` holding
+ * 2^log2_capacity cells of the table's layout, and recounts used/live on the
+ * device.  Used to hand the migration a given array in tests. */
+int lpht_import_cells(lpht_table *t, const void *src_device, uint32_t log2_capacity, void *stream);
+
+/* Returns the sticky device error (LPHT_ERR_FULL before
+ * LPHT_ERR_RESERVED_KEY, else LPHT_OK) and clears it.  Synchronises `stream`. */
+int lpht_status(lpht_table *t, void *stream);
+
+/* Kernel launch parameters for this table.  Values are checked; INVALID
+ * leaves the previous tuning in place.  `lpht_get_tuning` reads them back. */
+int lpht_set_tuning(lpht_table *t, const lpht_tuning *tuning);
+int lpht_get_tuning(const lpht_table *t, lpht_tuning *tuning);
+
+/* Migration statistics.  With `timing` = 1 every data migration is bracketed
+ * by HIP events on its stream and migrate_ms accumulates their elapsed time
+ * (read at the next lpht_get_stats, which then synchronises). */
+int lpht_set_timing(lpht_table *t, int timing);
+int lpht_get_stats(lpht_table *t, lpht_stats *stats);
+
+/* Static description of an error code. */
+const char *lpht_strerror(int code);
+
+/* Library version string. */
+const char *lpht_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPHT_H */

@@ -1,0 +1,530 @@
+// Host side of liblpht: table objects, the growth rule, allocation and the C
+// ABI declared in include/lpht.h.  Every table operation is executed by the
+// HIP kernels of lpht_kernels.hip; this file only validates arguments, sizes
+// launches and decides when to migrate.
+
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/lpht.h"
+#include "lpht_internal.h"
+
+using namespace lpht;
+
+namespace {
+
+// CRC-32C register update (reflected Castagnoli polynomial, no inversion)
+// from register 0 over the `nbytes` little-endian bytes of `x`, bit by bit.
+// Used once per table for the two hash constants CRC(0, seed).
+uint32_t crc0_bytes(uint64_t x, int nbytes) {
+  uint32_t r = 0;
+  for (int i = 0; i < nbytes; ++i) {
+    r ^= (uint32_t)((x >> (8 * i)) & 0xFFu);
+    for (int b = 0; b < 8; ++b) r = (r >> 1) ^ (0x82F63B78u & (0u - (r & 1u)));
+  }
+  return r;
+}
+
+struct Timing {
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct lpht_table {
+  lpht_config cfg;
+  int device;
+  uint32_t log2c;
+  void *cells;
+  DevStatus *status;
+  uint32_t crc_hi, crc_lo;
+  // host view of the counts for the growth rule: exact at the last
+  // synchronisation, plus an upper bound of insertions since then
+  uint64_t known_used, known_live, pending;
+  lpht_tuning tuning;
+  LaunchCfg launch;
+  lpht_stats stats;
+  int timing;
+  std::vector<Timing> timed;
+};
+
+namespace {
+
+int from_hip(hipError_t e) {
+  if (e == hipSuccess) return LPHT_OK;
+  if (e == hipErrorOutOfMemory) return LPHT_ERR_OOM;
+  if (e == hipErrorInvalidValue) return LPHT_ERR_INVALID;
+  return LPHT_ERR_DEVICE;
+}
+
+uint64_t cell_bytes(uint32_t layout) { return layout == LPHT_PACKED32 ? 8u : 16u; }
+
+void *dev_alloc(lpht_table *t, size_t bytes, hipStream_t s) {
+  if (t->cfg.alloc) return t->cfg.alloc(bytes, (void *)s, t->cfg.alloc_ctx);
+  void *p = nullptr;
+  if (hipMallocAsync(&p, bytes, s) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(lpht_table *t, void *p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  if (t->cfg.free) {
+    t->cfg.free(p, bytes, (void *)s, t->cfg.alloc_ctx);
+    return;
+  }
+  (void)hipFreeAsync(p, s);
+}
+
+void fill_launch(lpht_table *t) {
+  t->launch.block_threads = t->tuning.block_threads;
+  t->launch.group_width = t->tuning.group_width;
+  t->launch.blocks_per_cu = t->tuning.blocks_per_cu;
+  t->launch.migrate_block = t->tuning.migrate_block;
+  t->launch.aggregate = t->tuning.aggregate;
+}
+
+bool tuning_ok(const lpht_tuning *u) {
+  if (u->block_threads < 64 || u->block_threads > 1024 || (u->block_threads % 64)) return false;
+  switch (u->group_width) {
+    case 1: case 2: case 4: case 8: case 16: break;
+    default: return false;
+  }
+  if (u->blocks_per_cu < 1 || u->blocks_per_cu > 32) return false;
+  if (u->migrate_block < 256 || u->migrate_block > 8192 ||
+      (u->migrate_block & (u->migrate_block - 1)))
+    return false;
+  if (u->aggregate > 1) return false;
+  return true;
+}
+
+bool within_fill(const lpht_table *t, uint64_t x, uint64_t c) {
+  return (unsigned __int128)x * t->cfg.max_fill_den <= (unsigned __int128)c * t->cfg.max_fill_num;
+}
+
+int sync_counts(lpht_table *t, hipStream_t s) {
+  DevStatus h;
+  hipError_t e = hipMemcpyAsync(&h, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return from_hip(e);
+  t->known_used = h.used;
+  t->known_live = h.live;
+  t->pending = 0;
+  return LPHT_OK;
+}
+
+// Replaces the cells by an all-empty table of 2^log2_new cells; `steps` is
+// the number of migrations of the growth rule this resize stands for.
+int resize_empty(lpht_table *t, uint32_t log2_new, hipStream_t s, uint32_t steps = 1) {
+  const size_t nb = (size_t)cell_bytes(t->cfg.layout) << log2_new;
+  void *nc = dev_alloc(t, nb, s);
+  if (!nc) return LPHT_ERR_OOM;
+  hipError_t e = launch_fill_zero(nc, nb, t->launch, s);
+  if (e == hipSuccess) e = launch_set_status(t->status, 0, 0, 0, s);
+  if (e != hipSuccess) {
+    dev_free(t, nc, nb, s);
+    return from_hip(e);
+  }
+  dev_free(t, t->cells, (size_t)cell_bytes(t->cfg.layout) << t->log2c, s);
+  t->cells = nc;
+  t->log2c = log2_new;
+  t->known_used = t->known_live = 0;
+  t->pending = 0;
+  t->stats.resizes += steps;
+  return LPHT_OK;
+}
+
+// One migration into 2^log2_new cells (>= current).  The host must know the
+// exact live count (`known_live`); afterwards used = live = that count.
+int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
+  if (t->known_live == 0) return resize_empty(t, log2_new, s);
+  const size_t ob = (size_t)cell_bytes(t->cfg.layout) << t->log2c;
+  const size_t nb = (size_t)cell_bytes(t->cfg.layout) << log2_new;
+  void *nc = dev_alloc(t, nb, s);
+  if (!nc) return LPHT_ERR_OOM;
+  Timing tm{};
+  if (t->timing) {
+    if (hipEventCreate(&tm.start) != hipSuccess || hipEventCreate(&tm.stop) != hipSuccess)
+      return LPHT_ERR_DEVICE;
+    (void)hipEventRecord(tm.start, s);
+  }
+  const int old_full = (t->known_used == (1ull << t->log2c)) ? 1 : 0;
+  hipError_t e = launch_set_status(t->status, 0, 0, 0, s);
+  if (e == hipSuccess)
+    e = launch_migrate(t->cells, t->log2c, nc, log2_new, t->cfg.layout, t->crc_hi, t->crc_lo,
+                       old_full, t->status, t->launch, s);
+  if (e != hipSuccess) {
+    dev_free(t, nc, nb, s);
+    return from_hip(e);
+  }
+  if (t->timing) {
+    (void)hipEventRecord(tm.stop, s);
+    t->timed.push_back(tm);
+  }
+  dev_free(t, t->cells, ob, s);
+  t->stats.migrations++;
+  t->stats.resizes++;
+  t->stats.cells_migrated += 1ull << t->log2c;
+  t->cells = nc;
+  t->log2c = log2_new;
+  t->known_used = t->known_live;
+  t->pending = 0;
+  return LPHT_OK;
+}
+
+// The growth rule before a batch of b operations that may insert (bulk
+// insertion by pre-growing, Sec. 5.5; trigger at fill factor alpha and
+// doubling, Sec. 5.3.2 and Sec. 7; cleanup decided on non-empty cells and
+// live elements, Sec. 5.4):
+//   used + b <= alpha*c     -> nothing
+//   live + b <= alpha*c/2   -> migrate with gamma = 1 (drops tombstones)
+//   otherwise               -> migrate with gamma = 2, repeated while
+//                              live + b > alpha*c.
+// Decisions use exact counts.  The host keeps an upper bound of `used` and
+// reads the device counters only when the bound does not already rule a
+// migration out.
+int grow_before_batch(lpht_table *t, uint64_t b, hipStream_t s) {
+  if (!t->cfg.auto_grow || b == 0) return LPHT_OK;
+  const uint64_t c = 1ull << t->log2c;
+  if (within_fill(t, t->known_used + t->pending + b, c)) {
+    t->pending += b;
+    return LPHT_OK;
+  }
+  int rc = sync_counts(t, s);
+  if (rc) return rc;
+  t->stats.host_syncs++;
+  if (within_fill(t, t->known_used + b, c)) {
+    t->pending = b;
+    return LPHT_OK;
+  }
+  if ((unsigned __int128)(t->known_live + b) * 2 * t->cfg.max_fill_den <=
+      (unsigned __int128)c * t->cfg.max_fill_num) {
+    rc = migrate_once(t, t->log2c, s);
+  } else {
+    uint32_t target = t->log2c;
+    do {
+      if (target >= 34) return LPHT_ERR_OOM;
+      ++target;
+    } while (!within_fill(t, t->known_live + b, 1ull << target));
+    if (t->known_live == 0) {
+      // migrations of an empty table are resizes; jump to the final size
+      rc = resize_empty(t, target, s, target - t->log2c);
+    } else {
+      while (!rc && t->log2c < target) rc = migrate_once(t, t->log2c + 1, s);
+    }
+  }
+  if (rc) return rc;
+  t->pending = b;
+  return LPHT_OK;
+}
+
+BulkArgs make_args(lpht_table *t) {
+  BulkArgs a{};
+  a.cells = t->cells;
+  a.log2c = t->log2c;
+  a.layout = t->cfg.layout;
+  a.crc_hi = t->crc_hi;
+  a.crc_lo = t->crc_lo;
+  a.status = t->status;
+  return a;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int check_arrays(lpht_table *t, const void *keys, const void *vals, uint64_t n) {
+  if (!t) return LPHT_ERR_INVALID;
+  if (n && !keys) return LPHT_ERR_INVALID;
+  const size_t w = t->cfg.layout == LPHT_PACKED32 ? 4 : 8;
+  if (!aligned(keys, w) || !aligned(vals, w)) return LPHT_ERR_INVALID;
+  return LPHT_OK;
+}
+
+int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint64_t n, uint32_t up,
+             void *vals_out, uint8_t *flags, void *stream) {
+  int rc = check_arrays(t, keys, vals, n);
+  if (rc) return rc;
+  if (up > LPHT_ADD) return LPHT_ERR_INVALID;
+  if (vals_out && !aligned(vals_out, t->cfg.layout == LPHT_PACKED32 ? 4 : 8))
+    return LPHT_ERR_INVALID;
+  if (n == 0) return LPHT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  if (op == OP_INSERT || op == OP_UPSERT) {
+    rc = grow_before_batch(t, n, s);
+    if (rc) return rc;
+  }
+  BulkArgs a = make_args(t);
+  a.keys = keys;
+  a.vals = vals;
+  a.n = n;
+  a.vals_out = vals_out;
+  a.flags = flags;
+  a.up = up;
+  return from_hip(launch_bulk(op, a, t->launch, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+void lpht_config_default(lpht_config *cfg) {
+  if (!cfg) return;
+  *cfg = lpht_config{};
+  cfg->layout = LPHT_KV64;
+  cfg->log2_capacity = 12;
+  cfg->seed_hi = 0x9E3779B9u;
+  cfg->seed_lo = 0xFFFFFFFFu;
+  cfg->max_fill_num = 1;
+  cfg->max_fill_den = 2;
+  cfg->auto_grow = 0;
+}
+
+int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out) {
+  if (!out) return LPHT_ERR_INVALID;
+  *out = nullptr;
+  if (!cfg) return LPHT_ERR_INVALID;
+  if (cfg->layout != LPHT_PACKED32 && cfg->layout != LPHT_KV64) return LPHT_ERR_INVALID;
+  if (cfg->log2_capacity < 6 || cfg->log2_capacity > 34) return LPHT_ERR_INVALID;
+  if (cfg->max_fill_num == 0 || cfg->max_fill_den == 0 || cfg->max_fill_num > cfg->max_fill_den)
+    return LPHT_ERR_INVALID;
+  if (cfg->reserved0 != 0) return LPHT_ERR_INVALID;
+  if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return LPHT_ERR_INVALID;
+  lpht_table *t = new (std::nothrow) lpht_table();
+  if (!t) return LPHT_ERR_OOM;
+  t->cfg = *cfg;
+  if (hipGetDevice(&t->device) != hipSuccess) {
+    delete t;
+    return LPHT_ERR_DEVICE;
+  }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, t->device) != hipSuccess ||
+      ncu <= 0) {
+    delete t;
+    return LPHT_ERR_DEVICE;
+  }
+  t->launch.num_cus = (uint32_t)ncu;
+  t->tuning.block_threads = 256;
+  t->tuning.group_width = 1;
+  t->tuning.blocks_per_cu = 8;
+  t->tuning.migrate_block = 4096;
+  t->tuning.aggregate = 0;
+  fill_launch(t);
+  const int kb = cfg->layout == LPHT_PACKED32 ? 4 : 8;
+  t->crc_hi = crc0_bytes(cfg->seed_hi, kb);
+  t->crc_lo = crc0_bytes(cfg->seed_lo, kb);
+  hipStream_t s = (hipStream_t)stream;
+  t->status = (DevStatus *)dev_alloc(t, sizeof(DevStatus), s);
+  if (!t->status) {
+    delete t;
+    return LPHT_ERR_OOM;
+  }
+  hipError_t e = launch_set_status(t->status, 0, 0, 1, s);
+  if (e != hipSuccess) {
+    dev_free(t, t->status, sizeof(DevStatus), s);
+    delete t;
+    return from_hip(e);
+  }
+  const size_t nb = (size_t)cell_bytes(cfg->layout) << cfg->log2_capacity;
+  t->cells = dev_alloc(t, nb, s);
+  if (!t->cells) {
+    dev_free(t, t->status, sizeof(DevStatus), s);
+    delete t;
+    return LPHT_ERR_OOM;
+  }
+  t->log2c = cfg->log2_capacity;
+  e = launch_fill_zero(t->cells, nb, t->launch, s);
+  if (e != hipSuccess) {
+    dev_free(t, t->cells, nb, s);
+    dev_free(t, t->status, sizeof(DevStatus), s);
+    delete t;
+    return from_hip(e);
+  }
+  *out = t;
+  return LPHT_OK;
+}
+
+int lpht_clear(lpht_table *t, void *stream) {
+  if (!t) return LPHT_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  hipError_t e = launch_fill_zero(t->cells, (size_t)cell_bytes(t->cfg.layout) << t->log2c, t->launch, s);
+  if (e == hipSuccess) e = launch_set_status(t->status, 0, 0, 1, s);
+  if (e != hipSuccess) return from_hip(e);
+  t->known_used = t->known_live = 0;
+  t->pending = 0;
+  return LPHT_OK;
+}
+
+int lpht_destroy(lpht_table *t, void *stream) {
+  if (!t) return LPHT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  (void)hipSetDevice(t->device);
+  dev_free(t, t->cells, (size_t)cell_bytes(t->cfg.layout) << t->log2c, s);
+  dev_free(t, t->status, sizeof(DevStatus), s);
+  for (auto &tm : t->timed) {
+    (void)hipEventDestroy(tm.start);
+    (void)hipEventDestroy(tm.stop);
+  }
+  delete t;
+  return LPHT_OK;
+}
+
+int lpht_insert(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint8_t *flags,
+                void *stream) {
+  return run_bulk(t, OP_INSERT, keys, vals, n, 0, nullptr, flags, stream);
+}
+
+int lpht_find(lpht_table *t, const void *keys, uint64_t n, void *vals_out, uint8_t *found,
+              void *stream) {
+  return run_bulk(t, OP_FIND, keys, nullptr, n, 0, vals_out, found, stream);
+}
+
+int lpht_insert_or_update(lpht_table *t, const void *keys, const void *vals, uint64_t n,
+                          uint32_t op, uint8_t *inserted, void *stream) {
+  return run_bulk(t, OP_UPSERT, keys, vals, n, op, nullptr, inserted, stream);
+}
+
+int lpht_update(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op,
+                uint8_t *flags, void *stream) {
+  return run_bulk(t, OP_UPDATE, keys, vals, n, op, nullptr, flags, stream);
+}
+
+int lpht_erase(lpht_table *t, const void *keys, uint64_t n, uint8_t *flags, void *stream) {
+  return run_bulk(t, OP_ERASE, keys, nullptr, n, 0, nullptr, flags, stream);
+}
+
+int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream) {
+  if (!t) return LPHT_ERR_INVALID;
+  if (log2_new_capacity < t->log2c || log2_new_capacity > 34) return LPHT_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  int rc = sync_counts(t, s);
+  if (rc) return rc;
+  return migrate_once(t, log2_new_capacity, s);
+}
+
+int lpht_count(lpht_table *t, uint64_t *used, uint64_t *live, void *stream) {
+  if (!t) return LPHT_ERR_INVALID;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  int rc = sync_counts(t, (hipStream_t)stream);
+  if (rc) return rc;
+  if (used) *used = t->known_used;
+  if (live) *live = t->known_live;
+  return LPHT_OK;
+}
+
+int lpht_capacity(const lpht_table *t, uint64_t *cells, uint32_t *log2_capacity) {
+  if (!t) return LPHT_ERR_INVALID;
+  if (cells) *cells = 1ull << t->log2c;
+  if (log2_capacity) *log2_capacity = t->log2c;
+  return LPHT_OK;
+}
+
+uint32_t lpht_cell_bytes(uint32_t layout) { return (uint32_t)cell_bytes(layout); }
+
+int lpht_export_cells(lpht_table *t, void *dst_device, void *stream) {
+  if (!t || !dst_device) return LPHT_ERR_INVALID;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  const size_t nb = (size_t)cell_bytes(t->cfg.layout) << t->log2c;
+  return from_hip(hipMemcpyAsync(dst_device, t->cells, nb, hipMemcpyDeviceToDevice,
+                                 (hipStream_t)stream));
+}
+
+int lpht_import_cells(lpht_table *t, const void *src_device, uint32_t log2_capacity, void *stream) {
+  if (!t || !src_device) return LPHT_ERR_INVALID;
+  if (log2_capacity < 6 || log2_capacity > 34) return LPHT_ERR_INVALID;
+  if (!aligned(src_device, 16)) return LPHT_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  const size_t nb = (size_t)cell_bytes(t->cfg.layout) << log2_capacity;
+  void *nc = t->cells;
+  if (log2_capacity != t->log2c) {
+    nc = dev_alloc(t, nb, s);
+    if (!nc) return LPHT_ERR_OOM;
+  }
+  hipError_t e = hipMemcpyAsync(nc, src_device, nb, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) {
+    if (nc != t->cells) dev_free(t, nc, nb, s);
+    return from_hip(e);
+  }
+  if (nc != t->cells) {
+    dev_free(t, t->cells, (size_t)cell_bytes(t->cfg.layout) << t->log2c, s);
+    t->cells = nc;
+    t->log2c = log2_capacity;
+  }
+  e = launch_set_status(t->status, 0, 0, 0, s);
+  if (e == hipSuccess) e = launch_recount(t->cells, t->log2c, t->cfg.layout, t->status, t->launch, s);
+  if (e != hipSuccess) return from_hip(e);
+  return sync_counts(t, s);
+}
+
+int lpht_status(lpht_table *t, void *stream) {
+  if (!t) return LPHT_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  DevStatus h;
+  hipError_t e = hipMemcpyAsync(&h, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return from_hip(e);
+  t->known_used = h.used;
+  t->known_live = h.live;
+  t->pending = 0;
+  if (h.err) {
+    e = launch_set_status(t->status, h.used, h.live, 1, s);
+    if (e != hipSuccess) return from_hip(e);
+  }
+  if (h.err & kErrFull) return LPHT_ERR_FULL;
+  if (h.err & kErrReserved) return LPHT_ERR_RESERVED_KEY;
+  return LPHT_OK;
+}
+
+int lpht_set_tuning(lpht_table *t, const lpht_tuning *tuning) {
+  if (!t || !tuning || !tuning_ok(tuning)) return LPHT_ERR_INVALID;
+  t->tuning = *tuning;
+  fill_launch(t);
+  return LPHT_OK;
+}
+
+int lpht_get_tuning(const lpht_table *t, lpht_tuning *tuning) {
+  if (!t || !tuning) return LPHT_ERR_INVALID;
+  *tuning = t->tuning;
+  return LPHT_OK;
+}
+
+int lpht_set_timing(lpht_table *t, int timing) {
+  if (!t) return LPHT_ERR_INVALID;
+  t->timing = timing ? 1 : 0;
+  return LPHT_OK;
+}
+
+int lpht_get_stats(lpht_table *t, lpht_stats *stats) {
+  if (!t || !stats) return LPHT_ERR_INVALID;
+  for (auto &tm : t->timed) {
+    if (hipEventSynchronize(tm.stop) != hipSuccess) return LPHT_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, tm.start, tm.stop) == hipSuccess) t->stats.migrate_ms += ms;
+    (void)hipEventDestroy(tm.start);
+    (void)hipEventDestroy(tm.stop);
+  }
+  t->timed.clear();
+  *stats = t->stats;
+  return LPHT_OK;
+}
+
+const char *lpht_strerror(int code) {
+  switch (code) {
+    case LPHT_OK: return "ok";
+    case LPHT_ERR_INVALID: return "invalid argument";
+    case LPHT_ERR_OOM: return "out of device memory";
+    case LPHT_ERR_FULL: return "bounded table full: an insertion found no empty cell";
+    case LPHT_ERR_RESERVED_KEY: return "reserved key (0 = empty, 1 = tombstone) used";
+    case LPHT_ERR_DEVICE: return "HIP runtime error";
+    case LPHT_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+const char *lpht_version(void) { return "lpht 0.1 gfx950"; }
+
+}  // extern "C"

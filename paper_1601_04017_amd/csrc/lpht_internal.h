@@ -1,0 +1,69 @@
+// Internal interface between the host side of liblpht (lpht_api.cpp) and its
+// HIP kernels (lpht_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpht {
+
+constexpr uint64_t kEmpty = 0;  // empty_key
+constexpr uint64_t kTomb = 1;   // del_key
+
+constexpr uint32_t kErrFull = 1u;
+constexpr uint32_t kErrReserved = 2u;
+
+// Per-table device status block: exact counts and sticky error bits.
+struct alignas(64) DevStatus {
+  unsigned long long used;  // non-empty cells
+  unsigned long long live;  // live keys
+  unsigned int err;         // kErr* bits
+  unsigned int pad;
+  unsigned long long moved; // elements written by the last migration
+  unsigned long long aux[4];
+};
+
+enum OpKind : int { OP_FIND = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_UPDATE = 3, OP_ERASE = 4 };
+
+// Everything a bulk kernel needs, passed by value.
+struct BulkArgs {
+  void *cells;          // 2^log2c cells
+  uint32_t log2c;
+  uint32_t layout;      // 0 packed32, 1 kv64
+  uint32_t crc_hi;      // CRC-32C of the upper seed over zero data (hash constant)
+  uint32_t crc_lo;      // same for the lower seed
+  DevStatus *status;
+  const void *keys;
+  const void *vals;     // may be null: every value is 1
+  uint64_t n;
+  void *vals_out;       // find only; may be null
+  uint8_t *flags;       // may be null
+  uint32_t up;          // 0 assign, 1 add
+  uint32_t pad;
+};
+
+struct LaunchCfg {
+  uint32_t block_threads;
+  uint32_t group_width;
+  uint32_t blocks_per_cu;
+  uint32_t num_cus;
+  uint32_t migrate_block;
+  uint32_t aggregate;
+};
+
+// Kernel launchers (lpht_kernels.hip).  Each returns a hipError_t.
+hipError_t launch_bulk(OpKind op, const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_fill_zero(void *ptr, uint64_t bytes, const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_set_status(DevStatus *st, uint64_t used, uint64_t live, int clear_err,
+                             hipStream_t s);
+hipError_t launch_recount(const void *cells, uint32_t log2c, uint32_t layout, DevStatus *st,
+                          const LaunchCfg &cfg, hipStream_t s);
+// Block-parallel cluster migration of `old_cells` (2^log2_old cells) into
+// `new_cells` (2^log2_new cells, log2_new >= log2_old).  `new_cells` need not
+// be initialised.  Adds the number of moved elements to st->used and
+// st->live (the caller zeroes them first).
+hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_cells,
+                          uint32_t log2_new, uint32_t layout, uint32_t crc_hi, uint32_t crc_lo,
+                          int old_is_full, DevStatus *st, const LaunchCfg &cfg, hipStream_t s);
+
+}  // namespace lpht

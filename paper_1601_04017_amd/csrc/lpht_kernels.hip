@@ -1,0 +1,619 @@
+// HIP kernels of liblpht for gfx950 (CDNA4, wave64).
+//
+// Bulk operations of the folklore linear-probing table (Maier, Sanders,
+// Dementiev, arXiv 1601.04017, Sec. 4, Algorithm 1; tombstones Sec. 5.4) and
+// its block-parallel cluster migration (Sec. 5.3.1, Lemma 1).
+//
+// Execution model
+// ---------------
+// A "group" of G lanes (G = 1, 2, 4, 8, 16; all in one wavefront) works on one
+// operation at a time.  The group scans the table in windows of G consecutive
+// cells aligned to G, so that for G = 8 (16-byte cells) or G = 16 (8-byte
+// cells) one window is one 128-byte line read by one coalesced load.  The
+// first window starts at the operation's home cell; lanes before it are
+// masked.  Group-wide decisions come from wave ballots, so the lanes of a
+// group always take the same branches.  When an operation finishes, its group
+// immediately takes the next one (grid-stride over operations), so short and
+// long probe sequences do not hold each other up.
+//
+// The hash is the paper's: two CRC-32C register updates with different seeds
+// give the upper and lower 32 bits (Sec. 8.3).  gfx950 has no CRC
+// instruction, so each workgroup builds slicing-by-8 tables for the
+// Castagnoli polynomial in LDS.  The register update has no inversion and is
+// linear over GF(2), so CRC(seed, x) = CRC(0, x) ^ CRC(0, seed): one table
+// evaluation per key plus two constants computed on the host.  The cell
+// position is the top log2(c) bits of the 64-bit hash (scaling map of
+// Sec. 5.3.1).
+//
+// Atomics: 64-bit compare-and-swap claims an empty cell (the whole cell for
+// the packed layout, the key word for the 16-byte layout); a failed CAS
+// returns the current word, which is examined in place of the cell (the
+// "revisit" of Algorithm 1).  Increments use fetch-and-add and overwrites a
+// single store (Sec. 4).  All table atomics are device (agent) scope.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lpht_internal.h"
+
+namespace lpht {
+
+typedef unsigned long long u64;
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------- CRC-32C
+
+constexpr uint32_t kPolyRefl = 0x82F63B78u;  // Castagnoli, reflected
+
+// T[j][b] = CRC register after feeding byte b and then j zero bytes,
+// starting from register 0.
+__device__ __forceinline__ void crc_tables_build(uint32_t (*T)[256]) {
+  for (uint32_t b = threadIdx.x; b < 256; b += blockDim.x) {
+    uint32_t r = b;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r = (r >> 1) ^ (kPolyRefl & (0u - (r & 1u)));
+    T[0][b] = r;
+  }
+  __syncthreads();
+  for (int j = 1; j < 8; ++j) {
+    for (uint32_t b = threadIdx.x; b < 256; b += blockDim.x) {
+      uint32_t r = T[j - 1][b];
+      T[j][b] = (r >> 8) ^ T[0][r & 0xFFu];
+    }
+    __syncthreads();
+  }
+}
+
+// CRC(0, x) over the 8 little-endian bytes of x: byte i contributes
+// T[7 - i][byte].
+__device__ __forceinline__ uint32_t crc0_u64(const uint32_t (*T)[256], u64 x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  return T[7][lo & 0xFF] ^ T[6][(lo >> 8) & 0xFF] ^ T[5][(lo >> 16) & 0xFF] ^ T[4][lo >> 24] ^
+         T[3][hi & 0xFF] ^ T[2][(hi >> 8) & 0xFF] ^ T[1][(hi >> 16) & 0xFF] ^ T[0][hi >> 24];
+}
+
+// CRC(0, x) over the 4 little-endian bytes of a 32-bit key.
+__device__ __forceinline__ uint32_t crc0_u32(const uint32_t (*T)[256], uint32_t x) {
+  return T[3][x & 0xFF] ^ T[2][(x >> 8) & 0xFF] ^ T[1][(x >> 16) & 0xFF] ^ T[0][x >> 24];
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ u64 home_of(const uint32_t (*T)[256], u64 key, uint32_t crc_hi,
+                                       uint32_t crc_lo, uint32_t log2c) {
+  uint32_t c = (LAYOUT == 0) ? crc0_u32(T, (uint32_t)key) : crc0_u64(T, key);
+  u64 h = ((u64)(c ^ crc_hi) << 32) | (u64)(c ^ crc_lo);
+  return h >> (64 - log2c);
+}
+
+// ---------------------------------------------------------------- atomics
+
+__device__ __forceinline__ u64 cas64(u64 *p, u64 expected, u64 desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return expected;  // the word found in memory (== the expected one on success)
+}
+
+__device__ __forceinline__ void add64(u64 *p, u64 d) {
+  __hip_atomic_fetch_add(p, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store64(u64 *p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Adds the per-lane deltas of used/live and ORs the error bits into the
+// status block: wave reduction, LDS, then one atomic per workgroup.
+__device__ __forceinline__ void flush_counts(DevStatus *st, long long d_used, long long d_live,
+                                             uint32_t err, long long *s_acc, uint32_t *s_err) {
+  if (threadIdx.x == 0) {
+    s_acc[0] = 0;
+    s_acc[1] = 0;
+    *s_err = 0;
+  }
+  __syncthreads();
+  long long u = wave_sum(d_used);
+  long long l = wave_sum(d_live);
+  uint64_t anyerr = __ballot(err != 0);
+  uint32_t e = err;
+  if (anyerr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (u) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)u);
+    if (l) atomicAdd((unsigned long long *)&s_acc[1], (unsigned long long)l);
+    if (e) atomicOr(s_err, e);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_acc[0]) add64(&st->used, (u64)s_acc[0]);
+    if (s_acc[1]) add64(&st->live, (u64)s_acc[1]);
+    if (*s_err) atomicOr(&st->err, *s_err);
+  }
+}
+
+// ---------------------------------------------------------------- cells
+
+// Key and value of cell `i`.  PACKED32: one word, key low, value high.
+// KV64: words 2i (key) and 2i+1 (value).
+template <int LAYOUT>
+struct Cells;
+
+template <>
+struct Cells<0> {
+  static __device__ __forceinline__ u64 word(const void *c, u64 i) {
+    return ((const u64 *)c)[i];
+  }
+  static __device__ __forceinline__ u64 key_of(u64 w) { return w & 0xFFFFFFFFull; }
+  static __device__ __forceinline__ u64 val_of(u64 w) { return w >> 32; }
+};
+
+template <>
+struct Cells<1> {
+  static __device__ __forceinline__ u64x2 cell(const void *c, u64 i) {
+    return ((const u64x2 *)c)[i];
+  }
+  static __device__ __forceinline__ u64 key(const void *c, u64 i) {
+    return ((const u64 *)c)[2 * i];
+  }
+};
+
+// ---------------------------------------------------------------- bulk kernel
+
+template <int G>
+__device__ __forceinline__ uint32_t group_bits(uint64_t ballot, uint32_t gbase) {
+  if (G == 64) return (uint32_t)ballot;  // unused width
+  return (uint32_t)((ballot >> gbase) & ((1ull << G) - 1));
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ u64 load_key_in(const void *keys, u64 i) {
+  if (LAYOUT == 0) return ((const uint32_t *)keys)[i];
+  return ((const u64 *)keys)[i];
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void store_val_out(void *out, u64 i, u64 v) {
+  if (LAYOUT == 0)
+    ((uint32_t *)out)[i] = (uint32_t)v;
+  else
+    ((u64 *)out)[i] = v;
+}
+
+// One kernel for every bulk operation; OP and UP are compile-time.
+//   OP_FIND    : found flag + value
+//   OP_INSERT  : insert(k, d)
+//   OP_UPSERT  : insertOrUpdate(k, d, up)
+//   OP_UPDATE  : update(k, d, up)
+//   OP_ERASE   : tombstone delete
+template <int LAYOUT, int OP, int UP, int G>
+__global__ void __launch_bounds__(1024) k_bulk(BulkArgs A) {
+  __shared__ uint32_t T[8][256];
+  __shared__ long long s_acc[2];
+  __shared__ uint32_t s_err;
+  crc_tables_build(T);
+
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t gl = lane & (G - 1);    // lane within the group
+  const uint32_t gbase = lane - gl;      // first lane of the group in the wave
+  const u64 ngroups = ((u64)gridDim.x * blockDim.x) / G;
+  const u64 cap = 1ull << A.log2c;
+  const u64 mask = cap - 1;
+  const u64 max_windows = cap / G;       // plus one when the home is unaligned
+
+  long long d_used = 0, d_live = 0;
+  uint32_t err = 0;
+
+  u64 i = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  u64 k = 0, d = 1, base = 0, windows = 0, limit = 0;
+  uint32_t first = 0;
+  bool active = false;
+
+  // Takes operations from index i on until one needs probing (reserved keys
+  // are answered at once).
+  auto start = [&]() {
+    active = false;
+    while (i < A.n) {
+      k = load_key_in<LAYOUT>(A.keys, i);
+      if (k == kEmpty || k == kTomb) {
+        err |= kErrReserved;
+        if (gl == 0) {
+          if (A.flags) A.flags[i] = 0xFE;
+          if (OP == OP_FIND && A.vals_out) store_val_out<LAYOUT>(A.vals_out, i, 0);
+        }
+        i += ngroups;
+        continue;
+      }
+      d = A.vals ? load_key_in<LAYOUT>(A.vals, i) : 1;
+      u64 h = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
+      base = h & ~(u64)(G - 1);
+      first = (uint32_t)(h & (G - 1));
+      windows = 0;
+      limit = max_windows + (first ? 1 : 0);
+      active = true;
+      return;
+    }
+  };
+
+  auto finish = [&](uint8_t flag, u64 v) {
+    if (gl == 0) {
+      if (A.flags) A.flags[i] = flag;
+      if (OP == OP_FIND && A.vals_out) store_val_out<LAYOUT>(A.vals_out, i, v);
+    }
+    i += ngroups;
+    start();
+  };
+
+  start();
+  while (__any(active)) {
+    if (active) {
+      const u64 idx = base + gl;
+      u64 ck, cv = 0;
+      if (LAYOUT == 0) {
+        u64 w = Cells<0>::word(A.cells, idx);
+        ck = Cells<0>::key_of(w);
+        cv = Cells<0>::val_of(w);
+      } else if (OP == OP_FIND) {
+        u64x2 c = Cells<1>::cell(A.cells, idx);
+        ck = c.x;
+        cv = c.y;
+      } else {
+        ck = Cells<1>::key(A.cells, idx);
+      }
+      bool done = false;
+      uint8_t flag = 0;
+      u64 outv = 0;
+      // Evaluate the window; a failed CAS updates the lane's key and the
+      // window is evaluated again from the next lane on.
+      while (true) {
+        const bool valid = gl >= first;
+        const uint32_t bh = group_bits<G>(__ballot(valid && ck == k), gbase);
+        const uint32_t be = group_bits<G>(__ballot(valid && ck == kEmpty), gbase);
+        const uint32_t ev = bh | be;
+        if (ev == 0) break;
+        const uint32_t j = __builtin_ctz(ev);
+        const uint32_t src = gbase + j;
+        if ((bh >> j) & 1u) {
+          // key present at lane j
+          if (OP == OP_FIND) {
+            outv = __shfl(cv, src, 64);
+            flag = 1;
+            done = true;
+          } else if (OP == OP_INSERT) {
+            flag = 0;
+            done = true;
+          } else if (OP == OP_UPSERT || OP == OP_UPDATE) {
+            if (gl == j) {
+              if (LAYOUT == 0) {
+                u64 *w = (u64 *)A.cells + idx;
+                if (UP == 1)
+                  add64(w, d << 32);
+                else
+                  store32((uint32_t *)w + 1, (uint32_t)d);
+              } else {
+                u64 *v = (u64 *)A.cells + 2 * idx + 1;
+                if (UP == 1)
+                  add64(v, d);
+                else
+                  store64(v, d);
+              }
+            }
+            flag = (OP == OP_UPDATE) ? 1 : 0;
+            done = true;
+          } else {  // OP_ERASE
+            u64 old = 0;
+            bool won = false;
+            if (gl == j) {
+              if (LAYOUT == 0) {
+                u64 w = ((u64)cv << 32) | k;
+                old = cas64((u64 *)A.cells + idx, w, (w & ~0xFFFFFFFFull) | kTomb);
+                won = (old == w);
+                if (!won) old &= 0xFFFFFFFFull;
+              } else {
+                old = cas64((u64 *)A.cells + 2 * idx, k, kTomb);
+                won = (old == k);
+              }
+              if (won) d_live -= 1;
+            }
+            won = __shfl((int)won, src, 64) != 0;
+            if (won) {
+              flag = 1;
+              done = true;
+            } else {
+              // another operation changed this cell first; look at what is there now
+              old = __shfl(old, src, 64);
+              if (gl == j) ck = old;
+              if (LAYOUT == 0 && gl == j && old == k) {
+                // only the value changed under us: reload the word and retry
+                u64 w = Cells<0>::word(A.cells, idx);
+                ck = Cells<0>::key_of(w);
+                cv = Cells<0>::val_of(w);
+              }
+              first = j;  // re-evaluate lane j with its new key
+              continue;
+            }
+          }
+        } else {
+          // empty cell at lane j: k is absent
+          if (OP == OP_FIND || OP == OP_UPDATE || OP == OP_ERASE) {
+            flag = 0;
+            outv = 0;
+            done = true;
+          } else {
+            u64 old = 0;
+            if (gl == j) {
+              if (LAYOUT == 0) {
+                old = cas64((u64 *)A.cells + idx, 0ull, (d << 32) | k);
+                if (old == 0) {
+                  d_used += 1;
+                  d_live += 1;
+                }
+              } else {
+                old = cas64((u64 *)A.cells + 2 * idx, kEmpty, k);
+                if (old == kEmpty) {
+                  u64 *v = (u64 *)A.cells + 2 * idx + 1;
+                  if (OP == OP_UPSERT && UP == 1)
+                    add64(v, d);  // concurrent increments of the same key also add
+                  else
+                    store64(v, d);
+                  d_used += 1;
+                  d_live += 1;
+                }
+              }
+            }
+            old = __shfl(old, src, 64);
+            const u64 okey = (LAYOUT == 0) ? (old & 0xFFFFFFFFull) : old;
+            if (old == 0) {
+              flag = 1;
+              done = true;
+            } else if (okey == k) {
+              // lost the race to an insertion of the same key
+              if (OP == OP_UPSERT && gl == j) {
+                if (LAYOUT == 0) {
+                  u64 *w = (u64 *)A.cells + idx;
+                  if (UP == 1)
+                    add64(w, d << 32);
+                  else
+                    store32((uint32_t *)w + 1, (uint32_t)d);
+                } else {
+                  u64 *v = (u64 *)A.cells + 2 * idx + 1;
+                  if (UP == 1)
+                    add64(v, d);
+                  else
+                    store64(v, d);
+                }
+              }
+              flag = 0;
+              done = true;
+            } else {
+              // another key took the cell: revisit it with that key
+              if (gl == j) ck = okey;
+              first = j;
+              continue;
+            }
+          }
+        }
+        break;
+      }
+      if (done) {
+        finish(flag, outv);
+      } else {
+        // next window
+        base = (base + G) & mask;
+        first = 0;
+        windows += 1;
+        if (windows >= limit) {
+          if (OP == OP_INSERT || OP == OP_UPSERT) {
+            err |= kErrFull;
+            finish(0xFF, 0);
+          } else {
+            finish(0, 0);
+          }
+        }
+      }
+    }
+  }
+  flush_counts(A.status, d_used, d_live, err, s_acc, &s_err);
+}
+
+// ---------------------------------------------------------------- small kernels
+
+__global__ void k_fill_zero(u64x2 *p, u64 n16) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  const u64x2 z = {0ull, 0ull};
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    __builtin_nontemporal_store(z, p + i);
+}
+
+__global__ void k_set_status(DevStatus *st, u64 used, u64 live, int clear_err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->used = used;
+    st->live = live;
+    st->moved = 0;
+    if (clear_err) st->err = 0;
+  }
+}
+
+template <int LAYOUT>
+__global__ void k_recount(const void *cells, u64 cap, DevStatus *st) {
+  __shared__ long long s_acc[2];
+  __shared__ uint32_t s_err;
+  long long u = 0, l = 0;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += stride) {
+    u64 key = (LAYOUT == 0) ? (((const u64 *)cells)[i] & 0xFFFFFFFFull) : ((const u64 *)cells)[2 * i];
+    u += (key != kEmpty);
+    l += (key != kEmpty && key != kTomb);
+  }
+  flush_counts(st, u, l, 0, s_acc, &s_err);
+}
+
+// ---------------------------------------------------------------- migration
+
+// Simple block-parallel migration (Sec. 5.3.1): one thread per old cell; a
+// thread whose cell starts a cluster (non-empty, predecessor empty) walks
+// the cluster in old-array order and re-inserts its live elements into the
+// zero-initialised new table with plain linear probing.  By Lemma 1 the
+// target ranges of distinct clusters are disjoint, so no atomics are needed
+// and the result equals the sequential migration.  A table without empty
+// cells is one cluster that starts at cell 0.
+template <int LAYOUT>
+__global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, uint32_t log2_old,
+                                                        void *new_cells, uint32_t log2_new,
+                                                        uint32_t crc_hi, uint32_t crc_lo,
+                                                        int old_is_full, DevStatus *st) {
+  __shared__ uint32_t T[8][256];
+  __shared__ long long s_acc[2];
+  __shared__ uint32_t s_err;
+  crc_tables_build(T);
+  const u64 cap = 1ull << log2_old, mask = cap - 1;
+  const u64 nmask = (1ull << log2_new) - 1;
+  long long moved = 0;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 a = (u64)blockIdx.x * blockDim.x + threadIdx.x; a < cap; a += stride) {
+    u64 ka, kp;
+    if (LAYOUT == 0) {
+      ka = ((const u64 *)old_cells)[a] & 0xFFFFFFFFull;
+      kp = ((const u64 *)old_cells)[(a - 1) & mask] & 0xFFFFFFFFull;
+    } else {
+      ka = ((const u64 *)old_cells)[2 * a];
+      kp = ((const u64 *)old_cells)[2 * ((a - 1) & mask)];
+    }
+    bool is_start = old_is_full ? (a == 0) : (ka != kEmpty && kp == kEmpty);
+    if (!is_start) continue;
+    u64 j = a;
+    for (u64 steps = 0; steps < cap; ++steps, j = (j + 1) & mask) {
+      u64 key, val;
+      if (LAYOUT == 0) {
+        u64 w = ((const u64 *)old_cells)[j];
+        key = w & 0xFFFFFFFFull;
+        val = w >> 32;
+      } else {
+        u64x2 c = ((const u64x2 *)old_cells)[j];
+        key = c.x;
+        val = c.y;
+      }
+      if (key == kEmpty) break;
+      if (key == kTomb) continue;
+      u64 p = home_of<LAYOUT>(T, key, crc_hi, crc_lo, log2_new);
+      if (LAYOUT == 0) {
+        u64 *nc = (u64 *)new_cells;
+        while ((nc[p] & 0xFFFFFFFFull) != kEmpty) p = (p + 1) & nmask;
+        nc[p] = key | (val << 32);
+      } else {
+        u64x2 *nc = (u64x2 *)new_cells;
+        while (((u64 *)new_cells)[2 * p] != kEmpty) p = (p + 1) & nmask;
+        u64x2 cell = {key, val};
+        nc[p] = cell;
+      }
+      moved += 1;
+    }
+  }
+  flush_counts(st, moved, moved, 0, s_acc, &s_err);
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline uint32_t grid_for(u64 work_items, const LaunchCfg &cfg) {
+  u64 blocks = (work_items + cfg.block_threads - 1) / cfg.block_threads;
+  u64 cap = (u64)cfg.num_cus * cfg.blocks_per_cu;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  return (uint32_t)blocks;
+}
+
+template <int LAYOUT, int OP, int UP, int G>
+static hipError_t launch_g(const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  uint32_t grid = grid_for(a.n * (u64)G, cfg);
+  hipLaunchKernelGGL((k_bulk<LAYOUT, OP, UP, G>), dim3(grid), dim3(cfg.block_threads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int LAYOUT, int OP, int UP>
+static hipError_t launch_lo(const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  switch (cfg.group_width) {
+    case 1: return launch_g<LAYOUT, OP, UP, 1>(a, cfg, s);
+    case 2: return launch_g<LAYOUT, OP, UP, 2>(a, cfg, s);
+    case 4: return launch_g<LAYOUT, OP, UP, 4>(a, cfg, s);
+    case 8: return launch_g<LAYOUT, OP, UP, 8>(a, cfg, s);
+    case 16: return launch_g<LAYOUT, OP, UP, 16>(a, cfg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LAYOUT>
+static hipError_t launch_layout(OpKind op, const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  switch (op) {
+    case OP_FIND: return launch_lo<LAYOUT, OP_FIND, 0>(a, cfg, s);
+    case OP_INSERT: return launch_lo<LAYOUT, OP_INSERT, 0>(a, cfg, s);
+    case OP_UPSERT:
+      return a.up ? launch_lo<LAYOUT, OP_UPSERT, 1>(a, cfg, s) : launch_lo<LAYOUT, OP_UPSERT, 0>(a, cfg, s);
+    case OP_UPDATE:
+      return a.up ? launch_lo<LAYOUT, OP_UPDATE, 1>(a, cfg, s) : launch_lo<LAYOUT, OP_UPDATE, 0>(a, cfg, s);
+    case OP_ERASE: return launch_lo<LAYOUT, OP_ERASE, 0>(a, cfg, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_bulk(OpKind op, const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  return a.layout == 0 ? launch_layout<0>(op, a, cfg, s) : launch_layout<1>(op, a, cfg, s);
+}
+
+hipError_t launch_fill_zero(void *ptr, uint64_t bytes, const LaunchCfg &cfg, hipStream_t s) {
+  u64 n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  uint32_t grid = grid_for(n16, cfg);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(cfg.block_threads), 0, s, (u64x2 *)ptr, n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_status(DevStatus *st, uint64_t used, uint64_t live, int clear_err,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, st, (u64)used, (u64)live, clear_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_recount(const void *cells, uint32_t log2c, uint32_t layout, DevStatus *st,
+                          const LaunchCfg &cfg, hipStream_t s) {
+  u64 cap = 1ull << log2c;
+  uint32_t grid = grid_for(cap, cfg);
+  if (layout == 0)
+    hipLaunchKernelGGL(k_recount<0>, dim3(grid), dim3(cfg.block_threads), 0, s, cells, cap, st);
+  else
+    hipLaunchKernelGGL(k_recount<1>, dim3(grid), dim3(cfg.block_threads), 0, s, cells, cap, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_cells,
+                          uint32_t log2_new, uint32_t layout, uint32_t crc_hi, uint32_t crc_lo,
+                          int old_is_full, DevStatus *st, const LaunchCfg &cfg, hipStream_t s) {
+  const u64 new_bytes = (1ull << log2_new) * (layout == 0 ? 8ull : 16ull);
+  hipError_t e = launch_fill_zero(new_cells, new_bytes, cfg, s);
+  if (e != hipSuccess) return e;
+  u64 cap = 1ull << log2_old;
+  LaunchCfg c2 = cfg;
+  c2.block_threads = 256;
+  uint32_t grid = grid_for(cap, c2);
+  if (layout == 0)
+    hipLaunchKernelGGL(k_migrate_simple<0>, dim3(grid), dim3(256), 0, s, old_cells, log2_old,
+                       new_cells, log2_new, crc_hi, crc_lo, old_is_full, st);
+  else
+    hipLaunchKernelGGL(k_migrate_simple<1>, dim3(grid), dim3(256), 0, s, old_cells, log2_old,
+                       new_cells, log2_new, crc_hi, crc_lo, old_is_full, st);
+  return hipGetLastError();
+}
+
+}  // namespace lpht

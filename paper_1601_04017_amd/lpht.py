@@ -1,0 +1,296 @@
+"""ctypes binding of liblpht.so (C ABI in include/lpht.h).
+
+Argument marshalling only: every table operation runs in the library's HIP
+kernels.  Device arrays are torch tensors on the table's GPU (any integer
+dtype of the right width; keys and values are bit patterns), streams are torch
+streams.  If the library is missing this module raises instead of falling
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblpht.so")
+
+OK = 0
+ERR_INVALID = -1
+ERR_OOM = -2
+ERR_FULL = -3
+ERR_RESERVED_KEY = -4
+ERR_DEVICE = -5
+ERR_UNSUPPORTED = -6
+
+FLAG_RESERVED = 0xFE
+FLAG_FULL = 0xFF
+
+PACKED32 = 0
+KV64 = 1
+ASSIGN = 0
+ADD = 1
+
+SEED_HI = 0x9E3779B9
+SEED_LO = 0xFFFFFFFF
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class lpht_config(ctypes.Structure):
+    _fields_ = [
+        ("layout", ctypes.c_uint32),
+        ("log2_capacity", ctypes.c_uint32),
+        ("seed_hi", ctypes.c_uint32),
+        ("seed_lo", ctypes.c_uint32),
+        ("max_fill_num", ctypes.c_uint32),
+        ("max_fill_den", ctypes.c_uint32),
+        ("auto_grow", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("alloc", _ALLOC_FN),
+        ("free", _FREE_FN),
+        ("alloc_ctx", ctypes.c_void_p),
+    ]
+
+
+class lpht_tuning(ctypes.Structure):
+    _fields_ = [
+        ("block_threads", ctypes.c_uint32),
+        ("group_width", ctypes.c_uint32),
+        ("blocks_per_cu", ctypes.c_uint32),
+        ("migrate_block", ctypes.c_uint32),
+        ("aggregate", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
+    ]
+
+
+class lpht_stats(ctypes.Structure):
+    _fields_ = [
+        ("migrations", ctypes.c_uint64),
+        ("resizes", ctypes.c_uint64),
+        ("cells_migrated", ctypes.c_uint64),
+        ("host_syncs", ctypes.c_uint64),
+        ("migrate_ms", ctypes.c_double),
+    ]
+
+
+# name -> (restype, argtypes); names are the C ABI's
+_VP = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_U32 = ctypes.c_uint32
+_SIGS = {
+    "lpht_config_default": (None, [ctypes.POINTER(lpht_config)]),
+    "lpht_create": (ctypes.c_int, [ctypes.POINTER(lpht_config), _VP, ctypes.POINTER(_VP)]),
+    "lpht_destroy": (ctypes.c_int, [_VP, _VP]),
+    "lpht_clear": (ctypes.c_int, [_VP, _VP]),
+    "lpht_insert": (ctypes.c_int, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    "lpht_find": (ctypes.c_int, [_VP, _VP, _U64, _VP, _VP, _VP]),
+    "lpht_insert_or_update": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP, _VP]),
+    "lpht_update": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP, _VP]),
+    "lpht_erase": (ctypes.c_int, [_VP, _VP, _U64, _VP, _VP]),
+    "lpht_grow": (ctypes.c_int, [_VP, _U32, _VP]),
+    "lpht_count": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
+    "lpht_capacity": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U32)]),
+    "lpht_cell_bytes": (_U32, [_U32]),
+    "lpht_export_cells": (ctypes.c_int, [_VP, _VP, _VP]),
+    "lpht_import_cells": (ctypes.c_int, [_VP, _VP, _U32, _VP]),
+    "lpht_status": (ctypes.c_int, [_VP, _VP]),
+    "lpht_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_tuning)]),
+    "lpht_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_tuning)]),
+    "lpht_set_timing": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "lpht_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_stats)]),
+    "lpht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "lpht_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads liblpht.so and declares its signatures.  Raises if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"liblpht.so not built ({path}); run python -m paper_1601_04017_amd.build")
+        L = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+class LphtError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = load().lpht_strerror(code).decode()
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise LphtError(rc, what)
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Table:
+    """One device table.  Methods map one-to-one onto the C ABI calls."""
+
+    def __init__(self, layout: int = KV64, log2_capacity: int = 12, auto_grow: bool = False,
+                 seed_hi: int = SEED_HI, seed_lo: int = SEED_LO, alpha=(1, 2), stream=None):
+        import torch
+        L = load()
+        self.layout = layout
+        self.word = 4 if layout == PACKED32 else 8
+        self.torch_dtype = torch.int32 if layout == PACKED32 else torch.int64
+        cfg = lpht_config()
+        L.lpht_config_default(ctypes.byref(cfg))
+        cfg.layout = layout
+        cfg.log2_capacity = log2_capacity
+        cfg.seed_hi = seed_hi
+        cfg.seed_lo = seed_lo
+        cfg.max_fill_num, cfg.max_fill_den = alpha
+        cfg.auto_grow = 1 if auto_grow else 0
+        h = ctypes.c_void_p()
+        self._stream = stream
+        _check(L.lpht_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)), "lpht_create")
+        self._h = h
+
+    def close(self, stream=None):
+        if getattr(self, "_h", None):
+            load().lpht_destroy(self._h, _stream_handle(stream if stream is not None else self._stream))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clear(self, stream=None):
+        _check(load().lpht_clear(self._h, _stream_handle(stream)), "lpht_clear")
+
+    # ---- helpers
+    def _n(self, keys):
+        if keys.element_size() != self.word:
+            raise ValueError(f"keys must be {self.word}-byte integers")
+        return keys.numel()
+
+    def _flags(self, n, want):
+        import torch
+        return torch.empty(n, dtype=torch.uint8, device="cuda") if want else None
+
+    # ---- operations (stream-ordered; results are device tensors)
+    def insert(self, keys, vals=None, flags=True, stream=None):
+        n = self._n(keys)
+        f = self._flags(n, flags)
+        _check(load().lpht_insert(self._h, _ptr(keys), _ptr(vals), n, _ptr(f), _stream_handle(stream)),
+               "lpht_insert")
+        return f
+
+    def find(self, keys, vals_out=None, found=None, stream=None):
+        import torch
+        n = self._n(keys)
+        if vals_out is None:
+            vals_out = torch.empty(n, dtype=self.torch_dtype, device="cuda")
+        if found is None:
+            found = torch.empty(n, dtype=torch.uint8, device="cuda")
+        _check(load().lpht_find(self._h, _ptr(keys), n, _ptr(vals_out), _ptr(found),
+                                _stream_handle(stream)), "lpht_find")
+        return vals_out, found
+
+    def insert_or_update(self, keys, vals=None, op=ADD, flags=True, stream=None):
+        n = self._n(keys)
+        f = self._flags(n, flags)
+        _check(load().lpht_insert_or_update(self._h, _ptr(keys), _ptr(vals), n, op, _ptr(f),
+                                            _stream_handle(stream)), "lpht_insert_or_update")
+        return f
+
+    def update(self, keys, vals=None, op=ASSIGN, flags=True, stream=None):
+        n = self._n(keys)
+        f = self._flags(n, flags)
+        _check(load().lpht_update(self._h, _ptr(keys), _ptr(vals), n, op, _ptr(f),
+                                  _stream_handle(stream)), "lpht_update")
+        return f
+
+    def erase(self, keys, flags=True, stream=None):
+        n = self._n(keys)
+        f = self._flags(n, flags)
+        _check(load().lpht_erase(self._h, _ptr(keys), n, _ptr(f), _stream_handle(stream)), "lpht_erase")
+        return f
+
+    def grow(self, log2_new: int, stream=None):
+        _check(load().lpht_grow(self._h, log2_new, _stream_handle(stream)), "lpht_grow")
+
+    def count(self, stream=None):
+        u, l = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().lpht_count(self._h, ctypes.byref(u), ctypes.byref(l), _stream_handle(stream)),
+               "lpht_count")
+        return u.value, l.value
+
+    @property
+    def capacity(self) -> int:
+        c, lg = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(load().lpht_capacity(self._h, ctypes.byref(c), ctypes.byref(lg)), "lpht_capacity")
+        return c.value
+
+    @property
+    def log2_capacity(self) -> int:
+        c, lg = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(load().lpht_capacity(self._h, ctypes.byref(c), ctypes.byref(lg)), "lpht_capacity")
+        return lg.value
+
+    def export_cells(self, stream=None):
+        """Raw cells as an int64 device tensor: one word per cell (PACKED32)
+        or key, value words (KV64)."""
+        import torch
+        words = self.capacity * (1 if self.layout == PACKED32 else 2)
+        out = torch.empty(words, dtype=torch.int64, device="cuda")
+        _check(load().lpht_export_cells(self._h, _ptr(out), _stream_handle(stream)), "lpht_export_cells")
+        return out
+
+    def import_cells(self, cells, log2_capacity: int, stream=None):
+        _check(load().lpht_import_cells(self._h, _ptr(cells), log2_capacity, _stream_handle(stream)),
+               "lpht_import_cells")
+
+    def status(self, stream=None) -> int:
+        return load().lpht_status(self._h, _stream_handle(stream))
+
+    def set_tuning(self, block_threads=256, group_width=1, blocks_per_cu=8, migrate_block=4096,
+                   aggregate=0):
+        t = lpht_tuning(block_threads, group_width, blocks_per_cu, migrate_block, aggregate)
+        _check(load().lpht_set_tuning(self._h, ctypes.byref(t)), "lpht_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = lpht_tuning()
+        _check(load().lpht_get_tuning(self._h, ctypes.byref(t)), "lpht_get_tuning")
+        return {k: getattr(t, k) for k in ("block_threads", "group_width", "blocks_per_cu",
+                                            "migrate_block", "aggregate")}
+
+    def set_timing(self, on: bool = True):
+        _check(load().lpht_set_timing(self._h, 1 if on else 0), "lpht_set_timing")
+
+    def stats(self) -> dict:
+        s = lpht_stats()
+        _check(load().lpht_get_stats(self._h, ctypes.byref(s)), "lpht_get_stats")
+        return {k: getattr(s, k) for k, _ in lpht_stats._fields_}

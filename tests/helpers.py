@@ -174,3 +174,32 @@ class DictModel:
             del self.d[k]
             return 1
         return 0
+
+
+def key_run_starts(cells, layout):
+    """Live keys sorted, with the start index of the maximal non-empty run
+    holding each one and its value.  Two tables with equal occupancy and equal
+    outputs here hold the same keys in the same runs."""
+    keys, vals = split_cells(cells, layout)
+    occ = keys != EMPTY
+    live = occ & (keys != TOMB)
+    rs = run_start(occ) % occ.size if not occ.all() else np.zeros(occ.size, np.int64)
+    k = keys[live]
+    o = np.argsort(k, kind="stable")
+    return k[o], rs[live][o], vals[live][o]
+
+
+def assert_same_table_modulo_run_order(cells_a, cells_b, layout):
+    """Equal occupancy bitmaps, and every live key in the same run with the
+    same value.  Within a run the order of keys may differ (it depends on the
+    order in which concurrent insertions were linearized)."""
+    oa, ob = occupancy(cells_a, layout), occupancy(cells_b, layout)
+    assert oa.size == ob.size
+    if not np.array_equal(oa, ob):
+        bad = np.flatnonzero(oa != ob)
+        raise AssertionError(f"occupancy differs at {bad.size} cells, first {bad[:8]}")
+    ka, ra, va = key_run_starts(cells_a, layout)
+    kb, rb, vb = key_run_starts(cells_b, layout)
+    assert np.array_equal(ka, kb), "live key sets differ"
+    assert np.array_equal(ra, rb), "a key sits in a different run"
+    assert np.array_equal(va, vb), "values differ"

@@ -1,0 +1,69 @@
+"""CPU-side checks of the C ABI: the library loads without a GPU and exports
+every function that include/lpht.h declares, and the binding declares the same
+set.  No compute call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1601_04017_amd import build as libbuild
+from paper_1601_04017_amd import lpht
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpht.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(lpht_[a-z0-9_]+)\s*\(", src))
+    # function-pointer typedefs are not functions
+    return {n for n in names if not n.endswith("_fn")}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    libbuild.build(force=False)
+    return lpht.load()
+
+
+def test_header_declares_functions():
+    d = _declared()
+    assert {"lpht_create", "lpht_insert", "lpht_find", "lpht_insert_or_update", "lpht_update",
+            "lpht_erase", "lpht_grow", "lpht_count", "lpht_destroy"} <= d
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in sorted(_declared()):
+        assert hasattr(lib, name), name
+        assert isinstance(getattr(lib, name), ctypes._CFuncPtr)
+
+
+def test_binding_covers_header(lib):
+    assert set(lpht.exported_symbols()) == _declared()
+
+
+def test_static_calls_need_no_gpu(lib):
+    assert lib.lpht_version().startswith(b"lpht")
+    assert lib.lpht_strerror(lpht.ERR_FULL).startswith(b"bounded table full")
+    assert lib.lpht_cell_bytes(lpht.PACKED32) == 8 and lib.lpht_cell_bytes(lpht.KV64) == 16
+    cfg = lpht.lpht_config()
+    lib.lpht_config_default(ctypes.byref(cfg))
+    assert (cfg.layout, cfg.log2_capacity, cfg.seed_hi, cfg.seed_lo) == (1, 12, 0x9E3779B9, 0xFFFFFFFF)
+    assert (cfg.max_fill_num, cfg.max_fill_den, cfg.auto_grow) == (1, 2, 0)
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    # rejected before any device call
+    out = ctypes.c_void_p()
+    cfg = lpht.lpht_config()
+    lib.lpht_config_default(ctypes.byref(cfg))
+    cfg.log2_capacity = 3
+    assert lib.lpht_create(ctypes.byref(cfg), None, ctypes.byref(out)) == lpht.ERR_INVALID
+    cfg.log2_capacity = 12
+    cfg.layout = 7
+    assert lib.lpht_create(ctypes.byref(cfg), None, ctypes.byref(out)) == lpht.ERR_INVALID
+    assert lib.lpht_insert(None, None, None, 0, None, None) == lpht.ERR_INVALID
+    assert lib.lpht_grow(None, 10, None) == lpht.ERR_INVALID
+    assert lib.lpht_destroy(None, None) == lpht.OK
