@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--group-width", type=int, default=None)
+    ap.add_argument("--aggregate", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (tables shard by hash "
@@ -127,9 +128,14 @@ def main():
 
     t1 = lpht.Table(layout=lpht.KV64, log2_capacity=LOG2C)
     t2 = lpht.Table(layout=lpht.KV64, log2_capacity=LOG2C)
-    if args.group_width:
-        t1.set_tuning(group_width=args.group_width)
-        t2.set_tuning(group_width=args.group_width)
+    if args.group_width or args.aggregate is not None:
+        tun = t1.get_tuning()
+        if args.group_width:
+            tun["group_width"] = args.group_width
+        if args.aggregate is not None:
+            tun["aggregate"] = args.aggregate
+        t1.set_tuning(**tun)
+        t2.set_tuning(**tun)
     stream = torch.cuda.current_stream()
     phases = ["clear1", "insert", "find_hit", "find_miss", "clear2", "upsert_zipf"]
 
@@ -155,7 +161,10 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # correctness spot check of the last warmup pass (full arrays, on device)
+    if args.warmup < 1:
+        step()
+        torch.cuda.synchronize()
+    # correctness spot check of the last warmup pass (on device)
     hv, hf = t1.find(d_hit[:1 << 20])
     assert bool((hf == 1).all()), "present keys not found"
     assert bool((hv == torch.from_numpy(perm[:1 << 20].astype(np.int64)).to(dev)).all()), "values"
@@ -218,6 +227,7 @@ def main():
             "fill": round(alpha, 4),
             "zipf_s": ZIPF_S,
             "group_width": t1.get_tuning()["group_width"],
+            "aggregate": t2.get_tuning()["aggregate"],
         },
         "phases_ms": {k: round(v, 3) for k, v in ph_ms.items()},
         "phase_mops": {p: round(N_OPS / (ph_ms[p] / 1e3) / 1e6, 1)

@@ -106,7 +106,7 @@ typedef struct lpht_tuning {
   uint32_t group_width;   /* lanes that probe one operation together: 1, 2, 4, 8 or 16 */
   uint32_t blocks_per_cu; /* resident workgroups per compute unit the grid is sized for, 1..32 */
   uint32_t migrate_block; /* old cells per migration workgroup, power of two 256..8192 */
-  uint32_t aggregate;     /* 1: combine equal keys inside a workgroup before LPHT_ADD upserts */
+  uint32_t aggregate;     /* 1 (default): combine equal keys in LDS before LPHT_ADD upserts */
   uint32_t reserved[3];
 } lpht_tuning;
 

@@ -11,6 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblpht.so")
 SOURCES = ["lpht_kernels.hip", "lpht_api.cpp"]
+ROOFLINE_OUT = os.path.join(PKG, "libroofline.so")
+ROOFLINE_SOURCES = ["lpht_roofline.hip"]
 HEADERS = ["lpht_internal.h", os.path.join("..", "..", "include", "lpht.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -27,29 +29,35 @@ FLAGS = [
 ]
 
 
-def _stale() -> bool:
-    if not os.path.exists(OUT):
+def _stale(out, sources, headers) -> bool:
+    if not os.path.exists(out):
         return True
-    t = os.path.getmtime(OUT)
-    for f in SOURCES + HEADERS:
+    t = os.path.getmtime(out)
+    for f in sources + headers:
         if os.path.getmtime(os.path.join(CSRC, f)) > t:
             return True
     return False
 
 
-def build(force: bool = True, verbose: bool = False) -> str:
-    if not force and not _stale():
-        return OUT
-    tmp = OUT + ".tmp"
+def _hipcc(out, sources, verbose):
+    tmp = out + ".tmp"
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp]
-    cmd += [os.path.join(CSRC, f) for f in SOURCES]
+    cmd += [os.path.join(CSRC, f) for f in sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building liblpht.so")
-    os.replace(tmp, OUT)
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+    os.replace(tmp, out)
+
+
+def build(force: bool = True, verbose: bool = False) -> str:
+    """Builds liblpht.so (the table) and libroofline.so (memory ceilings)."""
+    if force or _stale(OUT, SOURCES, HEADERS):
+        _hipcc(OUT, SOURCES, verbose)
+    if force or _stale(ROOFLINE_OUT, ROOFLINE_SOURCES, []):
+        _hipcc(ROOFLINE_OUT, ROOFLINE_SOURCES, verbose)
     return OUT
 
 

@@ -185,7 +185,11 @@ int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
 // reads the device counters only when the bound does not already rule a
 // migration out.
 int grow_before_batch(lpht_table *t, uint64_t b, hipStream_t s) {
-  if (!t->cfg.auto_grow || b == 0) return LPHT_OK;
+  if (b == 0) return LPHT_OK;
+  if (!t->cfg.auto_grow) {
+    t->pending += b;
+    return LPHT_OK;
+  }
   const uint64_t c = 1ull << t->log2c;
   if (within_fill(t, t->known_used + t->pending + b, c)) {
     t->pending += b;
@@ -261,6 +265,12 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
   a.vals_out = vals_out;
   a.flags = flags;
   a.up = up;
+  // Combining equal keys is exact for "add" as long as no insertion can find
+  // the table full: used + (insertions since the last count) <= c.
+  a.aggregate = (op == OP_UPSERT && up == LPHT_ADD && t->tuning.aggregate &&
+                 t->known_used + t->pending <= (1ull << t->log2c))
+                    ? 1u
+                    : 0u;
   return from_hip(launch_bulk(op, a, t->launch, s));
 }
 
@@ -308,7 +318,7 @@ int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out) {
   t->tuning.group_width = 1;
   t->tuning.blocks_per_cu = 8;
   t->tuning.migrate_block = 4096;
-  t->tuning.aggregate = 0;
+  t->tuning.aggregate = 1;
   fill_launch(t);
   const int kb = cfg->layout == LPHT_PACKED32 ? 4 : 8;
   t->crc_hi = crc0_bytes(cfg->seed_hi, kb);

@@ -39,7 +39,7 @@ struct BulkArgs {
   void *vals_out;       // find only; may be null
   uint8_t *flags;       // may be null
   uint32_t up;          // 0 assign, 1 add
-  uint32_t pad;
+  uint32_t aggregate;   // 1: combine equal keys in LDS (upsert with add only)
 };
 
 struct LaunchCfg {

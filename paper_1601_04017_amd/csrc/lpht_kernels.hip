@@ -97,14 +97,6 @@ __device__ __forceinline__ void add64(u64 *p, u64 d) {
   __hip_atomic_fetch_add(p, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void store64(u64 *p, u64 v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void store32(uint32_t *p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // ---------------------------------------------------------------- reductions
 
 __device__ __forceinline__ long long wave_sum(long long v) {
@@ -192,6 +184,30 @@ __device__ __forceinline__ void store_val_out(void *out, u64 i, u64 v) {
     ((u64 *)out)[i] = v;
 }
 
+// Writes of values into cells.  Plain stores: a value is written either by
+// the lane whose CAS claimed the cell (no other lane writes it in that call)
+// or as an overwrite whose result may be any one of the concurrent values;
+// the line stays in L2 and is written back whole.
+__device__ __forceinline__ void put64(u64 *p, u64 v) { *p = v; }
+__device__ __forceinline__ void put32(uint32_t *p, uint32_t v) { *p = v; }
+
+// Orders LDS accesses of the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Operations per wavefront round.  A wavefront takes rounds of ROUND
+// consecutive operations; its groups work through them, results are staged
+// in LDS, and at the end of the round the wavefront writes them out as whole
+// lines (128 flag bytes, 128 values), so output lines are written once.
+constexpr uint32_t ROUND = 128;
+
+__host__ __device__ constexpr uint32_t bulk_lds_bytes_per_wave(int op) {
+  return ROUND * (op == OP_FIND ? 9u : 1u);
+}
+
 // One kernel for every bulk operation; OP and UP are compile-time.
 //   OP_FIND    : found flag + value
 //   OP_INSERT  : insert(k, d)
@@ -203,227 +219,464 @@ __global__ void __launch_bounds__(1024) k_bulk(BulkArgs A) {
   __shared__ uint32_t T[8][256];
   __shared__ long long s_acc[2];
   __shared__ uint32_t s_err;
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
   crc_tables_build(T);
 
+  constexpr uint32_t NGW = 64 / G;            // groups per wavefront
+  constexpr uint32_t PER_GROUP = ROUND / NGW; // operations per group per round
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t gl = lane & (G - 1);    // lane within the group
-  const uint32_t gbase = lane - gl;      // first lane of the group in the wave
-  const u64 ngroups = ((u64)gridDim.x * blockDim.x) / G;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t nwb = blockDim.x >> 6;
+  const uint32_t gl = lane & (G - 1);  // lane within the group
+  const uint32_t gbase = lane - gl;    // first lane of the group in the wave
+  const uint32_t gi = lane / G;        // group within the wave
   const u64 cap = 1ull << A.log2c;
   const u64 mask = cap - 1;
-  const u64 max_windows = cap / G;       // plus one when the home is unaligned
+  const u64 max_windows = cap / G;     // plus one when the home is unaligned
+  uint8_t *wflag = dyn_lds + (OP == OP_FIND ? nwb * ROUND * 8 : 0) + wave * ROUND;
+  u64 *wout = (u64 *)dyn_lds + wave * ROUND;  // FIND only
 
   long long d_used = 0, d_live = 0;
   uint32_t err = 0;
 
-  u64 i = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  u64 k = 0, d = 1, base = 0, windows = 0, limit = 0;
-  uint32_t first = 0;
-  bool active = false;
+  const u64 nrounds = (A.n + ROUND - 1) / ROUND;
+  const u64 gw = (u64)blockIdx.x * nwb + wave;
+  const u64 nw = (u64)gridDim.x * nwb;
+  const bool flags8 = A.flags && (((uintptr_t)A.flags & 7) == 0);
+  const bool vals_vec = (OP == OP_FIND) && A.vals_out && (((uintptr_t)A.vals_out & 15) == 0);
 
-  // Takes operations from index i on until one needs probing (reserved keys
-  // are answered at once).
-  auto start = [&]() {
-    active = false;
-    while (i < A.n) {
-      k = load_key_in<LAYOUT>(A.keys, i);
-      if (k == kEmpty || k == kTomb) {
-        err |= kErrReserved;
-        if (gl == 0) {
-          if (A.flags) A.flags[i] = 0xFE;
-          if (OP == OP_FIND && A.vals_out) store_val_out<LAYOUT>(A.vals_out, i, 0);
+  for (u64 r = gw; r < nrounds; r += nw) {
+    const u64 rbase = r * ROUND;
+    const uint32_t cnt = (uint32_t)((A.n - rbase) < ROUND ? (A.n - rbase) : ROUND);
+    uint32_t j = 0;
+    u64 i = 0, k = 0, d = 1, base = 0, windows = 0, limit = 0;
+    uint32_t first = 0;
+    bool active = false;
+
+    // Takes the group's next operation of the round (reserved keys are
+    // answered at once).
+    auto start = [&]() {
+      active = false;
+      while (j < PER_GROUP) {
+        const uint32_t loc = gi + j * NGW;
+        if (loc >= cnt) {
+          j = PER_GROUP;
+          break;
         }
-        i += ngroups;
-        continue;
-      }
-      d = A.vals ? load_key_in<LAYOUT>(A.vals, i) : 1;
-      u64 h = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
-      base = h & ~(u64)(G - 1);
-      first = (uint32_t)(h & (G - 1));
-      windows = 0;
-      limit = max_windows + (first ? 1 : 0);
-      active = true;
-      return;
-    }
-  };
-
-  auto finish = [&](uint8_t flag, u64 v) {
-    if (gl == 0) {
-      if (A.flags) A.flags[i] = flag;
-      if (OP == OP_FIND && A.vals_out) store_val_out<LAYOUT>(A.vals_out, i, v);
-    }
-    i += ngroups;
-    start();
-  };
-
-  start();
-  while (__any(active)) {
-    if (active) {
-      const u64 idx = base + gl;
-      u64 ck, cv = 0;
-      if (LAYOUT == 0) {
-        u64 w = Cells<0>::word(A.cells, idx);
-        ck = Cells<0>::key_of(w);
-        cv = Cells<0>::val_of(w);
-      } else if (OP == OP_FIND) {
-        u64x2 c = Cells<1>::cell(A.cells, idx);
-        ck = c.x;
-        cv = c.y;
-      } else {
-        ck = Cells<1>::key(A.cells, idx);
-      }
-      bool done = false;
-      uint8_t flag = 0;
-      u64 outv = 0;
-      // Evaluate the window; a failed CAS updates the lane's key and the
-      // window is evaluated again from the next lane on.
-      while (true) {
-        const bool valid = gl >= first;
-        const uint32_t bh = group_bits<G>(__ballot(valid && ck == k), gbase);
-        const uint32_t be = group_bits<G>(__ballot(valid && ck == kEmpty), gbase);
-        const uint32_t ev = bh | be;
-        if (ev == 0) break;
-        const uint32_t j = __builtin_ctz(ev);
-        const uint32_t src = gbase + j;
-        if ((bh >> j) & 1u) {
-          // key present at lane j
-          if (OP == OP_FIND) {
-            outv = __shfl(cv, src, 64);
-            flag = 1;
-            done = true;
-          } else if (OP == OP_INSERT) {
-            flag = 0;
-            done = true;
-          } else if (OP == OP_UPSERT || OP == OP_UPDATE) {
-            if (gl == j) {
-              if (LAYOUT == 0) {
-                u64 *w = (u64 *)A.cells + idx;
-                if (UP == 1)
-                  add64(w, d << 32);
-                else
-                  store32((uint32_t *)w + 1, (uint32_t)d);
-              } else {
-                u64 *v = (u64 *)A.cells + 2 * idx + 1;
-                if (UP == 1)
-                  add64(v, d);
-                else
-                  store64(v, d);
-              }
-            }
-            flag = (OP == OP_UPDATE) ? 1 : 0;
-            done = true;
-          } else {  // OP_ERASE
-            u64 old = 0;
-            bool won = false;
-            if (gl == j) {
-              if (LAYOUT == 0) {
-                u64 w = ((u64)cv << 32) | k;
-                old = cas64((u64 *)A.cells + idx, w, (w & ~0xFFFFFFFFull) | kTomb);
-                won = (old == w);
-                if (!won) old &= 0xFFFFFFFFull;
-              } else {
-                old = cas64((u64 *)A.cells + 2 * idx, k, kTomb);
-                won = (old == k);
-              }
-              if (won) d_live -= 1;
-            }
-            won = __shfl((int)won, src, 64) != 0;
-            if (won) {
-              flag = 1;
-              done = true;
-            } else {
-              // another operation changed this cell first; look at what is there now
-              old = __shfl(old, src, 64);
-              if (gl == j) ck = old;
-              if (LAYOUT == 0 && gl == j && old == k) {
-                // only the value changed under us: reload the word and retry
-                u64 w = Cells<0>::word(A.cells, idx);
-                ck = Cells<0>::key_of(w);
-                cv = Cells<0>::val_of(w);
-              }
-              first = j;  // re-evaluate lane j with its new key
-              continue;
-            }
+        i = rbase + loc;
+        k = load_key_in<LAYOUT>(A.keys, i);
+        if (k == kEmpty || k == kTomb) {
+          err |= kErrReserved;
+          if (gl == 0) {
+            wflag[loc] = 0xFE;
+            if (OP == OP_FIND) wout[loc] = 0;
           }
+          ++j;
+          continue;
+        }
+        d = A.vals ? load_key_in<LAYOUT>(A.vals, i) : 1;
+        const u64 h = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
+        base = h & ~(u64)(G - 1);
+        first = (uint32_t)(h & (G - 1));
+        windows = 0;
+        limit = max_windows + (first ? 1 : 0);
+        active = true;
+        return;
+      }
+    };
+
+    auto finish = [&](uint8_t flag, u64 v) {
+      if (gl == 0) {
+        const uint32_t loc = gi + j * NGW;
+        wflag[loc] = flag;
+        if (OP == OP_FIND) wout[loc] = v;
+      }
+      ++j;
+      start();
+    };
+
+    start();
+    while (__any(active)) {
+      if (active) {
+        const u64 idx = base + gl;
+        u64 ck, cv = 0;
+        if (LAYOUT == 0) {
+          const u64 w = Cells<0>::word(A.cells, idx);
+          ck = Cells<0>::key_of(w);
+          cv = Cells<0>::val_of(w);
+        } else if (OP == OP_FIND) {
+          const u64x2 c = Cells<1>::cell(A.cells, idx);
+          ck = c.x;
+          cv = c.y;
         } else {
-          // empty cell at lane j: k is absent
-          if (OP == OP_FIND || OP == OP_UPDATE || OP == OP_ERASE) {
-            flag = 0;
-            outv = 0;
-            done = true;
-          } else {
-            u64 old = 0;
-            if (gl == j) {
-              if (LAYOUT == 0) {
-                old = cas64((u64 *)A.cells + idx, 0ull, (d << 32) | k);
-                if (old == 0) {
-                  d_used += 1;
-                  d_live += 1;
-                }
-              } else {
-                old = cas64((u64 *)A.cells + 2 * idx, kEmpty, k);
-                if (old == kEmpty) {
-                  u64 *v = (u64 *)A.cells + 2 * idx + 1;
-                  if (OP == OP_UPSERT && UP == 1)
-                    add64(v, d);  // concurrent increments of the same key also add
-                  else
-                    store64(v, d);
-                  d_used += 1;
-                  d_live += 1;
-                }
-              }
-            }
-            old = __shfl(old, src, 64);
-            const u64 okey = (LAYOUT == 0) ? (old & 0xFFFFFFFFull) : old;
-            if (old == 0) {
+          ck = Cells<1>::key(A.cells, idx);
+        }
+        bool done = false;
+        uint8_t flag = 0;
+        u64 outv = 0;
+        // Evaluate the window; a failed CAS updates the lane's key and the
+        // window is evaluated again from that lane on.
+        while (true) {
+          const bool valid = gl >= first;
+          const uint32_t bh = group_bits<G>(__ballot(valid && ck == k), gbase);
+          const uint32_t be = group_bits<G>(__ballot(valid && ck == kEmpty), gbase);
+          const uint32_t ev = bh | be;
+          if (ev == 0) break;
+          const uint32_t jl = __builtin_ctz(ev);
+          const uint32_t src = gbase + jl;
+          if ((bh >> jl) & 1u) {
+            // key present at lane jl
+            if (OP == OP_FIND) {
+              outv = __shfl(cv, src, 64);
               flag = 1;
               done = true;
-            } else if (okey == k) {
-              // lost the race to an insertion of the same key
-              if (OP == OP_UPSERT && gl == j) {
+            } else if (OP == OP_INSERT) {
+              flag = 0;
+              done = true;
+            } else if (OP == OP_UPSERT || OP == OP_UPDATE) {
+              if (gl == jl) {
                 if (LAYOUT == 0) {
                   u64 *w = (u64 *)A.cells + idx;
                   if (UP == 1)
                     add64(w, d << 32);
                   else
-                    store32((uint32_t *)w + 1, (uint32_t)d);
+                    put32((uint32_t *)w + 1, (uint32_t)d);
                 } else {
                   u64 *v = (u64 *)A.cells + 2 * idx + 1;
                   if (UP == 1)
                     add64(v, d);
                   else
-                    store64(v, d);
+                    put64(v, d);
                 }
               }
+              flag = (OP == OP_UPDATE) ? 1 : 0;
+              done = true;
+            } else {  // OP_ERASE
+              u64 old = 0;
+              bool won = false;
+              if (gl == jl) {
+                if (LAYOUT == 0) {
+                  const u64 w = ((u64)cv << 32) | k;
+                  old = cas64((u64 *)A.cells + idx, w, (w & ~0xFFFFFFFFull) | kTomb);
+                  won = (old == w);
+                  if (!won) old &= 0xFFFFFFFFull;
+                } else {
+                  old = cas64((u64 *)A.cells + 2 * idx, k, kTomb);
+                  won = (old == k);
+                }
+                if (won) d_live -= 1;
+              }
+              won = __shfl((int)won, src, 64) != 0;
+              if (won) {
+                flag = 1;
+                done = true;
+              } else {
+                // another operation changed this cell first; look at what is there now
+                old = __shfl(old, src, 64);
+                if (gl == jl) ck = old;
+                if (LAYOUT == 0 && gl == jl && old == k) {
+                  // only the value changed: reload the word and retry
+                  const u64 w = Cells<0>::word(A.cells, idx);
+                  ck = Cells<0>::key_of(w);
+                  cv = Cells<0>::val_of(w);
+                }
+                first = jl;
+                continue;
+              }
+            }
+          } else {
+            // empty cell at lane jl: k is absent
+            if (OP == OP_FIND || OP == OP_UPDATE || OP == OP_ERASE) {
               flag = 0;
+              outv = 0;
               done = true;
             } else {
-              // another key took the cell: revisit it with that key
-              if (gl == j) ck = okey;
-              first = j;
-              continue;
+              u64 old = 0;
+              if (gl == jl) {
+                if (LAYOUT == 0) {
+                  old = cas64((u64 *)A.cells + idx, 0ull, (d << 32) | k);
+                  if (old == 0) {
+                    d_used += 1;
+                    d_live += 1;
+                  }
+                } else {
+                  old = cas64((u64 *)A.cells + 2 * idx, kEmpty, k);
+                  if (old == kEmpty) {
+                    u64 *v = (u64 *)A.cells + 2 * idx + 1;
+                    if (OP == OP_UPSERT && UP == 1)
+                      add64(v, d);  // concurrent increments of the same key also add
+                    else
+                      put64(v, d);
+                    d_used += 1;
+                    d_live += 1;
+                  }
+                }
+              }
+              old = __shfl(old, src, 64);
+              const u64 okey = (LAYOUT == 0) ? (old & 0xFFFFFFFFull) : old;
+              if (old == 0) {
+                flag = 1;
+                done = true;
+              } else if (okey == k) {
+                // lost the race to an insertion of the same key
+                if (OP == OP_UPSERT && gl == jl) {
+                  if (LAYOUT == 0) {
+                    u64 *w = (u64 *)A.cells + idx;
+                    if (UP == 1)
+                      add64(w, d << 32);
+                    else
+                      put32((uint32_t *)w + 1, (uint32_t)d);
+                  } else {
+                    u64 *v = (u64 *)A.cells + 2 * idx + 1;
+                    if (UP == 1)
+                      add64(v, d);
+                    else
+                      put64(v, d);
+                  }
+                }
+                flag = 0;
+                done = true;
+              } else {
+                // another key took the cell: revisit it with that key
+                if (gl == jl) ck = okey;
+                first = jl;
+                continue;
+              }
             }
           }
+          break;
         }
-        break;
-      }
-      if (done) {
-        finish(flag, outv);
-      } else {
-        // next window
-        base = (base + G) & mask;
-        first = 0;
-        windows += 1;
-        if (windows >= limit) {
-          if (OP == OP_INSERT || OP == OP_UPSERT) {
-            err |= kErrFull;
-            finish(0xFF, 0);
-          } else {
-            finish(0, 0);
+        if (done) {
+          finish(flag, outv);
+        } else {
+          base = (base + G) & mask;
+          first = 0;
+          windows += 1;
+          if (windows >= limit) {
+            if (OP == OP_INSERT || OP == OP_UPSERT) {
+              err |= kErrFull;
+              finish(0xFF, 0);
+            } else {
+              finish(0, 0);
+            }
           }
         }
       }
     }
+    // write the round's results as whole lines
+    wave_sync();
+    if (A.flags) {
+      if (cnt == ROUND && flags8) {
+        if (lane < ROUND / 8)
+          ((u64 *)(A.flags + rbase))[lane] = ((const u64 *)wflag)[lane];
+      } else {
+        for (uint32_t t = lane; t < cnt; t += 64) A.flags[rbase + t] = wflag[t];
+      }
+    }
+    if (OP == OP_FIND && A.vals_out) {
+      if (cnt == ROUND && vals_vec) {
+        if (LAYOUT == 0) {
+          typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+          u32x2 v = {(uint32_t)wout[2 * lane], (uint32_t)wout[2 * lane + 1]};
+          ((u32x2 *)((uint32_t *)A.vals_out + rbase))[lane] = v;
+        } else {
+          u64x2 v = {wout[2 * lane], wout[2 * lane + 1]};
+          ((u64x2 *)((u64 *)A.vals_out + rbase))[lane] = v;
+        }
+      } else {
+        for (uint32_t t = lane; t < cnt; t += 64) store_val_out<LAYOUT>(A.vals_out, rbase + t, wout[t]);
+      }
+    }
+    wave_sync();
+  }
+  flush_counts(A.status, d_used, d_live, err, s_acc, &s_err);
+}
+
+// ---------------------------------------------------------------- aggregated insert-or-increment
+//
+// With the update function "add", the outcome of a bulk insertOrUpdate does
+// not depend on the order of its operations, so operations on equal keys can
+// be combined before they reach the table (the paper avoids contention on
+// skewed inputs by sorting, Sec. 5.5; here a workgroup combines in LDS).  A
+// workgroup takes chunks of AGG_CHUNK operations; equal keys of a chunk meet
+// in an LDS hash table and leave it as one upsert with the summed increment.
+// A key seen at least HOT_MIN times in one chunk moves to a second LDS table
+// that lives for the whole kernel and is written back once at the end, so the
+// hottest keys cost one global atomic per workgroup instead of one per
+// occurrence.  Each combined upsert is issued by a representative operation
+// (the first to claim the LDS slot); it carries the "inserted" flag, every
+// other operation of that key reports "updated".  Exactly one operation per
+// inserted key therefore reports true, as in the sequential table.
+//
+// The host only selects this kernel when the table cannot run out of empty
+// cells during the call, so no combined operation can fail with "full".
+
+constexpr int AGG_BLOCK = 256;
+constexpr int AGG_PER_THREAD = 4;
+constexpr int AGG_CHUNK = AGG_BLOCK * AGG_PER_THREAD;  // operations per chunk
+constexpr int AGG_SLOTS = 2 * AGG_CHUNK;              // LDS hash slots per chunk
+constexpr int HOT_SLOTS = 256;                        // kernel-lifetime hot keys
+constexpr int HOT_MAX = (HOT_SLOTS * 3) / 4;          // at most 3/4 full
+constexpr uint32_t HOT_MIN = 3;                       // promotion threshold
+
+// One insertOrUpdate(k, d, add) on the table by a single lane (Algorithm 1
+// with fetch-and-add as atomicUpdate).  Returns the flag.
+template <int LAYOUT>
+__device__ __forceinline__ uint8_t upsert_add_one(const BulkArgs &A, const uint32_t (*T)[256], u64 k,
+                                                  u64 d, long long &d_used, long long &d_live,
+                                                  uint32_t &err) {
+  const u64 cap = 1ull << A.log2c, mask = cap - 1;
+  u64 p = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
+  for (u64 probes = 0; probes < cap; ++probes, p = (p + 1) & mask) {
+    if (LAYOUT == 0) {
+      u64 *w = (u64 *)A.cells + p;
+      u64 ck = *w & 0xFFFFFFFFull;
+      if (ck == kEmpty) {
+        const u64 old = cas64(w, 0ull, (d << 32) | k);
+        if (old == 0) {
+          d_used += 1;
+          d_live += 1;
+          return 1;
+        }
+        ck = old & 0xFFFFFFFFull;
+      }
+      if (ck == k) {
+        add64(w, d << 32);
+        return 0;
+      }
+    } else {
+      u64 *kp = (u64 *)A.cells + 2 * p;
+      u64 ck = *kp;
+      if (ck == kEmpty) {
+        const u64 old = cas64(kp, kEmpty, k);
+        if (old == kEmpty) {
+          add64(kp + 1, d);
+          d_used += 1;
+          d_live += 1;
+          return 1;
+        }
+        ck = old;
+      }
+      if (ck == k) {
+        add64(kp + 1, d);
+        return 0;
+      }
+    }
+  }
+  err |= kErrFull;
+  return 0xFF;
+}
+
+template <int LAYOUT>
+__global__ void __launch_bounds__(AGG_BLOCK) k_upsert_add_agg(BulkArgs A) {
+  __shared__ uint32_t T[8][256];
+  __shared__ u64 s_key[AGG_SLOTS];
+  __shared__ u64 s_sum[AGG_SLOTS];
+  __shared__ uint32_t s_cnt[AGG_SLOTS];
+  __shared__ uint32_t s_rep[AGG_SLOTS];
+  __shared__ u64 h_key[HOT_SLOTS];
+  __shared__ u64 h_sum[HOT_SLOTS];
+  __shared__ u64 h_rep[HOT_SLOTS];
+  __shared__ uint32_t h_n;
+  __shared__ long long s_acc[2];
+  __shared__ uint32_t s_err;
+
+  crc_tables_build(T);
+  for (int s = threadIdx.x; s < AGG_SLOTS; s += AGG_BLOCK) {
+    s_key[s] = 0;
+    s_sum[s] = 0;
+    s_cnt[s] = 0;
+  }
+  for (int s = threadIdx.x; s < HOT_SLOTS; s += AGG_BLOCK) {
+    h_key[s] = 0;
+    h_sum[s] = 0;
+  }
+  if (threadIdx.x == 0) h_n = 0;
+  __syncthreads();
+
+  long long d_used = 0, d_live = 0;
+  uint32_t err = 0;
+  const u64 nchunks = (A.n + AGG_CHUNK - 1) / AGG_CHUNK;
+  for (u64 ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const u64 base = ch * AGG_CHUNK;
+    // combine equal keys of the chunk in LDS
+#pragma unroll
+    for (int j = 0; j < AGG_PER_THREAD; ++j) {
+      const uint32_t off = j * AGG_BLOCK + threadIdx.x;
+      const u64 i = base + off;
+      if (i >= A.n) continue;
+      const u64 k = load_key_in<LAYOUT>(A.keys, i);
+      if (k == kEmpty || k == kTomb) {
+        err |= kErrReserved;
+        if (A.flags) A.flags[i] = 0xFE;
+        continue;
+      }
+      const u64 d = A.vals ? load_key_in<LAYOUT>(A.vals, i) : 1;
+      const uint32_t hc = ((LAYOUT == 0) ? crc0_u32(T, (uint32_t)k) : crc0_u64(T, k)) ^ A.crc_lo;
+      uint32_t hs = (hc >> 11) & (HOT_SLOTS - 1);
+      bool hot = false;
+      for (int q = 0; q < HOT_SLOTS; ++q) {
+        const u64 hk = h_key[hs];
+        if (hk == k) {
+          hot = true;
+          break;
+        }
+        if (hk == 0) break;
+        hs = (hs + 1) & (HOT_SLOTS - 1);
+      }
+      if (hot) {
+        atomicAdd(&h_sum[hs], d);
+        if (A.flags) A.flags[i] = 0;
+        continue;
+      }
+      uint32_t s = hc & (AGG_SLOTS - 1);
+      bool rep = false;
+      while (true) {
+        const u64 old = atomicCAS(&s_key[s], 0ull, k);
+        if (old == 0) {
+          rep = true;
+          s_rep[s] = off;
+          break;
+        }
+        if (old == k) break;
+        s = (s + 1) & (AGG_SLOTS - 1);
+      }
+      atomicAdd(&s_sum[s], d);
+      atomicAdd(&s_cnt[s], 1u);
+      if (!rep && A.flags) A.flags[i] = 0;
+    }
+    __syncthreads();
+    // one upsert per distinct key of the chunk, or promotion to the hot table
+    for (int s = threadIdx.x; s < AGG_SLOTS; s += AGG_BLOCK) {
+      const u64 k = s_key[s];
+      if (k == 0) continue;
+      const u64 sum = s_sum[s];
+      const uint32_t cnt = s_cnt[s];
+      const u64 rep = base + s_rep[s];
+      s_key[s] = 0;
+      s_sum[s] = 0;
+      s_cnt[s] = 0;
+      bool promoted = false;
+      if (cnt >= HOT_MIN && atomicAdd(&h_n, 1u) < (uint32_t)HOT_MAX) {
+        const uint32_t hc = ((LAYOUT == 0) ? crc0_u32(T, (uint32_t)k) : crc0_u64(T, k)) ^ A.crc_lo;
+        uint32_t hs = (hc >> 11) & (HOT_SLOTS - 1);
+        while (atomicCAS(&h_key[hs], 0ull, k) != 0ull) hs = (hs + 1) & (HOT_SLOTS - 1);
+        h_sum[hs] = sum;
+        h_rep[hs] = rep;
+        promoted = true;
+      }
+      if (!promoted) {
+        const uint8_t f = upsert_add_one<LAYOUT>(A, T, k, sum, d_used, d_live, err);
+        if (A.flags) A.flags[rep] = f;
+      }
+    }
+    __syncthreads();
+  }
+  for (int hs = threadIdx.x; hs < HOT_SLOTS; hs += AGG_BLOCK) {
+    const u64 k = h_key[hs];
+    if (k == 0) continue;
+    const uint8_t f = upsert_add_one<LAYOUT>(A, T, k, h_sum[hs], d_used, d_live, err);
+    if (A.flags) A.flags[h_rep[hs]] = f;
   }
   flush_counts(A.status, d_used, d_live, err, s_acc, &s_err);
 }
@@ -536,8 +789,10 @@ static inline uint32_t grid_for(u64 work_items, const LaunchCfg &cfg) {
 
 template <int LAYOUT, int OP, int UP, int G>
 static hipError_t launch_g(const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
-  uint32_t grid = grid_for(a.n * (u64)G, cfg);
-  hipLaunchKernelGGL((k_bulk<LAYOUT, OP, UP, G>), dim3(grid), dim3(cfg.block_threads), 0, s, a);
+  const u64 nrounds = (a.n + ROUND - 1) / ROUND;
+  const uint32_t grid = grid_for(nrounds * 64, cfg);
+  const size_t lds = (size_t)(cfg.block_threads / 64) * bulk_lds_bytes_per_wave(OP);
+  hipLaunchKernelGGL((k_bulk<LAYOUT, OP, UP, G>), dim3(grid), dim3(cfg.block_threads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -569,6 +824,16 @@ static hipError_t launch_layout(OpKind op, const BulkArgs &a, const LaunchCfg &c
 
 hipError_t launch_bulk(OpKind op, const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
+  if (op == OP_UPSERT && a.up == 1 && a.aggregate) {
+    const u64 nchunks = (a.n + AGG_CHUNK - 1) / AGG_CHUNK;
+    u64 grid = (u64)cfg.num_cus * 2;  // LDS use allows two workgroups per CU
+    if (grid > nchunks) grid = nchunks;
+    if (a.layout == 0)
+      hipLaunchKernelGGL(k_upsert_add_agg<0>, dim3((uint32_t)grid), dim3(AGG_BLOCK), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_upsert_add_agg<1>, dim3((uint32_t)grid), dim3(AGG_BLOCK), 0, s, a);
+    return hipGetLastError();
+  }
   return a.layout == 0 ? launch_layout<0>(op, a, cfg, s) : launch_layout<1>(op, a, cfg, s);
 }
 

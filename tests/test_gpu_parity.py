@@ -122,16 +122,16 @@ def test_insert_with_duplicates_one_winner(layout, G):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("G", [1, 8])
+@pytest.mark.parametrize("G,agg", [(1, 0), (8, 0), (1, 1)])
 @pytest.mark.parametrize("s", [0.5, 1.0, 1.5])
-def test_upsert_add_zipf_histogram(layout, G, s):
+def test_upsert_add_zipf_histogram(layout, G, agg, s):
     m = 300_001
     keys = inputs.zipf_keys_u64(m, 1_000_000, s, seed=400 + int(10 * s)).astype(keys_dtype(layout))
     vals = (np.arange(m) % 7 + 1).astype(keys_dtype(layout))
     orc = oracle.OracleTable(layout, 20)
     of = orc.insert_or_update(keys, vals, oracle.ADD)
     t = make_table(layout, 20)
-    t.set_tuning(group_width=G)
+    t.set_tuning(group_width=G, aggregate=agg)
     gf = to_host(t.insert_or_update(to_dev(keys), to_dev(vals), op=oracle.ADD))
     assert np.array_equal(H.canonical_flags(keys, gf), of)
     assert t.count() == orc.counts()
@@ -139,15 +139,51 @@ def test_upsert_add_zipf_histogram(layout, G, s):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_upsert_increment_null_values(layout):
+@pytest.mark.parametrize("agg", [0, 1])
+def test_upsert_increment_null_values(layout, agg):
     rng = np.random.default_rng(12)
     keys = rng.integers(2, 5000, size=100_000).astype(keys_dtype(layout))
+    keys[::1000] = 1  # reserved keys among them
     orc = oracle.OracleTable(layout, 14)
     of = orc.insert_or_update(keys, None, oracle.ADD)
     t = make_table(layout, 14)
+    t.set_tuning(aggregate=agg)
     gf = to_host(t.insert_or_update(to_dev(keys), None, op=oracle.ADD))
     assert np.array_equal(H.canonical_flags(keys, gf), of)
+    from paper_1601_04017_amd import lpht
+    assert t.status() == lpht.ERR_RESERVED_KEY
     H.assert_same_table_modulo_run_order(cells_host(t), orc.cells(), layout)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_upsert_add_hot_table_overflow(layout):
+    # every key repeats in every chunk: more hot keys than a workgroup keeps
+    rng = np.random.default_rng(14)
+    keys = rng.integers(2, 260, size=2_000_000).astype(keys_dtype(layout))
+    vals = rng.integers(0, 1 << 20, size=keys.size).astype(keys_dtype(layout))
+    orc = oracle.OracleTable(layout, 12)
+    of = orc.insert_or_update(keys, vals, oracle.ADD)
+    t = make_table(layout, 12)
+    gf = to_host(t.insert_or_update(to_dev(keys), to_dev(vals), op=oracle.ADD))
+    assert np.array_equal(H.canonical_flags(keys, gf), of)
+    H.assert_same_table_modulo_run_order(cells_host(t), orc.cells(), layout)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_upsert_add_bounded_near_full_falls_back(layout):
+    # a bounded table that may fill up: combining is not used, and operations
+    # on keys that find no empty cell all report "full"
+    keys = _keys(layout, 70, 21)
+    keys = np.concatenate([keys, keys[::-1]])
+    orc = oracle.OracleTable(layout, 6)
+    of = orc.insert_or_update(keys, None, oracle.ADD)
+    t = make_table(layout, 6)
+    gf = to_host(t.insert_or_update(to_dev(keys), None, op=oracle.ADD))
+    assert (gf == 1).sum() == (of == 1).sum() == 64
+    # every key that did not get a cell reports full on all its operations
+    d = H.live_dict(cells_host(t), layout)
+    for k, f in zip(keys.tolist(), gf.tolist()):
+        assert (f == 0xFF) == (k not in d)
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
