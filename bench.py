@@ -59,6 +59,28 @@ def algorithmic_bytes_per_op(alpha):
     }
 
 
+OP_CODE = {"insert": 1, "find_hit": 0, "find_miss": 0}
+
+
+def measured_traffic(phase, group_width):
+    """HBM bytes per launch of the phase's kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the
+    summary is missing or was taken with a different kernel source."""
+    from paper_1601_04017_amd import profsum
+
+    path = os.path.join(ROOT, "profiles", "k_bulk_kv64_headline_step.traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha") != profsum.kernel_source_sha():
+        return None
+    name = f"k_bulk<1, {OP_CODE[phase]}, 0, {group_width}>"
+    k = rec.get("per_kernel", {}).get(name)
+    if k is None:
+        return None
+    return round(k["read_bytes"] + k["write_bytes"])
+
+
 def cpu_baseline(keys, fkeys_hit, fkeys_miss, zipf, budget_s=25.0):
     """The oracle, single-threaded, on a bounded sample of the same workload:
     the first n keys of each stream into a 2^25-cell table (same fill as
@@ -86,6 +108,154 @@ def cpu_baseline(keys, fkeys_hit, fkeys_miss, zipf, budget_s=25.0):
     }
 
 
+def _timed(fn, stream):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b)
+
+
+def run_suite(dev, reps=3):
+    """The other workloads, each timed on the GPU (mean of `reps` after one
+    warm-up): packed 2^21 table; the fill sweep of the 2^28 table; growing
+    from 4096 cells in batches of 2^20; Zipf insert-or-increment presized and
+    growing for s in {0.5, 1, 1.25, 1.5}; and the measured memory ceilings."""
+    import torch
+
+    from paper_1601_04017_amd import inputs, lpht, roofline
+
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def up(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int64 if a.dtype == np.uint64 else np.int32)).to(dev)
+
+    log("suite: ceilings")
+    out["ceilings"] = roofline.measure()
+
+    # packed 2^21 cells: 2^20 inserts, 2^20 finds (half absent)
+    log("suite: packed32 2^21")
+    n = 1 << 20
+    k = inputs.distinct_keys_u32(n, 101)
+    absent = inputs.distinct_keys_u32(n // 2, 101, absent=True)
+    present = k[inputs.permutation(n, 102)[: n // 2]]
+    fk, _ = inputs.shuffled_mix(present, absent, 103)
+    dk, dv, dfk = up(k), up(np.arange(n, dtype=np.uint32)), up(fk)
+    t = lpht.Table(layout=lpht.PACKED32, log2_capacity=21)
+    res = []
+    for r in range(reps + 1):
+        t.clear()
+        ti = _timed(lambda: t.insert(dk, dv, flags=False), stream)
+        tf = _timed(lambda: t.find(dfk), stream)
+        if r:
+            res.append((ti, tf))
+    ti, tf = np.mean(res, axis=0)
+    out["packed32_2e21"] = {"insert_ms": round(ti, 4), "find_ms": round(tf, 4),
+                            "insert_mops": round(n / ti / 1e3, 1), "find_mops": round(n / tf / 1e3, 1)}
+    t.close()
+    del dk, dv, dfk
+
+    # fill sweep on 2^28 cells of 16 bytes
+    log("suite: fill sweep")
+    sweep = {}
+    nmax = 201_326_592
+    keys = inputs.distinct_keys_u64(nmax, 201)
+    miss = inputs.distinct_keys_u64(10 ** 8, 201, absent=True)
+    dkeys, dmiss = up(keys), up(miss)
+    dvals = torch.arange(nmax, dtype=torch.int64, device=dev)
+    t = lpht.Table(layout=lpht.KV64, log2_capacity=28)
+    outv = torch.empty(10 ** 8, dtype=torch.int64, device=dev)
+    outf = torch.empty(10 ** 8, dtype=torch.uint8, device=dev)
+    for nn in (67_108_864, 10 ** 8, 134_217_728, 201_326_592):
+        hit = dkeys[torch.randperm(nn, device=dev)[: 10 ** 8] if nn >= 10 ** 8 else
+                    torch.randint(0, nn, (10 ** 8,), device=dev)]
+        res = []
+        for r in range(reps + 1):
+            t.clear()
+            ti = _timed(lambda: t.insert(dkeys[:nn], dvals[:nn], flags=False), stream)
+            th = _timed(lambda: t.find(hit, outv, outf), stream)
+            tm = _timed(lambda: t.find(dmiss, outv, outf), stream)
+            if r:
+                res.append((ti, th, tm))
+        ti, th, tm = np.mean(res, axis=0)
+        sweep[f"{nn / (1 << 28):.4f}"] = {"n": nn, "insert_ms": round(ti, 3), "find_hit_ms": round(th, 3),
+                                           "find_miss_ms": round(tm, 3),
+                                           "insert_mops": round(nn / ti / 1e3, 1),
+                                           "find_hit_mops": round(1e8 / th / 1e3, 1),
+                                           "find_miss_mops": round(1e8 / tm / 1e3, 1)}
+        del hit
+    out["fill_sweep_2e28"] = sweep
+    t.close()
+    del dmiss, outv, outf
+
+    # growing from 4096 cells, 10^8 keys in batches of 2^20
+    log("suite: growing")
+    b = 1 << 20
+    res = []
+    for r in range(reps + 1):
+        t = lpht.Table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+        t.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lo in range(0, N_OPS, b):
+            hi = min(N_OPS, lo + b)
+            t.insert(dkeys[lo:hi], dvals[lo:hi], flags=False)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) * 1e3
+        st = t.stats()
+        if r:
+            res.append((el, st["migrate_ms"], st["migrations"], st["resizes"], t.log2_capacity))
+        assert t.count() == (N_OPS, N_OPS)
+        t.close()
+    el, mig, nmig, nres, lg = np.mean(res, axis=0)
+    out["growing_from_4096"] = {"total_ms": round(el, 3), "migrate_ms": round(mig, 3),
+                                "insert_ms_excl_migration": round(el - mig, 3),
+                                "mops": round(N_OPS / el / 1e3, 1), "data_migrations": int(nmig),
+                                "resizes": int(nres), "final_log2_capacity": int(lg)}
+    del dkeys, dvals
+
+    # Zipf insert-or-increment, presized 2^28 and growing from 4096
+    zres = {}
+    for sx in (0.5, 1.0, 1.25, 1.5):
+        log(f"suite: zipf s={sx}")
+        z = up(inputs.zipf_keys_u64(N_OPS, ZIPF_N, sx, seed=400 + int(sx * 4)))
+        t = lpht.Table(layout=lpht.KV64, log2_capacity=28)
+        res = []
+        for r in range(reps + 1):
+            t.clear()
+            tp = _timed(lambda: t.insert_or_update(z, None, op=lpht.ADD, flags=False), stream)
+            if r:
+                res.append(tp)
+        distinct = t.count()[1]
+        t.close()
+        gres = []
+        for r in range(2):
+            g = lpht.Table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+            g.set_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for lo in range(0, N_OPS, b):
+                g.insert_or_update(z[lo:lo + b], None, op=lpht.ADD, flags=False)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) * 1e3
+            st = g.stats()
+            if r:
+                gres.append((el, st["migrate_ms"], g.log2_capacity))
+            assert g.count()[1] == distinct
+            g.close()
+        zres[str(sx)] = {"presized_ms": round(float(np.mean(res)), 3),
+                         "presized_mops": round(N_OPS / np.mean(res) / 1e3, 1),
+                         "growing_ms": round(gres[0][0], 3), "growing_migrate_ms": round(gres[0][1], 3),
+                         "growing_mops": round(N_OPS / gres[0][0] / 1e3, 1),
+                         "growing_final_log2_capacity": int(gres[0][2]), "distinct": int(distinct)}
+        del z
+    out["zipf_increment"] = zres
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +264,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--group-width", type=int, default=None)
     ap.add_argument("--aggregate", type=int, default=None)
+    ap.add_argument("--suite", action="store_true", help="also measure the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (tables shard by hash "
@@ -198,12 +369,13 @@ def main():
     dominant = max(("insert", "find_hit", "find_miss"), key=lambda p: ph_ms[p])
     roofline = {
         "bound": "hbm",
-        "kernel": f"k_bulk<KV64,{dominant}>",
+        "kernel": f"k_bulk<KV64,{dominant},G={t1.get_tuning()['group_width']}>",
         "achieved": round(ach[dominant], 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(ach[dominant] / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dominant, t1.get_tuning()["group_width"]),
+        "algorithmic_bytes_per_launch": round(bpo[dominant] * N_OPS),
     }
 
     out = {
@@ -235,6 +407,11 @@ def main():
         "phase_gbs_algorithmic": {k: round(v, 1) for k, v in ach.items()},
         "roofline": roofline,
     }
+    if args.suite:
+        del d_keys, d_vals, d_hit, d_miss, d_zipf, d_out, d_flags, d_found
+        t1.close()
+        t2.close()
+        out["suite"] = run_suite(dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 thread)")
         out["cpu_baseline"] = cpu_baseline(keys, hit, miss, zipf)

@@ -32,8 +32,9 @@
  *   reserved key, LPHT_FLAG_FULL (0xFF) when a bounded table had no empty cell
  *   left for an inserting operation (sticky error LPHT_ERR_FULL).
  * - The table's cells and its status block are owned by the library and
- *   allocated through the configured allocator (default: stream-ordered
- *   hipMallocAsync / hipFreeAsync on the call's stream).
+ *   allocated through the configured allocator (default: the library's own
+ *   stream-ordered memory pool on the table's device, which keeps freed
+ *   memory for reuse until the process ends).
  */
 #ifndef LPHT_H
 #define LPHT_H
@@ -82,7 +83,8 @@ extern "C" {
 
 /* Allocator hook: returns device memory of `bytes` bytes (256-byte aligned)
  * usable in stream order on `stream`, or NULL.  `free` releases it in stream
- * order.  Both NULL selects hipMallocAsync / hipFreeAsync. */
+ * order.  Both NULL selects the library's pool (hipMallocFromPoolAsync /
+ * hipFreeAsync on a per-device pool that never releases memory). */
 typedef void *(*lpht_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*lpht_free_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
 

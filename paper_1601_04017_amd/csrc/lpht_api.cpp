@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -61,10 +62,38 @@ int from_hip(hipError_t e) {
 
 uint64_t cell_bytes(uint32_t layout) { return layout == LPHT_PACKED32 ? 8u : 16u; }
 
+// The library's own stream-ordered memory pool per device.  It keeps freed
+// memory mapped (release threshold: never), so that the repeated growth of
+// a table reuses pages instead of mapping new ones; the paper uses a
+// user-space memory pool for the same reason (Sec. 7).
+constexpr int kMaxDevices = 64;
+std::mutex g_pool_mu;
+hipMemPool_t g_pools[kMaxDevices];
+
+hipMemPool_t device_pool(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (!g_pools[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) return nullptr;
+    uint64_t keep = ~0ull;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    g_pools[dev] = pool;
+  }
+  return g_pools[dev];
+}
+
 void *dev_alloc(lpht_table *t, size_t bytes, hipStream_t s) {
   if (t->cfg.alloc) return t->cfg.alloc(bytes, (void *)s, t->cfg.alloc_ctx);
+  hipMemPool_t pool = device_pool(t->device);
+  if (!pool) return nullptr;
   void *p = nullptr;
-  if (hipMallocAsync(&p, bytes, s) != hipSuccess) return nullptr;
+  if (hipMallocFromPoolAsync(&p, bytes, pool, s) != hipSuccess) return nullptr;
   return p;
 }
 
@@ -317,7 +346,7 @@ int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out) {
   t->tuning.block_threads = 256;
   t->tuning.group_width = 1;
   t->tuning.blocks_per_cu = 8;
-  t->tuning.migrate_block = 4096;
+  t->tuning.migrate_block = 512;
   t->tuning.aggregate = 1;
   fill_launch(t);
   const int kb = cfg->layout == LPHT_PACKED32 ? 4 : 8;

@@ -695,8 +695,24 @@ __global__ void k_set_status(DevStatus *st, u64 used, u64 live, int clear_err) {
     st->used = used;
     st->live = live;
     st->moved = 0;
+    st->aux[0] = 0;  // migration overflow flag
     if (clear_err) st->err = 0;
   }
+}
+
+// Zeroes `n16` 16-byte units when the migration overflow flag is set (and
+// then also resets the counts the interrupted migration added); otherwise
+// returns at once.
+__global__ void k_fill_zero_if(u64x2 *p, u64 n16, DevStatus *st) {
+  if (st->aux[0] == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->used = 0;
+    st->live = 0;
+  }
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  const u64x2 z = {0ull, 0ull};
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    __builtin_nontemporal_store(z, p + i);
 }
 
 template <int LAYOUT>
@@ -726,10 +742,14 @@ template <int LAYOUT>
 __global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, uint32_t log2_old,
                                                         void *new_cells, uint32_t log2_new,
                                                         uint32_t crc_hi, uint32_t crc_lo,
-                                                        int old_is_full, DevStatus *st) {
+                                                        int old_is_full, int guarded,
+                                                        DevStatus *st) {
   __shared__ uint32_t T[8][256];
   __shared__ long long s_acc[2];
   __shared__ uint32_t s_err;
+  // as the fallback of the LDS-staged migration it runs only when that one
+  // reported a cluster longer than its halo
+  if (guarded && st->aux[0] == 0) return;
   crc_tables_build(T);
   const u64 cap = 1ull << log2_old, mask = cap - 1;
   const u64 nmask = (1ull << log2_new) - 1;
@@ -773,6 +793,148 @@ __global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, u
       }
       moved += 1;
     }
+  }
+  flush_counts(st, moved, moved, 0, s_acc, &s_err);
+}
+
+// LDS-staged block migration with owner writes (Sec. 5.3.1).  Workgroup w
+// owns old block [d, d+B) and writes new cells [g*d, g*(d+B)) exactly once,
+// empty cells included, so the new table needs no separate initialisation.
+// By Lemma 1 only clusters that overlap the block send elements into that
+// range: the one that may start before d (up to MIG_HALO cells back) and the
+// ones starting inside the block (the last may run up to MIG_HALO cells past
+// it).  The workgroup stages old cells [d - H, d + B + H) in LDS, re-inserts
+// every overlapping cluster in old-array order into an LDS image of the new
+// range [g*a0, g*(b_last + 1)), and streams the owned part of the image out.
+// Elements of the last cluster that land past the owned range are written by
+// the next workgroup, which sees that cluster as its incoming one; the first
+// block's incoming cluster is the one that wraps around the table end.
+// Positions are kept unwrapped (old cell x may be negative for block 0).
+// A cluster longer than the halo (or a table without empty cells) sets the
+// overflow flag; the guarded simple migration then redoes the whole move.
+constexpr int MIG_HALO = 128;
+
+__host__ __device__ constexpr uint32_t mig_window(uint32_t mb) { return mb + 2 * MIG_HALO; }
+
+__host__ __device__ constexpr size_t mig_lds_bytes(uint32_t mb, uint32_t layout, uint32_t gamma) {
+  return (size_t)mig_window(mb) * (layout == 0 ? 8u : 16u) * (1 + gamma);
+}
+
+template <int LAYOUT>
+__global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint32_t log2_old,
+                                                     void *new_cells, uint32_t g, uint32_t crc_hi,
+                                                     uint32_t crc_lo, uint32_t mb, DevStatus *st) {
+  __shared__ uint32_t T[8][256];
+  __shared__ long long s_acc[2];
+  __shared__ uint32_t s_err;
+  __shared__ int s_last_empty, s_first_empty;
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
+  crc_tables_build(T);
+
+  const int H = MIG_HALO;
+  const uint32_t W = mig_window(mb);
+  const uint32_t gamma = 1u << g;
+  const uint32_t IW = gamma * W;  // image cells
+  // old window and image: key and value arrays (KV64) or words (PACKED32)
+  u64 *okey = (u64 *)dyn_lds;
+  u64 *oval = okey + W;                              // KV64 only
+  u64 *ikey = (LAYOUT == 0) ? okey + W : okey + 2 * W;
+  u64 *ival = ikey + IW;                             // KV64 only
+  auto key_o = [&](int t) -> u64 { return LAYOUT == 0 ? (okey[t] & 0xFFFFFFFFull) : okey[t]; };
+  auto key_i = [&](uint32_t t) -> u64 { return LAYOUT == 0 ? (ikey[t] & 0xFFFFFFFFull) : ikey[t]; };
+
+  const u64 cap = 1ull << log2_old, mask = cap - 1;
+  const uint32_t log2_new = log2_old + g;
+  const u64 nblocks = cap / mb;
+  long long moved = 0;
+
+  for (u64 blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const long long d = (long long)(blk * mb);
+    if (threadIdx.x == 0) {
+      s_last_empty = -1;
+      s_first_empty = 0x7FFFFFFF;
+    }
+    for (uint32_t t = threadIdx.x; t < W; t += blockDim.x) {
+      const u64 x = (u64)(d - H + (long long)t) & mask;
+      if (LAYOUT == 0) {
+        okey[t] = ((const u64 *)old_cells)[x];
+      } else {
+        const u64x2 c = ((const u64x2 *)old_cells)[x];
+        okey[t] = c.x;
+        oval[t] = c.y;
+      }
+    }
+    for (uint32_t t = threadIdx.x; t < IW; t += blockDim.x) {
+      ikey[t] = 0;
+      if (LAYOUT == 1) ival[t] = 0;
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < W; t += blockDim.x) {
+      if (key_o(t) != kEmpty) continue;
+      if ((int)t < H) atomicMax(&s_last_empty, (int)t);
+      if ((int)t >= H + (int)mb) atomicMin(&s_first_empty, (int)t);
+    }
+    __syncthreads();
+    // window indices [lo, hi) of the clusters that overlap the block
+    bool overflow = false;
+    int lo = H, hi = H + (int)mb;
+    if (key_o(H - 1) != kEmpty && key_o(H) != kEmpty) {
+      if (s_last_empty < 0) overflow = true;
+      lo = s_last_empty + 1;
+    }
+    if (key_o(H + mb - 1) != kEmpty) {
+      if (s_first_empty == 0x7FFFFFFF) overflow = true;
+      hi = s_first_empty;
+    }
+    if (overflow) {
+      if (threadIdx.x == 0) atomicOr((unsigned long long *)&st->aux[0], 1ull);
+      __syncthreads();
+      continue;
+    }
+    const long long ib = (long long)gamma * (d - H + lo);  // image base (unwrapped new index)
+    bool bad = false;
+    for (int t = lo + (int)threadIdx.x; t < hi; t += (int)blockDim.x) {
+      if (key_o(t) == kEmpty || key_o(t - 1) != kEmpty) continue;  // not a cluster start
+      for (int u = t; u < hi; ++u) {
+        const u64 k = key_o(u);
+        if (k == kEmpty) break;
+        if (k == kTomb) continue;
+        const u64 v = (LAYOUT == 0) ? (okey[u] >> 32) : oval[u];
+        const long long x = d - H + u;  // unwrapped old position
+        const u64 hn = home_of<LAYOUT>(T, k, crc_hi, crc_lo, log2_new);
+        const u64 oh = hn >> g;  // home in the old table
+        const u64 delta = ((u64)x - oh) & mask;
+        const long long nh = (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
+        long long p = nh - ib;
+        while (p < (long long)IW && key_i((uint32_t)p) != kEmpty) ++p;
+        if (p < 0 || p >= (long long)IW) {
+          bad = true;
+          break;
+        }
+        if (LAYOUT == 0) {
+          ikey[p] = okey[u];
+        } else {
+          ikey[p] = k;
+          ival[p] = v;
+        }
+      }
+    }
+    if (bad) atomicOr((unsigned long long *)&st->aux[0], 1ull);
+    __syncthreads();
+    const uint32_t off = gamma * (uint32_t)(H - lo);
+    const u64 dst0 = (u64)d * gamma;
+    for (uint32_t t = threadIdx.x; t < gamma * mb; t += blockDim.x) {
+      if (LAYOUT == 0) {
+        const u64 w = ikey[off + t];
+        ((u64 *)new_cells)[dst0 + t] = w;
+        moved += (w != 0);
+      } else {
+        const u64x2 c = {ikey[off + t], ival[off + t]};
+        ((u64x2 *)new_cells)[dst0 + t] = c;
+        moved += (c.x != kEmpty);
+      }
+    }
+    __syncthreads();
   }
   flush_counts(st, moved, moved, 0, s_acc, &s_err);
 }
@@ -865,19 +1027,47 @@ hipError_t launch_recount(const void *cells, uint32_t log2c, uint32_t layout, De
 hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_cells,
                           uint32_t log2_new, uint32_t layout, uint32_t crc_hi, uint32_t crc_lo,
                           int old_is_full, DevStatus *st, const LaunchCfg &cfg, hipStream_t s) {
+  const u64 cap = 1ull << log2_old;
   const u64 new_bytes = (1ull << log2_new) * (layout == 0 ? 8ull : 16ull);
-  hipError_t e = launch_fill_zero(new_cells, new_bytes, cfg, s);
-  if (e != hipSuccess) return e;
-  u64 cap = 1ull << log2_old;
-  LaunchCfg c2 = cfg;
-  c2.block_threads = 256;
-  uint32_t grid = grid_for(cap, c2);
+  const uint32_t g = log2_new - log2_old;
+  const uint32_t mb = cfg.migrate_block;
+  // static LDS of the kernel (CRC tables and counters) plus the staged window
+  // and image must fit the 64 KiB a workgroup may allocate
+  const size_t lds_total = (g <= 1) ? mig_lds_bytes(mb, layout, 1u << g) + 8192 + 64 : ~(size_t)0;
+  const bool lds_path = !old_is_full && g <= 1 && mb >= 256 && cap >= mb && lds_total <= 65536;
+  const uint32_t sgrid = grid_for(cap, LaunchCfg{256, 1, cfg.blocks_per_cu, cfg.num_cus, mb, 0});
+  if (lds_path) {
+    const size_t lds = mig_lds_bytes(mb, layout, 1u << g);
+    u64 nblocks = cap / mb;
+    u64 per_cu = (160 * 1024) / lds_total;
+    if (per_cu < 1) per_cu = 1;
+    u64 grid = (u64)cfg.num_cus * per_cu;
+    if (grid > nblocks) grid = nblocks;
+    if (layout == 0)
+      hipLaunchKernelGGL(k_migrate_lds<0>, dim3((uint32_t)grid), dim3(256), lds, s, old_cells, log2_old,
+                         new_cells, g, crc_hi, crc_lo, mb, st);
+    else
+      hipLaunchKernelGGL(k_migrate_lds<1>, dim3((uint32_t)grid), dim3(256), lds, s, old_cells, log2_old,
+                         new_cells, g, crc_hi, crc_lo, mb, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // fallback, a no-op unless a workgroup reported overflow
+    const u64 n16 = new_bytes / 16;
+    hipLaunchKernelGGL(k_fill_zero_if, dim3(grid_for(n16, cfg)), dim3(cfg.block_threads), 0, s,
+                       (u64x2 *)new_cells, n16, st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else {
+    hipError_t e = launch_fill_zero(new_cells, new_bytes, cfg, s);
+    if (e != hipSuccess) return e;
+  }
+  const int guarded = lds_path ? 1 : 0;
   if (layout == 0)
-    hipLaunchKernelGGL(k_migrate_simple<0>, dim3(grid), dim3(256), 0, s, old_cells, log2_old,
-                       new_cells, log2_new, crc_hi, crc_lo, old_is_full, st);
+    hipLaunchKernelGGL(k_migrate_simple<0>, dim3(sgrid), dim3(256), 0, s, old_cells, log2_old,
+                       new_cells, log2_new, crc_hi, crc_lo, old_is_full, guarded, st);
   else
-    hipLaunchKernelGGL(k_migrate_simple<1>, dim3(grid), dim3(256), 0, s, old_cells, log2_old,
-                       new_cells, log2_new, crc_hi, crc_lo, old_is_full, st);
+    hipLaunchKernelGGL(k_migrate_simple<1>, dim3(sgrid), dim3(256), 0, s, old_cells, log2_old,
+                       new_cells, log2_new, crc_hi, crc_lo, old_is_full, guarded, st);
   return hipGetLastError();
 }
 

@@ -276,7 +276,7 @@ class Table:
     def status(self, stream=None) -> int:
         return load().lpht_status(self._h, _stream_handle(stream))
 
-    def set_tuning(self, block_threads=256, group_width=1, blocks_per_cu=8, migrate_block=4096,
+    def set_tuning(self, block_threads=256, group_width=1, blocks_per_cu=8, migrate_block=512,
                    aggregate=1):
         t = lpht_tuning(block_threads, group_width, blocks_per_cu, migrate_block, aggregate)
         _check(load().lpht_set_tuning(self._h, ctypes.byref(t)), "lpht_set_tuning")

@@ -301,7 +301,8 @@ def test_bounded_table_full(layout, G):
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("gamma_log", [0, 1, 2])
 @pytest.mark.parametrize("fill,erase_frac", [(0.45, 0.0), (0.5, 0.3), (0.8, 0.1)])
-def test_migration_matches_oracle_cell_for_cell(layout, gamma_log, fill, erase_frac):
+@pytest.mark.parametrize("mb", [256, 512, 1024])
+def test_migration_matches_oracle_cell_for_cell(layout, gamma_log, fill, erase_frac, mb):
     log2c = 16
     n = int(fill * (1 << log2c))
     keys = _keys(layout, n, 91)
@@ -312,6 +313,7 @@ def test_migration_matches_oracle_cell_for_cell(layout, gamma_log, fill, erase_f
         orc.erase(keys[rng.random(n) < erase_frac])
     old = orc.cells()
     t = make_table(layout, log2c)
+    t.set_tuning(migrate_block=mb)
     t.import_cells(to_dev(old), log2c)
     assert t.count() == orc.counts()
     t.grow(log2c + gamma_log)
@@ -341,6 +343,63 @@ def test_migration_wraparound_and_full_table(layout):
             t.grow(log2c + gl)
             o2.grow(log2c + gl)
             assert np.array_equal(cells_host(t), o2.cells()), (ks.size, gl)
+
+
+def _keys_with_home(layout, log2c, home, count, start=2):
+    kb = 4 if layout == oracle.PACKED32 else 8
+    out = []
+    lo = start
+    while len(out) < count:
+        cand = np.arange(lo, lo + 2_000_000, dtype=np.uint64)
+        hm = (oracle.hash_bulk(cand, kb) >> np.uint64(64 - log2c)).astype(np.int64)
+        out.extend(cand[hm == home].tolist())
+        lo += 2_000_000
+    return np.array(out[:count], dtype=keys_dtype(layout))
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("home", [100, 4095])
+def test_migration_long_cluster_falls_back(layout, home):
+    # one cluster of 300 cells, longer than the staging halo, plus random
+    # keys; the wrapped variant starts at the last cell
+    log2c = 12
+    keys = np.concatenate([_keys_with_home(layout, log2c, home, 300), _keys(layout, 1200, 61)])
+    orc = oracle.OracleTable(layout, log2c)
+    orc.insert(keys, _vals(layout, keys.size, 9))
+    old = orc.cells()
+    for gl in (0, 1):
+        for mb in (256, 512):
+            t = make_table(layout, log2c)
+            t.set_tuning(migrate_block=mb)
+            t.import_cells(to_dev(old), log2c)
+            o2 = oracle.OracleTable(layout, log2c)
+            o2.load_cells(old, log2c)
+            t.grow(log2c + gl)
+            o2.grow(log2c + gl)
+            assert np.array_equal(cells_host(t), o2.cells()), (gl, mb)
+            assert t.count() == o2.counts()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("log2c", [8, 9, 10])
+@pytest.mark.parametrize("gamma_log", [0, 1])
+def test_migration_small_tables_window_wraps(layout, log2c, gamma_log):
+    # tables of one to four staging blocks: the staged window covers cells
+    # twice and the wrapping cluster is seen as incoming and outgoing
+    for seed, fill in ((71, 0.5), (72, 0.7), (73, 0.3)):
+        n = int(fill * (1 << log2c))
+        keys = np.concatenate([_keys_with_home(layout, log2c, (1 << log2c) - 2, 6), _keys(layout, n, seed)])
+        orc = oracle.OracleTable(layout, log2c)
+        orc.insert(keys, _vals(layout, keys.size, 3))
+        orc.erase(keys[::7])
+        old = orc.cells()
+        t = make_table(layout, log2c)
+        t.set_tuning(migrate_block=256)
+        t.import_cells(to_dev(old), log2c)
+        t.grow(log2c + gamma_log)
+        orc.grow(log2c + gamma_log)
+        assert np.array_equal(cells_host(t), orc.cells()), (seed, fill)
+        assert t.count() == orc.counts()
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
