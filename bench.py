@@ -118,7 +118,10 @@ def _timed(fn, stream):
     return a.elapsed_time(b)
 
 
-def run_suite(dev, reps=3):
+SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "zipf")
+
+
+def run_suite(dev, reps=3, parts=SUITE_PARTS):
     """The other workloads, each timed on the GPU (mean of `reps` after one
     warm-up): packed 2^21 table; the fill sweep of the 2^28 table; growing
     from 4096 cells in batches of 2^20; Zipf insert-or-increment presized and
@@ -133,8 +136,33 @@ def run_suite(dev, reps=3):
     def up(a):
         return torch.from_numpy(np.ascontiguousarray(a).view(np.int64 if a.dtype == np.uint64 else np.int32)).to(dev)
 
-    log("suite: ceilings")
-    out["ceilings"] = roofline.measure()
+    if "ceilings" in parts:
+        log("suite: ceilings")
+        out["ceilings"] = roofline.measure()
+    if "packed32" in parts:
+        out["packed32_2e21"] = _suite_packed32(dev, up, stream, reps)
+    need_keys = "fill_sweep" in parts or "growing" in parts
+    if need_keys:
+        nmax = 201_326_592
+        keys = inputs.distinct_keys_u64(nmax, 201)
+        dkeys = up(keys)
+        dvals = torch.arange(nmax, dtype=torch.int64, device=dev)
+        del keys
+    if "fill_sweep" in parts:
+        out["fill_sweep_2e28"] = _suite_fill_sweep(dev, up, stream, reps, dkeys, dvals)
+    if "growing" in parts:
+        out["growing_from_4096"] = _suite_growing(stream, reps, dkeys, dvals)
+    if need_keys:
+        del dkeys, dvals
+    if "zipf" in parts:
+        out["zipf_increment"] = _suite_zipf(up, stream, reps)
+    return out
+
+
+def _suite_packed32(dev, up, stream, reps):
+    import torch  # noqa: F401
+
+    from paper_1601_04017_amd import inputs, lpht
 
     # packed 2^21 cells: 2^20 inserts, 2^20 finds (half absent)
     log("suite: packed32 2^21")
@@ -153,19 +181,20 @@ def run_suite(dev, reps=3):
         if r:
             res.append((ti, tf))
     ti, tf = np.mean(res, axis=0)
-    out["packed32_2e21"] = {"insert_ms": round(ti, 4), "find_ms": round(tf, 4),
-                            "insert_mops": round(n / ti / 1e3, 1), "find_mops": round(n / tf / 1e3, 1)}
     t.close()
-    del dk, dv, dfk
+    return {"insert_ms": round(ti, 4), "find_ms": round(tf, 4),
+            "insert_mops": round(n / ti / 1e3, 1), "find_mops": round(n / tf / 1e3, 1)}
+
+
+def _suite_fill_sweep(dev, up, stream, reps, dkeys, dvals):
+    import torch
+
+    from paper_1601_04017_amd import inputs, lpht
 
     # fill sweep on 2^28 cells of 16 bytes
     log("suite: fill sweep")
     sweep = {}
-    nmax = 201_326_592
-    keys = inputs.distinct_keys_u64(nmax, 201)
-    miss = inputs.distinct_keys_u64(10 ** 8, 201, absent=True)
-    dkeys, dmiss = up(keys), up(miss)
-    dvals = torch.arange(nmax, dtype=torch.int64, device=dev)
+    dmiss = up(inputs.distinct_keys_u64(10 ** 8, 201, absent=True))
     t = lpht.Table(layout=lpht.KV64, log2_capacity=28)
     outv = torch.empty(10 ** 8, dtype=torch.int64, device=dev)
     outf = torch.empty(10 ** 8, dtype=torch.uint8, device=dev)
@@ -187,9 +216,14 @@ def run_suite(dev, reps=3):
                                            "find_hit_mops": round(1e8 / th / 1e3, 1),
                                            "find_miss_mops": round(1e8 / tm / 1e3, 1)}
         del hit
-    out["fill_sweep_2e28"] = sweep
     t.close()
-    del dmiss, outv, outf
+    return sweep
+
+
+def _suite_growing(stream, reps, dkeys, dvals):
+    import torch
+
+    from paper_1601_04017_amd import lpht
 
     # growing from 4096 cells, 10^8 keys in batches of 2^20
     log("suite: growing")
@@ -207,17 +241,24 @@ def run_suite(dev, reps=3):
         el = (time.perf_counter() - t0) * 1e3
         st = t.stats()
         if r:
-            res.append((el, st["migrate_ms"], st["migrations"], st["resizes"], t.log2_capacity))
+            res.append((el, st["migrate_ms"], st["migrations"], st["resizes"], t.log2_capacity,
+                        st["host_syncs"]))
         assert t.count() == (N_OPS, N_OPS)
         t.close()
-    el, mig, nmig, nres, lg = np.mean(res, axis=0)
-    out["growing_from_4096"] = {"total_ms": round(el, 3), "migrate_ms": round(mig, 3),
-                                "insert_ms_excl_migration": round(el - mig, 3),
-                                "mops": round(N_OPS / el / 1e3, 1), "data_migrations": int(nmig),
-                                "resizes": int(nres), "final_log2_capacity": int(lg)}
-    del dkeys, dvals
+    el, mig, nmig, nres, lg, syncs = np.mean(res, axis=0)
+    return {"total_ms": round(el, 3), "migrate_ms": round(mig, 3),
+            "insert_ms_excl_migration": round(el - mig, 3),
+            "mops": round(N_OPS / el / 1e3, 1), "data_migrations": int(nmig),
+            "resizes": int(nres), "final_log2_capacity": int(lg), "host_syncs": int(syncs)}
+
+
+def _suite_zipf(up, stream, reps):
+    import torch
+
+    from paper_1601_04017_amd import inputs, lpht
 
     # Zipf insert-or-increment, presized 2^28 and growing from 4096
+    b = 1 << 20
     zres = {}
     for sx in (0.5, 1.0, 1.25, 1.5):
         log(f"suite: zipf s={sx}")
@@ -252,8 +293,7 @@ def run_suite(dev, reps=3):
                          "growing_mops": round(N_OPS / gres[0][0] / 1e3, 1),
                          "growing_final_log2_capacity": int(gres[0][2]), "distinct": int(distinct)}
         del z
-    out["zipf_increment"] = zres
-    return out
+    return zres
 
 
 def main():
@@ -265,6 +305,8 @@ def main():
     ap.add_argument("--group-width", type=int, default=None)
     ap.add_argument("--aggregate", type=int, default=None)
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads")
+    ap.add_argument("--parts", default=",".join(SUITE_PARTS), help="suite parts to run")
+    ap.add_argument("--suite-only", action="store_true", help="skip the headline step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (tables shard by hash "
@@ -279,6 +321,10 @@ def main():
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.suite_only:
+        print(json.dumps({"suite": run_suite(dev, parts=tuple(args.parts.split(",")))}), flush=True)
+        return
 
     log("generating inputs")
     keys = inputs.distinct_keys_u64(N_OPS, 201)
@@ -411,7 +457,7 @@ def main():
         del d_keys, d_vals, d_hit, d_miss, d_zipf, d_out, d_flags, d_found
         t1.close()
         t2.close()
-        out["suite"] = run_suite(dev)
+        out["suite"] = run_suite(dev, parts=tuple(args.parts.split(",")))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 thread)")
         out["cpu_baseline"] = cpu_baseline(keys, hit, miss, zipf)

@@ -210,6 +210,56 @@ int lpht_get_tuning(const lpht_table *t, lpht_tuning *tuning);
 int lpht_set_timing(lpht_table *t, int timing);
 int lpht_get_stats(lpht_table *t, lpht_stats *stats);
 
+/* ---- batches: many tables and calls in few launches ----
+ *
+ * A batch is a list of bulk calls (descriptors), possibly on different tables
+ * and of uneven lengths.  Descriptors are grouped by operation and update
+ * function; the groups run in the phase order FIND, INSERT, UPSERT, UPDATE,
+ * ERASE, each group as one kernel launch per cell layout in which the
+ * descriptors' 128-operation rounds are dealt to the wavefronts of one grid
+ * (the paper deals blocks of operations to threads, Sec. 8.3).  Descriptors of
+ * one group that name the same table behave like one bulk call on it.  Before
+ * an INSERT or UPSERT group, every auto-growing table of the group grows for
+ * the sum of its descriptors' lengths (Sec. 5.5).  Launch parameters are those
+ * of the group's first table.
+ *
+ * `kinds` (optional, device, n bytes): when set, the descriptor performs only
+ * the operations i with kinds[i] == kind_sel and leaves the other flag bytes
+ * unchanged; a FIND descriptor writes value 0 for the other operations.  This
+ * runs a mixed request in phase order with one descriptor per phase. */
+#define LPHT_OP_FIND 0u
+#define LPHT_OP_INSERT 1u
+#define LPHT_OP_UPSERT 2u
+#define LPHT_OP_UPDATE 3u
+#define LPHT_OP_ERASE 4u
+
+typedef struct lpht_batch_op {
+  lpht_table *table;
+  uint32_t op;           /* LPHT_OP_* */
+  uint32_t up;           /* LPHT_ASSIGN or LPHT_ADD (UPSERT, UPDATE) */
+  const void *keys;      /* device, n keys */
+  const void *vals;      /* device, n values, or NULL (value 1) */
+  uint64_t n;
+  void *vals_out;        /* FIND: device, n values, or NULL */
+  uint8_t *flags;        /* device, n flag bytes, or NULL */
+  const uint8_t *kinds;  /* device, n bytes, or NULL */
+  uint32_t kind_sel;
+  uint32_t count_sel;    /* with kinds: number of operations of kind kind_sel (the growth
+                            rule's b); a descriptor with kinds and count_sel 0 is skipped */
+} lpht_batch_op;
+
+typedef struct lpht_batch lpht_batch; /* descriptor staging ring; owned by the caller */
+
+/* Creates a batch context for up to `max_ops` descriptors per call on the
+ * current device (pinned and device staging buffers, reused in stream order). */
+int lpht_batch_create(uint32_t max_ops, lpht_batch **out);
+int lpht_batch_destroy(lpht_batch *b);
+
+/* Runs `nops` descriptors in stream order on `stream`.  Errors: INVALID
+ * (NULL or foreign table, mixed devices, nops > max_ops, misaligned arrays),
+ * OOM (growth), DEVICE. */
+int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void *stream);
+
 /* Static description of an error code. */
 const char *lpht_strerror(int code);
 

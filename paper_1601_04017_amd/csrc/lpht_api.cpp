@@ -132,13 +132,28 @@ bool within_fill(const lpht_table *t, uint64_t x, uint64_t c) {
   return (unsigned __int128)x * t->cfg.max_fill_den <= (unsigned __int128)c * t->cfg.max_fill_num;
 }
 
-int sync_counts(lpht_table *t, hipStream_t s) {
-  DevStatus h;
-  hipError_t e = hipMemcpyAsync(&h, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s);
+// Reads the status block (synchronises the stream) and the count totals.
+int read_status(lpht_table *t, hipStream_t s, DevStatus *h, uint64_t *used, uint64_t *live) {
+  hipError_t e = hipMemcpyAsync(h, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return from_hip(e);
-  t->known_used = h.used;
-  t->known_live = h.live;
+  uint64_t u = 0, l = 0;
+  for (int i = 0; i < kCountSlots; ++i) {
+    u += h->slot[i].used;
+    l += h->slot[i].live;
+  }
+  *used = u;
+  *live = l;
+  return LPHT_OK;
+}
+
+int sync_counts(lpht_table *t, hipStream_t s) {
+  DevStatus h;
+  uint64_t u, l;
+  int rc = read_status(t, s, &h, &u, &l);
+  if (rc) return rc;
+  t->known_used = u;
+  t->known_live = l;
   t->pending = 0;
   return LPHT_OK;
 }
@@ -305,7 +320,166 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
 
 }  // namespace
 
+struct lpht_batch {
+  static constexpr int kSlots = 16;
+  int device;
+  uint32_t max_ops;
+  size_t slot_bytes;
+  unsigned char *host[kSlots];  // pinned
+  unsigned char *dev[kSlots];
+  hipEvent_t ev[kSlots];
+  bool used[kSlots];
+  int next;
+};
+
+namespace {
+
+const OpKind kPhaseOrder[] = {OP_FIND, OP_INSERT, OP_UPSERT, OP_UPDATE, OP_ERASE};
+
+void batch_free(lpht_batch *b) {
+  for (int i = 0; i < lpht_batch::kSlots; ++i) {
+    if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+    if (b->host[i]) (void)hipHostFree(b->host[i]);
+    if (b->dev[i]) (void)hipFree(b->dev[i]);
+  }
+  delete b;
+}
+
+// Uploads one group's descriptors and round offsets through a ring slot and
+// launches it.
+int batch_launch(lpht_batch *b, OpKind op, uint32_t up, uint32_t layout, const BulkArgs *args,
+                 uint32_t nd, const LaunchCfg &cfg, hipStream_t s) {
+  const int slot = b->next;
+  b->next = (b->next + 1) % lpht_batch::kSlots;
+  if (b->used[slot] && hipEventSynchronize(b->ev[slot]) != hipSuccess) return LPHT_ERR_DEVICE;
+  BulkArgs *ha = (BulkArgs *)b->host[slot];
+  uint64_t *hr = (uint64_t *)(b->host[slot] + sizeof(BulkArgs) * b->max_ops);
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < nd; ++j) {
+    ha[j] = args[j];
+    hr[j] = total;
+    total += (args[j].n + kRound - 1) / kRound;
+  }
+  hr[nd] = total;
+  if (total == 0) return LPHT_OK;
+  hipError_t e = hipMemcpyAsync(b->dev[slot], b->host[slot], b->slot_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_bulk_multi(op, up, layout, (const BulkArgs *)b->dev[slot],
+                          (const uint64_t *)(b->dev[slot] + sizeof(BulkArgs) * b->max_ops), nd, total,
+                          cfg, s);
+  if (e == hipSuccess) e = hipEventRecord(b->ev[slot], s);
+  if (e != hipSuccess) return from_hip(e);
+  b->used[slot] = true;
+  return LPHT_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int lpht_batch_create(uint32_t max_ops, lpht_batch **out) {
+  if (!out) return LPHT_ERR_INVALID;
+  *out = nullptr;
+  if (max_ops == 0 || max_ops > (1u << 20)) return LPHT_ERR_INVALID;
+  lpht_batch *b = new (std::nothrow) lpht_batch();
+  if (!b) return LPHT_ERR_OOM;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return LPHT_ERR_DEVICE;
+  }
+  b->max_ops = max_ops;
+  b->slot_bytes = sizeof(BulkArgs) * max_ops + sizeof(uint64_t) * (max_ops + 1);
+  for (int i = 0; i < lpht_batch::kSlots; ++i) {
+    if (hipHostMalloc((void **)&b->host[i], b->slot_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&b->dev[i], b->slot_bytes) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) != hipSuccess) {
+      batch_free(b);
+      return LPHT_ERR_OOM;
+    }
+  }
+  *out = b;
+  return LPHT_OK;
+}
+
+int lpht_batch_destroy(lpht_batch *b) {
+  if (!b) return LPHT_OK;
+  (void)hipSetDevice(b->device);
+  for (int i = 0; i < lpht_batch::kSlots; ++i)
+    if (b->used[i]) (void)hipEventSynchronize(b->ev[i]);
+  batch_free(b);
+  return LPHT_OK;
+}
+
+int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void *stream) {
+  if (!b || (nops && !ops) || nops > b->max_ops) return LPHT_ERR_INVALID;
+  for (uint32_t j = 0; j < nops; ++j) {
+    const lpht_batch_op &o = ops[j];
+    if (!o.table || o.op > LPHT_OP_ERASE || o.up > LPHT_ADD) return LPHT_ERR_INVALID;
+    if (o.count_sel > o.n) return LPHT_ERR_INVALID;
+    if (o.table->device != b->device) return LPHT_ERR_INVALID;
+    int rc = check_arrays(o.table, o.keys, o.vals, o.n);
+    if (rc) return rc;
+    if (o.vals_out && !aligned(o.vals_out, o.table->cfg.layout == LPHT_PACKED32 ? 4 : 8))
+      return LPHT_ERR_INVALID;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(b->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  std::vector<BulkArgs> group;
+  group.reserve(nops);
+  for (OpKind op : kPhaseOrder) {
+    for (uint32_t up = 0; up <= 1; ++up) {
+      if (up == 1 && op != OP_UPSERT && op != OP_UPDATE) continue;
+      for (uint32_t layout = 0; layout <= 1; ++layout) {
+        // growth first: each table grows once for all of its descriptors
+        if (op == OP_INSERT || op == OP_UPSERT) {
+          std::vector<std::pair<lpht_table *, uint64_t>> need;
+          for (uint32_t j = 0; j < nops; ++j) {
+            const lpht_batch_op &o = ops[j];
+            if ((OpKind)o.op != op || o.table->cfg.layout != layout || o.n == 0) continue;
+            if (op == OP_UPSERT && o.up != up) continue;
+            if (o.kinds && o.count_sel == 0) continue;
+            const uint64_t b_ops = o.kinds ? o.count_sel : o.n;
+            bool found = false;
+            for (auto &pr : need)
+              if (pr.first == o.table) {
+                pr.second += b_ops;
+                found = true;
+              }
+            if (!found) need.emplace_back(o.table, b_ops);
+          }
+          for (auto &pr : need) {
+            int rc = grow_before_batch(pr.first, pr.second, s);
+            if (rc) return rc;
+          }
+        }
+        group.clear();
+        const lpht_table *first = nullptr;
+        for (uint32_t j = 0; j < nops; ++j) {
+          const lpht_batch_op &o = ops[j];
+          if ((OpKind)o.op != op || o.table->cfg.layout != layout || o.n == 0) continue;
+          if ((op == OP_UPSERT || op == OP_UPDATE) && o.up != up) continue;
+          if (o.kinds && o.count_sel == 0) continue;
+          BulkArgs a = make_args(o.table);
+          a.keys = o.keys;
+          a.vals = o.vals;
+          a.n = o.n;
+          a.vals_out = o.vals_out;
+          a.flags = o.flags;
+          a.up = up;
+          a.kinds = o.kinds;
+          a.kind_sel = o.kind_sel;
+          group.push_back(a);
+          if (!first) first = o.table;
+        }
+        if (group.empty()) continue;
+        int rc = batch_launch(b, op, up, layout, group.data(), (uint32_t)group.size(), first->launch, s);
+        if (rc) return rc;
+      }
+    }
+  }
+  return LPHT_OK;
+}
+
 
 void lpht_config_default(lpht_config *cfg) {
   if (!cfg) return;
@@ -503,14 +677,14 @@ int lpht_status(lpht_table *t, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
   DevStatus h;
-  hipError_t e = hipMemcpyAsync(&h, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return from_hip(e);
-  t->known_used = h.used;
-  t->known_live = h.live;
+  uint64_t u, l;
+  int rc = read_status(t, s, &h, &u, &l);
+  if (rc) return rc;
+  t->known_used = u;
+  t->known_live = l;
   t->pending = 0;
   if (h.err) {
-    e = launch_set_status(t->status, h.used, h.live, 1, s);
+    hipError_t e = launch_set_status(t->status, u, l, 1, s);
     if (e != hipSuccess) return from_hip(e);
   }
   if (h.err & kErrFull) return LPHT_ERR_FULL;

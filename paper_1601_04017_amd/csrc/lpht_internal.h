@@ -13,14 +13,24 @@ constexpr uint64_t kTomb = 1;   // del_key
 constexpr uint32_t kErrFull = 1u;
 constexpr uint32_t kErrReserved = 2u;
 
-// Per-table device status block: exact counts and sticky error bits.
-struct alignas(64) DevStatus {
+// Per-table device status block: exact counts and sticky error bits.  The
+// counts are spread over kCountSlots slots, one 128-byte line each, so that
+// the one-atomic-per-workgroup flush of a bulk kernel does not serialise all
+// workgroups on one address; the totals are the sums over the slots.
+constexpr int kCountSlots = 64;
+
+struct alignas(128) CountSlot {
   unsigned long long used;  // non-empty cells
   unsigned long long live;  // live keys
-  unsigned int err;         // kErr* bits
-  unsigned int pad;
-  unsigned long long moved; // elements written by the last migration
-  unsigned long long aux[4];
+  unsigned long long pad[14];
+};
+
+struct alignas(128) DevStatus {
+  unsigned int err;              // kErr* bits
+  unsigned int pad0;
+  unsigned long long overflow;   // set by a migration that needs the fallback
+  unsigned long long pad[14];
+  CountSlot slot[kCountSlots];
 };
 
 enum OpKind : int { OP_FIND = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_UPDATE = 3, OP_ERASE = 4 };
@@ -40,6 +50,9 @@ struct BulkArgs {
   uint8_t *flags;       // may be null
   uint32_t up;          // 0 assign, 1 add
   uint32_t aggregate;   // 1: combine equal keys in LDS (upsert with add only)
+  const uint8_t *kinds; // may be null; else only operations with kinds[i] == kind_sel run
+  uint32_t kind_sel;
+  uint32_t pad;
 };
 
 struct LaunchCfg {
@@ -53,6 +66,13 @@ struct LaunchCfg {
 
 // Kernel launchers (lpht_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_bulk(OpKind op, const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s);
+// One launch over `ndesc` descriptors of the same layout, operation and
+// update function (device arrays: descs[ndesc], round_start[ndesc + 1] with
+// round_start[j] = sum of ceil(n_i / kRound) for i < j).
+constexpr uint32_t kRound = 128;
+hipError_t launch_bulk_multi(OpKind op, uint32_t up, uint32_t layout, const BulkArgs *descs,
+                             const uint64_t *round_start, uint32_t ndesc, uint64_t total_rounds,
+                             const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_fill_zero(void *ptr, uint64_t bytes, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_set_status(DevStatus *st, uint64_t used, uint64_t live, int clear_err,
                              hipStream_t s);
@@ -60,8 +80,8 @@ hipError_t launch_recount(const void *cells, uint32_t log2c, uint32_t layout, De
                           const LaunchCfg &cfg, hipStream_t s);
 // Block-parallel cluster migration of `old_cells` (2^log2_old cells) into
 // `new_cells` (2^log2_new cells, log2_new >= log2_old).  `new_cells` need not
-// be initialised.  Adds the number of moved elements to st->used and
-// st->live (the caller zeroes them first).
+// be initialised.  Adds the number of moved elements to the used and live
+// counts (the caller zeroes them first).
 hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_cells,
                           uint32_t log2_new, uint32_t layout, uint32_t crc_hi, uint32_t crc_lo,
                           int old_is_full, DevStatus *st, const LaunchCfg &cfg, hipStream_t s);

@@ -130,8 +130,9 @@ __device__ __forceinline__ void flush_counts(DevStatus *st, long long d_used, lo
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (s_acc[0]) add64(&st->used, (u64)s_acc[0]);
-    if (s_acc[1]) add64(&st->live, (u64)s_acc[1]);
+    CountSlot *cs = &st->slot[blockIdx.x % kCountSlots];
+    if (s_acc[0]) add64(&cs->used, (u64)s_acc[0]);
+    if (s_acc[1]) add64(&cs->live, (u64)s_acc[1]);
     if (*s_err) atomicOr(&st->err, *s_err);
   }
 }
@@ -202,139 +203,223 @@ __device__ __forceinline__ void wave_sync() {
 // consecutive operations; its groups work through them, results are staged
 // in LDS, and at the end of the round the wavefront writes them out as whole
 // lines (128 flag bytes, 128 values), so output lines are written once.
-constexpr uint32_t ROUND = 128;
+constexpr uint32_t ROUND = kRound;
 
 __host__ __device__ constexpr uint32_t bulk_lds_bytes_per_wave(int op) {
   return ROUND * (op == OP_FIND ? 9u : 1u);
 }
 
-// One kernel for every bulk operation; OP and UP are compile-time.
+// Marks, in the staged flags of a round, an operation that belongs to another
+// phase of a mixed request; its flag byte in memory is left as it is.
+constexpr uint8_t kSkipFlag = 0xFD;
+
+// One round of a bulk call: operations [rbase, rbase + cnt) of A, each taken
+// by a group of G lanes; results are staged in LDS (wflag, wout) and written
+// as whole lines at the end.
 //   OP_FIND    : found flag + value
 //   OP_INSERT  : insert(k, d)
 //   OP_UPSERT  : insertOrUpdate(k, d, up)
 //   OP_UPDATE  : update(k, d, up)
 //   OP_ERASE   : tombstone delete
+// With A.kinds set, only operations whose kind byte equals A.kind_sel are
+// performed (phase order of mixed requests: finds, then insert-or-increments,
+// then erases); a find phase writes value 0 for the other operations.
 template <int LAYOUT, int OP, int UP, int G>
-__global__ void __launch_bounds__(1024) k_bulk(BulkArgs A) {
-  __shared__ uint32_t T[8][256];
-  __shared__ long long s_acc[2];
-  __shared__ uint32_t s_err;
-  extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
-  crc_tables_build(T);
-
+__device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T)[256], uint8_t *wflag,
+                                           u64 *wout, const u64 rbase, const uint32_t cnt,
+                                           long long &d_used, long long &d_live, uint32_t &err) {
   constexpr uint32_t NGW = 64 / G;            // groups per wavefront
   constexpr uint32_t PER_GROUP = ROUND / NGW; // operations per group per round
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = threadIdx.x >> 6;
-  const uint32_t nwb = blockDim.x >> 6;
   const uint32_t gl = lane & (G - 1);  // lane within the group
   const uint32_t gbase = lane - gl;    // first lane of the group in the wave
   const uint32_t gi = lane / G;        // group within the wave
   const u64 cap = 1ull << A.log2c;
   const u64 mask = cap - 1;
   const u64 max_windows = cap / G;     // plus one when the home is unaligned
-  uint8_t *wflag = dyn_lds + (OP == OP_FIND ? nwb * ROUND * 8 : 0) + wave * ROUND;
-  u64 *wout = (u64 *)dyn_lds + wave * ROUND;  // FIND only
-
-  long long d_used = 0, d_live = 0;
-  uint32_t err = 0;
-
-  const u64 nrounds = (A.n + ROUND - 1) / ROUND;
-  const u64 gw = (u64)blockIdx.x * nwb + wave;
-  const u64 nw = (u64)gridDim.x * nwb;
   const bool flags8 = A.flags && (((uintptr_t)A.flags & 7) == 0);
   const bool vals_vec = (OP == OP_FIND) && A.vals_out && (((uintptr_t)A.vals_out & 15) == 0);
+  uint32_t j = 0;
+  u64 i = 0, k = 0, d = 1, base = 0, windows = 0, limit = 0;
+  uint32_t first = 0;
+  bool active = false;
 
-  for (u64 r = gw; r < nrounds; r += nw) {
-    const u64 rbase = r * ROUND;
-    const uint32_t cnt = (uint32_t)((A.n - rbase) < ROUND ? (A.n - rbase) : ROUND);
-    uint32_t j = 0;
-    u64 i = 0, k = 0, d = 1, base = 0, windows = 0, limit = 0;
-    uint32_t first = 0;
-    bool active = false;
-
-    // Takes the group's next operation of the round (reserved keys are
-    // answered at once).
-    auto start = [&]() {
-      active = false;
-      while (j < PER_GROUP) {
-        const uint32_t loc = gi + j * NGW;
-        if (loc >= cnt) {
-          j = PER_GROUP;
-          break;
-        }
-        i = rbase + loc;
-        k = load_key_in<LAYOUT>(A.keys, i);
-        if (k == kEmpty || k == kTomb) {
-          err |= kErrReserved;
-          if (gl == 0) {
-            wflag[loc] = 0xFE;
-            if (OP == OP_FIND) wout[loc] = 0;
-          }
-          ++j;
-          continue;
-        }
-        d = A.vals ? load_key_in<LAYOUT>(A.vals, i) : 1;
-        const u64 h = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
-        base = h & ~(u64)(G - 1);
-        first = (uint32_t)(h & (G - 1));
-        windows = 0;
-        limit = max_windows + (first ? 1 : 0);
-        active = true;
-        return;
+  // Takes the group's next operation of the round (reserved keys are
+  // answered at once).
+  auto start = [&]() {
+    active = false;
+    while (j < PER_GROUP) {
+      const uint32_t loc = gi + j * NGW;
+      if (loc >= cnt) {
+        j = PER_GROUP;
+        break;
       }
-    };
-
-    auto finish = [&](uint8_t flag, u64 v) {
-      if (gl == 0) {
-        const uint32_t loc = gi + j * NGW;
-        wflag[loc] = flag;
-        if (OP == OP_FIND) wout[loc] = v;
+      i = rbase + loc;
+      if (A.kinds && A.kinds[i] != A.kind_sel) {
+        // an operation of another phase of a mixed request
+        if (gl == 0) {
+          wflag[loc] = kSkipFlag;
+          if (OP == OP_FIND) wout[loc] = 0;
+        }
+        ++j;
+        continue;
       }
-      ++j;
-      start();
-    };
+      k = load_key_in<LAYOUT>(A.keys, i);
+      if (k == kEmpty || k == kTomb) {
+        err |= kErrReserved;
+        if (gl == 0) {
+          wflag[loc] = 0xFE;
+          if (OP == OP_FIND) wout[loc] = 0;
+        }
+        ++j;
+        continue;
+      }
+      d = A.vals ? load_key_in<LAYOUT>(A.vals, i) : 1;
+      const u64 h = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
+      base = h & ~(u64)(G - 1);
+      first = (uint32_t)(h & (G - 1));
+      windows = 0;
+      limit = max_windows + (first ? 1 : 0);
+      active = true;
+      return;
+    }
+  };
 
+  auto finish = [&](uint8_t flag, u64 v) {
+    if (gl == 0) {
+      const uint32_t loc = gi + j * NGW;
+      wflag[loc] = flag;
+      if (OP == OP_FIND) wout[loc] = v;
+    }
+    ++j;
     start();
-    while (__any(active)) {
-      if (active) {
-        const u64 idx = base + gl;
-        u64 ck, cv = 0;
-        if (LAYOUT == 0) {
-          const u64 w = Cells<0>::word(A.cells, idx);
-          ck = Cells<0>::key_of(w);
-          cv = Cells<0>::val_of(w);
-        } else if (OP == OP_FIND) {
-          const u64x2 c = Cells<1>::cell(A.cells, idx);
-          ck = c.x;
-          cv = c.y;
-        } else {
-          ck = Cells<1>::key(A.cells, idx);
-        }
-        bool done = false;
-        uint8_t flag = 0;
-        u64 outv = 0;
-        // Evaluate the window; a failed CAS updates the lane's key and the
-        // window is evaluated again from that lane on.
-        while (true) {
-          const bool valid = gl >= first;
-          const uint32_t bh = group_bits<G>(__ballot(valid && ck == k), gbase);
-          const uint32_t be = group_bits<G>(__ballot(valid && ck == kEmpty), gbase);
-          const uint32_t ev = bh | be;
-          if (ev == 0) break;
-          const uint32_t jl = __builtin_ctz(ev);
-          const uint32_t src = gbase + jl;
-          if ((bh >> jl) & 1u) {
-            // key present at lane jl
-            if (OP == OP_FIND) {
-              outv = __shfl(cv, src, 64);
+  };
+
+  start();
+  while (__any(active)) {
+    if (active) {
+      const u64 idx = base + gl;
+      u64 ck, cv = 0;
+      if (LAYOUT == 0) {
+        const u64 w = Cells<0>::word(A.cells, idx);
+        ck = Cells<0>::key_of(w);
+        cv = Cells<0>::val_of(w);
+      } else if (OP == OP_FIND) {
+        const u64x2 c = Cells<1>::cell(A.cells, idx);
+        ck = c.x;
+        cv = c.y;
+      } else {
+        ck = Cells<1>::key(A.cells, idx);
+      }
+      bool done = false;
+      uint8_t flag = 0;
+      u64 outv = 0;
+      // Evaluate the window; a failed CAS updates the lane's key and the
+      // window is evaluated again from that lane on.
+      while (true) {
+        const bool valid = gl >= first;
+        const uint32_t bh = group_bits<G>(__ballot(valid && ck == k), gbase);
+        const uint32_t be = group_bits<G>(__ballot(valid && ck == kEmpty), gbase);
+        const uint32_t ev = bh | be;
+        if (ev == 0) break;
+        const uint32_t jl = __builtin_ctz(ev);
+        const uint32_t src = gbase + jl;
+        if ((bh >> jl) & 1u) {
+          // key present at lane jl
+          if (OP == OP_FIND) {
+            outv = __shfl(cv, src, 64);
+            flag = 1;
+            done = true;
+          } else if (OP == OP_INSERT) {
+            flag = 0;
+            done = true;
+          } else if (OP == OP_UPSERT || OP == OP_UPDATE) {
+            if (gl == jl) {
+              if (LAYOUT == 0) {
+                u64 *w = (u64 *)A.cells + idx;
+                if (UP == 1)
+                  add64(w, d << 32);
+                else
+                  put32((uint32_t *)w + 1, (uint32_t)d);
+              } else {
+                u64 *v = (u64 *)A.cells + 2 * idx + 1;
+                if (UP == 1)
+                  add64(v, d);
+                else
+                  put64(v, d);
+              }
+            }
+            flag = (OP == OP_UPDATE) ? 1 : 0;
+            done = true;
+          } else {  // OP_ERASE
+            u64 old = 0;
+            bool won = false;
+            if (gl == jl) {
+              if (LAYOUT == 0) {
+                const u64 w = ((u64)cv << 32) | k;
+                old = cas64((u64 *)A.cells + idx, w, (w & ~0xFFFFFFFFull) | kTomb);
+                won = (old == w);
+                if (!won) old &= 0xFFFFFFFFull;
+              } else {
+                old = cas64((u64 *)A.cells + 2 * idx, k, kTomb);
+                won = (old == k);
+              }
+              if (won) d_live -= 1;
+            }
+            won = __shfl((int)won, src, 64) != 0;
+            if (won) {
               flag = 1;
               done = true;
-            } else if (OP == OP_INSERT) {
-              flag = 0;
+            } else {
+              // another operation changed this cell first; look at what is there now
+              old = __shfl(old, src, 64);
+              if (gl == jl) ck = old;
+              if (LAYOUT == 0 && gl == jl && old == k) {
+                // only the value changed: reload the word and retry
+                const u64 w = Cells<0>::word(A.cells, idx);
+                ck = Cells<0>::key_of(w);
+                cv = Cells<0>::val_of(w);
+              }
+              first = jl;
+              continue;
+            }
+          }
+        } else {
+          // empty cell at lane jl: k is absent
+          if (OP == OP_FIND || OP == OP_UPDATE || OP == OP_ERASE) {
+            flag = 0;
+            outv = 0;
+            done = true;
+          } else {
+            u64 old = 0;
+            if (gl == jl) {
+              if (LAYOUT == 0) {
+                old = cas64((u64 *)A.cells + idx, 0ull, (d << 32) | k);
+                if (old == 0) {
+                  d_used += 1;
+                  d_live += 1;
+                }
+              } else {
+                old = cas64((u64 *)A.cells + 2 * idx, kEmpty, k);
+                if (old == kEmpty) {
+                  u64 *v = (u64 *)A.cells + 2 * idx + 1;
+                  if (OP == OP_UPSERT && UP == 1)
+                    add64(v, d);  // concurrent increments of the same key also add
+                  else
+                    put64(v, d);
+                  d_used += 1;
+                  d_live += 1;
+                }
+              }
+            }
+            old = __shfl(old, src, 64);
+            const u64 okey = (LAYOUT == 0) ? (old & 0xFFFFFFFFull) : old;
+            if (old == 0) {
+              flag = 1;
               done = true;
-            } else if (OP == OP_UPSERT || OP == OP_UPDATE) {
-              if (gl == jl) {
+            } else if (okey == k) {
+              // lost the race to an insertion of the same key
+              if (OP == OP_UPSERT && gl == jl) {
                 if (LAYOUT == 0) {
                   u64 *w = (u64 *)A.cells + idx;
                   if (UP == 1)
@@ -349,147 +434,139 @@ __global__ void __launch_bounds__(1024) k_bulk(BulkArgs A) {
                     put64(v, d);
                 }
               }
-              flag = (OP == OP_UPDATE) ? 1 : 0;
-              done = true;
-            } else {  // OP_ERASE
-              u64 old = 0;
-              bool won = false;
-              if (gl == jl) {
-                if (LAYOUT == 0) {
-                  const u64 w = ((u64)cv << 32) | k;
-                  old = cas64((u64 *)A.cells + idx, w, (w & ~0xFFFFFFFFull) | kTomb);
-                  won = (old == w);
-                  if (!won) old &= 0xFFFFFFFFull;
-                } else {
-                  old = cas64((u64 *)A.cells + 2 * idx, k, kTomb);
-                  won = (old == k);
-                }
-                if (won) d_live -= 1;
-              }
-              won = __shfl((int)won, src, 64) != 0;
-              if (won) {
-                flag = 1;
-                done = true;
-              } else {
-                // another operation changed this cell first; look at what is there now
-                old = __shfl(old, src, 64);
-                if (gl == jl) ck = old;
-                if (LAYOUT == 0 && gl == jl && old == k) {
-                  // only the value changed: reload the word and retry
-                  const u64 w = Cells<0>::word(A.cells, idx);
-                  ck = Cells<0>::key_of(w);
-                  cv = Cells<0>::val_of(w);
-                }
-                first = jl;
-                continue;
-              }
-            }
-          } else {
-            // empty cell at lane jl: k is absent
-            if (OP == OP_FIND || OP == OP_UPDATE || OP == OP_ERASE) {
               flag = 0;
-              outv = 0;
               done = true;
             } else {
-              u64 old = 0;
-              if (gl == jl) {
-                if (LAYOUT == 0) {
-                  old = cas64((u64 *)A.cells + idx, 0ull, (d << 32) | k);
-                  if (old == 0) {
-                    d_used += 1;
-                    d_live += 1;
-                  }
-                } else {
-                  old = cas64((u64 *)A.cells + 2 * idx, kEmpty, k);
-                  if (old == kEmpty) {
-                    u64 *v = (u64 *)A.cells + 2 * idx + 1;
-                    if (OP == OP_UPSERT && UP == 1)
-                      add64(v, d);  // concurrent increments of the same key also add
-                    else
-                      put64(v, d);
-                    d_used += 1;
-                    d_live += 1;
-                  }
-                }
-              }
-              old = __shfl(old, src, 64);
-              const u64 okey = (LAYOUT == 0) ? (old & 0xFFFFFFFFull) : old;
-              if (old == 0) {
-                flag = 1;
-                done = true;
-              } else if (okey == k) {
-                // lost the race to an insertion of the same key
-                if (OP == OP_UPSERT && gl == jl) {
-                  if (LAYOUT == 0) {
-                    u64 *w = (u64 *)A.cells + idx;
-                    if (UP == 1)
-                      add64(w, d << 32);
-                    else
-                      put32((uint32_t *)w + 1, (uint32_t)d);
-                  } else {
-                    u64 *v = (u64 *)A.cells + 2 * idx + 1;
-                    if (UP == 1)
-                      add64(v, d);
-                    else
-                      put64(v, d);
-                  }
-                }
-                flag = 0;
-                done = true;
-              } else {
-                // another key took the cell: revisit it with that key
-                if (gl == jl) ck = okey;
-                first = jl;
-                continue;
-              }
+              // another key took the cell: revisit it with that key
+              if (gl == jl) ck = okey;
+              first = jl;
+              continue;
             }
           }
-          break;
         }
-        if (done) {
-          finish(flag, outv);
-        } else {
-          base = (base + G) & mask;
-          first = 0;
-          windows += 1;
-          if (windows >= limit) {
-            if (OP == OP_INSERT || OP == OP_UPSERT) {
-              err |= kErrFull;
-              finish(0xFF, 0);
-            } else {
-              finish(0, 0);
-            }
+        break;
+      }
+      if (done) {
+        finish(flag, outv);
+      } else {
+        base = (base + G) & mask;
+        first = 0;
+        windows += 1;
+        if (windows >= limit) {
+          if (OP == OP_INSERT || OP == OP_UPSERT) {
+            err |= kErrFull;
+            finish(0xFF, 0);
+          } else {
+            finish(0, 0);
           }
         }
       }
     }
-    // write the round's results as whole lines
-    wave_sync();
-    if (A.flags) {
-      if (cnt == ROUND && flags8) {
-        if (lane < ROUND / 8)
-          ((u64 *)(A.flags + rbase))[lane] = ((const u64 *)wflag)[lane];
-      } else {
-        for (uint32_t t = lane; t < cnt; t += 64) A.flags[rbase + t] = wflag[t];
-      }
-    }
-    if (OP == OP_FIND && A.vals_out) {
-      if (cnt == ROUND && vals_vec) {
-        if (LAYOUT == 0) {
-          typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-          u32x2 v = {(uint32_t)wout[2 * lane], (uint32_t)wout[2 * lane + 1]};
-          ((u32x2 *)((uint32_t *)A.vals_out + rbase))[lane] = v;
-        } else {
-          u64x2 v = {wout[2 * lane], wout[2 * lane + 1]};
-          ((u64x2 *)((u64 *)A.vals_out + rbase))[lane] = v;
+  }
+  // write the round's results as whole lines
+  wave_sync();
+  if (A.flags) {
+    if (cnt == ROUND && flags8) {
+      if (lane < ROUND / 8) {
+        u64 w = ((const u64 *)wflag)[lane];
+        if (A.kinds) {
+          // keep the flags other phases wrote
+          const u64 old = ((const u64 *)(A.flags + rbase))[lane];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const u64 m = 0xFFull << (8 * b);
+            if (((w & m) >> (8 * b)) == kSkipFlag) w = (w & ~m) | (old & m);
+          }
         }
-      } else {
-        for (uint32_t t = lane; t < cnt; t += 64) store_val_out<LAYOUT>(A.vals_out, rbase + t, wout[t]);
+        ((u64 *)(A.flags + rbase))[lane] = w;
       }
+    } else {
+      for (uint32_t t = lane; t < cnt; t += 64)
+        if (wflag[t] != kSkipFlag) A.flags[rbase + t] = wflag[t];
     }
-    wave_sync();
+  }
+  if (OP == OP_FIND && A.vals_out) {
+    if (cnt == ROUND && vals_vec) {
+      if (LAYOUT == 0) {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        u32x2 v = {(uint32_t)wout[2 * lane], (uint32_t)wout[2 * lane + 1]};
+        ((u32x2 *)((uint32_t *)A.vals_out + rbase))[lane] = v;
+      } else {
+        u64x2 v = {wout[2 * lane], wout[2 * lane + 1]};
+        ((u64x2 *)((u64 *)A.vals_out + rbase))[lane] = v;
+      }
+    } else {
+      for (uint32_t t = lane; t < cnt; t += 64) store_val_out<LAYOUT>(A.vals_out, rbase + t, wout[t]);
+    }
+  }
+  wave_sync();
+}
+
+// Single-table bulk call: wavefronts take rounds of A in grid-stride order.
+template <int LAYOUT, int OP, int UP, int G>
+__global__ void __launch_bounds__(1024) k_bulk(BulkArgs A) {
+  __shared__ uint32_t T[8][256];
+  __shared__ long long s_acc[2];
+  __shared__ uint32_t s_err;
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
+  crc_tables_build(T);
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t nwb = blockDim.x >> 6;
+  uint8_t *wflag = dyn_lds + (OP == OP_FIND ? nwb * ROUND * 8 : 0) + wave * ROUND;
+  u64 *wout = (u64 *)dyn_lds + wave * ROUND;  // FIND only
+  long long d_used = 0, d_live = 0;
+  uint32_t err = 0;
+  const u64 nrounds = (A.n + ROUND - 1) / ROUND;
+  const u64 gw = (u64)blockIdx.x * nwb + wave;
+  const u64 nw = (u64)gridDim.x * nwb;
+  for (u64 r = gw; r < nrounds; r += nw) {
+    const u64 rbase = r * ROUND;
+    const uint32_t cnt = (uint32_t)((A.n - rbase) < ROUND ? (A.n - rbase) : ROUND);
+    bulk_round<LAYOUT, OP, UP, G>(A, T, wflag, wout, rbase, cnt, d_used, d_live, err);
   }
   flush_counts(A.status, d_used, d_live, err, s_acc, &s_err);
+}
+
+// Multi-table bulk call: descriptor j covers rounds [round_start[j],
+// round_start[j+1]) of one launch, so tables and calls of uneven sizes share
+// one grid.  Counts go to each descriptor's table after every round.
+template <int LAYOUT, int OP, int UP, int G>
+__global__ void __launch_bounds__(1024) k_bulk_multi(const BulkArgs *descs, const u64 *round_start,
+                                                     uint32_t ndesc) {
+  __shared__ uint32_t T[8][256];
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
+  crc_tables_build(T);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t nwb = blockDim.x >> 6;
+  uint8_t *wflag = dyn_lds + (OP == OP_FIND ? nwb * ROUND * 8 : 0) + wave * ROUND;
+  u64 *wout = (u64 *)dyn_lds + wave * ROUND;  // FIND only
+  const u64 total = round_start[ndesc];
+  const u64 gw = (u64)blockIdx.x * nwb + wave;
+  const u64 nw = (u64)gridDim.x * nwb;
+  for (u64 r = gw; r < total; r += nw) {
+    uint32_t lo = 0, hi = ndesc;  // last j with round_start[j] <= r
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (round_start[mid] <= r) lo = mid; else hi = mid;
+    }
+    const BulkArgs A = descs[lo];
+    const u64 rbase = (r - round_start[lo]) * ROUND;
+    const uint32_t cnt = (uint32_t)((A.n - rbase) < ROUND ? (A.n - rbase) : ROUND);
+    long long d_used = 0, d_live = 0;
+    uint32_t err = 0;
+    bulk_round<LAYOUT, OP, UP, G>(A, T, wflag, wout, rbase, cnt, d_used, d_live, err);
+    const long long u = wave_sum(d_used), l = wave_sum(d_live);
+    uint32_t e = err;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, 64);
+    if (lane == 0) {
+      CountSlot *cs = &A.status->slot[gw % kCountSlots];
+      if (u) add64(&cs->used, (u64)u);
+      if (l) add64(&cs->live, (u64)l);
+      if (e) atomicOr(&A.status->err, e);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- aggregated insert-or-increment
@@ -691,11 +768,14 @@ __global__ void k_fill_zero(u64x2 *p, u64 n16) {
 }
 
 __global__ void k_set_status(DevStatus *st, u64 used, u64 live, int clear_err) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->used = used;
-    st->live = live;
-    st->moved = 0;
-    st->aux[0] = 0;  // migration overflow flag
+  const uint32_t t = threadIdx.x;
+  if (blockIdx.x != 0) return;
+  if (t < kCountSlots) {
+    st->slot[t].used = t == 0 ? used : 0;
+    st->slot[t].live = t == 0 ? live : 0;
+  }
+  if (t == 0) {
+    st->overflow = 0;
     if (clear_err) st->err = 0;
   }
 }
@@ -704,10 +784,10 @@ __global__ void k_set_status(DevStatus *st, u64 used, u64 live, int clear_err) {
 // then also resets the counts the interrupted migration added); otherwise
 // returns at once.
 __global__ void k_fill_zero_if(u64x2 *p, u64 n16, DevStatus *st) {
-  if (st->aux[0] == 0) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->used = 0;
-    st->live = 0;
+  if (st->overflow == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x < kCountSlots) {
+    st->slot[threadIdx.x].used = 0;
+    st->slot[threadIdx.x].live = 0;
   }
   const u64 stride = (u64)gridDim.x * blockDim.x;
   const u64x2 z = {0ull, 0ull};
@@ -749,7 +829,7 @@ __global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, u
   __shared__ uint32_t s_err;
   // as the fallback of the LDS-staged migration it runs only when that one
   // reported a cluster longer than its halo
-  if (guarded && st->aux[0] == 0) return;
+  if (guarded && st->overflow == 0) return;
   crc_tables_build(T);
   const u64 cap = 1ull << log2_old, mask = cap - 1;
   const u64 nmask = (1ull << log2_new) - 1;
@@ -813,6 +893,7 @@ __global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, u
 // A cluster longer than the halo (or a table without empty cells) sets the
 // overflow flag; the guarded simple migration then redoes the whole move.
 constexpr int MIG_HALO = 128;
+constexpr int MIG_THREADS = 256;
 
 __host__ __device__ constexpr uint32_t mig_window(uint32_t mb) { return mb + 2 * MIG_HALO; }
 
@@ -820,10 +901,14 @@ __host__ __device__ constexpr size_t mig_lds_bytes(uint32_t mb, uint32_t layout,
   return (size_t)mig_window(mb) * (layout == 0 ? 8u : 16u) * (1 + gamma);
 }
 
-template <int LAYOUT>
-__global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint32_t log2_old,
-                                                     void *new_cells, uint32_t g, uint32_t crc_hi,
-                                                     uint32_t crc_lo, uint32_t mb, DevStatus *st) {
+// Q = window cells per thread (window = mb + 2*MIG_HALO cells, a multiple of
+// MIG_THREADS).  The next block's window is loaded into registers while the
+// current block is processed, so the loads' latency overlaps the LDS work.
+template <int LAYOUT, int Q>
+__global__ void __launch_bounds__(MIG_THREADS) k_migrate_lds(const void *old_cells, uint32_t log2_old,
+                                                             void *new_cells, uint32_t g,
+                                                             uint32_t crc_hi, uint32_t crc_lo,
+                                                             uint32_t mb, DevStatus *st) {
   __shared__ uint32_t T[8][256];
   __shared__ long long s_acc[2];
   __shared__ uint32_t s_err;
@@ -832,9 +917,9 @@ __global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint
   crc_tables_build(T);
 
   const int H = MIG_HALO;
-  const uint32_t W = mig_window(mb);
+  const uint32_t W = mig_window(mb);  // == Q * MIG_THREADS
   const uint32_t gamma = 1u << g;
-  const uint32_t IW = gamma * W;  // image cells
+  const uint32_t IW = gamma * W;      // image cells
   // old window and image: key and value arrays (KV64) or words (PACKED32)
   u64 *okey = (u64 *)dyn_lds;
   u64 *oval = okey + W;                              // KV64 only
@@ -845,93 +930,107 @@ __global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint
 
   const u64 cap = 1ull << log2_old, mask = cap - 1;
   const uint32_t log2_new = log2_old + g;
-  const u64 nblocks = cap / mb;
+  const u64 nblocks = cap >> (31 - __builtin_clz(mb));  // cap / mb, both powers of two
+  const uint32_t tid = threadIdx.x;
   long long moved = 0;
 
-  for (u64 blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-    const long long d = (long long)(blk * mb);
-    if (threadIdx.x == 0) {
-      s_last_empty = -1;
-      s_first_empty = 0x7FFFFFFF;
-    }
-    for (uint32_t t = threadIdx.x; t < W; t += blockDim.x) {
-      const u64 x = (u64)(d - H + (long long)t) & mask;
+  u64x2 pre[Q];
+  auto issue = [&](u64 b) {
+    const long long d = (long long)(b * mb);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const u64 x = (u64)(d - H + (long long)(tid + q * MIG_THREADS)) & mask;
       if (LAYOUT == 0) {
-        okey[t] = ((const u64 *)old_cells)[x];
+        pre[q].x = ((const u64 *)old_cells)[x];
       } else {
-        const u64x2 c = ((const u64x2 *)old_cells)[x];
-        okey[t] = c.x;
-        oval[t] = c.y;
+        pre[q] = ((const u64x2 *)old_cells)[x];
       }
     }
-    for (uint32_t t = threadIdx.x; t < IW; t += blockDim.x) {
+  };
+
+  u64 blk = blockIdx.x;
+  if (blk < nblocks) issue(blk);
+  for (; blk < nblocks; blk += gridDim.x) {
+    const long long d = (long long)(blk * mb);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const uint32_t t = tid + q * MIG_THREADS;
+      okey[t] = pre[q].x;
+      if (LAYOUT == 1) oval[t] = pre[q].y;
+    }
+    for (uint32_t t = tid; t < IW; t += MIG_THREADS) {
       ikey[t] = 0;
       if (LAYOUT == 1) ival[t] = 0;
     }
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < W; t += blockDim.x) {
-      if (key_o(t) != kEmpty) continue;
-      if ((int)t < H) atomicMax(&s_last_empty, (int)t);
-      if ((int)t >= H + (int)mb) atomicMin(&s_first_empty, (int)t);
+    if (tid == 0) {
+      s_last_empty = -1;
+      s_first_empty = 0x7FFFFFFF;
     }
     __syncthreads();
+    if (blk + gridDim.x < nblocks) issue(blk + gridDim.x);
+    for (uint32_t t = tid; t < (uint32_t)H; t += MIG_THREADS)
+      if (key_o(t) == kEmpty) atomicMax(&s_last_empty, (int)t);
+    for (uint32_t t = H + mb + tid; t < W; t += MIG_THREADS)
+      if (key_o(t) == kEmpty) atomicMin(&s_first_empty, (int)t);
+    __syncthreads();
     // window indices [lo, hi) of the clusters that overlap the block
-    bool overflow = false;
+    bool skip = false;
     int lo = H, hi = H + (int)mb;
     if (key_o(H - 1) != kEmpty && key_o(H) != kEmpty) {
-      if (s_last_empty < 0) overflow = true;
+      if (s_last_empty < 0) skip = true;
       lo = s_last_empty + 1;
     }
     if (key_o(H + mb - 1) != kEmpty) {
-      if (s_first_empty == 0x7FFFFFFF) overflow = true;
+      if (s_first_empty == 0x7FFFFFFF) skip = true;
       hi = s_first_empty;
     }
-    if (overflow) {
-      if (threadIdx.x == 0) atomicOr((unsigned long long *)&st->aux[0], 1ull);
-      __syncthreads();
-      continue;
-    }
-    const long long ib = (long long)gamma * (d - H + lo);  // image base (unwrapped new index)
-    bool bad = false;
-    for (int t = lo + (int)threadIdx.x; t < hi; t += (int)blockDim.x) {
-      if (key_o(t) == kEmpty || key_o(t - 1) != kEmpty) continue;  // not a cluster start
-      for (int u = t; u < hi; ++u) {
-        const u64 k = key_o(u);
-        if (k == kEmpty) break;
-        if (k == kTomb) continue;
-        const u64 v = (LAYOUT == 0) ? (okey[u] >> 32) : oval[u];
-        const long long x = d - H + u;  // unwrapped old position
-        const u64 hn = home_of<LAYOUT>(T, k, crc_hi, crc_lo, log2_new);
-        const u64 oh = hn >> g;  // home in the old table
-        const u64 delta = ((u64)x - oh) & mask;
-        const long long nh = (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
-        long long p = nh - ib;
-        while (p < (long long)IW && key_i((uint32_t)p) != kEmpty) ++p;
-        if (p < 0 || p >= (long long)IW) {
-          bad = true;
-          break;
-        }
-        if (LAYOUT == 0) {
-          ikey[p] = okey[u];
-        } else {
-          ikey[p] = k;
-          ival[p] = v;
+    if (skip) {
+      if (tid == 0) atomicOr(&st->overflow, 1ull);
+    } else {
+      const long long ib = (long long)gamma * (d - H + lo);  // image base (unwrapped new index)
+      bool bad = false;
+      for (int t = lo + (int)tid; t < hi; t += MIG_THREADS) {
+        if (key_o(t) == kEmpty || key_o(t - 1) != kEmpty) continue;  // not a cluster start
+        for (int u = t; u < hi; ++u) {
+          const u64 k = key_o(u);
+          if (k == kEmpty) break;
+          if (k == kTomb) continue;
+          const long long x = d - H + u;  // unwrapped old position
+          const u64 hn = home_of<LAYOUT>(T, k, crc_hi, crc_lo, log2_new);
+          const u64 oh = hn >> g;  // home in the old table
+          const u64 delta = ((u64)x - oh) & mask;
+          const long long nh =
+              (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
+          long long p = nh - ib;
+          while (p >= 0 && p < (long long)IW && key_i((uint32_t)p) != kEmpty) ++p;
+          if (p < 0 || p >= (long long)IW) {
+            bad = true;
+            break;
+          }
+          if (LAYOUT == 0) {
+            ikey[p] = okey[u];
+          } else {
+            ikey[p] = k;
+            ival[p] = oval[u];
+          }
         }
       }
+      if (bad) atomicOr(&st->overflow, 1ull);
     }
-    if (bad) atomicOr((unsigned long long *)&st->aux[0], 1ull);
     __syncthreads();
-    const uint32_t off = gamma * (uint32_t)(H - lo);
-    const u64 dst0 = (u64)d * gamma;
-    for (uint32_t t = threadIdx.x; t < gamma * mb; t += blockDim.x) {
-      if (LAYOUT == 0) {
-        const u64 w = ikey[off + t];
-        ((u64 *)new_cells)[dst0 + t] = w;
-        moved += (w != 0);
-      } else {
-        const u64x2 c = {ikey[off + t], ival[off + t]};
-        ((u64x2 *)new_cells)[dst0 + t] = c;
-        moved += (c.x != kEmpty);
+    if (!skip) {
+      const uint32_t off = gamma * (uint32_t)(H - lo);
+      const u64 dst0 = (u64)d * gamma;
+      for (uint32_t t = tid; t < gamma * mb; t += MIG_THREADS) {
+        if (LAYOUT == 0) {
+          const u64 w = ikey[off + t];
+          ((u64 *)new_cells)[dst0 + t] = w;
+          moved += (w != 0);
+        } else {
+          const u64x2 c = {ikey[off + t], ival[off + t]};
+          ((u64x2 *)new_cells)[dst0 + t] = c;
+          moved += (c.x != kEmpty);
+        }
       }
     }
     __syncthreads();
@@ -956,6 +1055,55 @@ static hipError_t launch_g(const BulkArgs &a, const LaunchCfg &cfg, hipStream_t 
   const size_t lds = (size_t)(cfg.block_threads / 64) * bulk_lds_bytes_per_wave(OP);
   hipLaunchKernelGGL((k_bulk<LAYOUT, OP, UP, G>), dim3(grid), dim3(cfg.block_threads), lds, s, a);
   return hipGetLastError();
+}
+
+template <int LAYOUT, int OP, int UP, int G>
+static hipError_t launch_mg(const BulkArgs *descs, const u64 *rs, uint32_t ndesc, u64 total,
+                            const LaunchCfg &cfg, hipStream_t s) {
+  const uint32_t grid = grid_for(total * 64, cfg);
+  const size_t lds = (size_t)(cfg.block_threads / 64) * bulk_lds_bytes_per_wave(OP);
+  hipLaunchKernelGGL((k_bulk_multi<LAYOUT, OP, UP, G>), dim3(grid), dim3(cfg.block_threads), lds, s,
+                     descs, rs, ndesc);
+  return hipGetLastError();
+}
+
+template <int LAYOUT, int OP, int UP>
+static hipError_t launch_mlo(const BulkArgs *d, const u64 *rs, uint32_t nd, u64 total,
+                             const LaunchCfg &cfg, hipStream_t s) {
+  switch (cfg.group_width) {
+    case 1: return launch_mg<LAYOUT, OP, UP, 1>(d, rs, nd, total, cfg, s);
+    case 2: return launch_mg<LAYOUT, OP, UP, 2>(d, rs, nd, total, cfg, s);
+    case 4: return launch_mg<LAYOUT, OP, UP, 4>(d, rs, nd, total, cfg, s);
+    case 8: return launch_mg<LAYOUT, OP, UP, 8>(d, rs, nd, total, cfg, s);
+    case 16: return launch_mg<LAYOUT, OP, UP, 16>(d, rs, nd, total, cfg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LAYOUT>
+static hipError_t launch_mlayout(OpKind op, uint32_t up, const BulkArgs *d, const u64 *rs, uint32_t nd,
+                                 u64 total, const LaunchCfg &cfg, hipStream_t s) {
+  switch (op) {
+    case OP_FIND: return launch_mlo<LAYOUT, OP_FIND, 0>(d, rs, nd, total, cfg, s);
+    case OP_INSERT: return launch_mlo<LAYOUT, OP_INSERT, 0>(d, rs, nd, total, cfg, s);
+    case OP_UPSERT:
+      return up ? launch_mlo<LAYOUT, OP_UPSERT, 1>(d, rs, nd, total, cfg, s)
+                : launch_mlo<LAYOUT, OP_UPSERT, 0>(d, rs, nd, total, cfg, s);
+    case OP_UPDATE:
+      return up ? launch_mlo<LAYOUT, OP_UPDATE, 1>(d, rs, nd, total, cfg, s)
+                : launch_mlo<LAYOUT, OP_UPDATE, 0>(d, rs, nd, total, cfg, s);
+    case OP_ERASE: return launch_mlo<LAYOUT, OP_ERASE, 0>(d, rs, nd, total, cfg, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_bulk_multi(OpKind op, uint32_t up, uint32_t layout, const BulkArgs *descs,
+                             const uint64_t *round_start, uint32_t ndesc, uint64_t total_rounds,
+                             const LaunchCfg &cfg, hipStream_t s) {
+  if (ndesc == 0 || total_rounds == 0) return hipSuccess;
+  const u64 *rs = (const u64 *)round_start;
+  return layout == 0 ? launch_mlayout<0>(op, up, descs, rs, ndesc, (u64)total_rounds, cfg, s)
+                     : launch_mlayout<1>(op, up, descs, rs, ndesc, (u64)total_rounds, cfg, s);
 }
 
 template <int LAYOUT, int OP, int UP>
@@ -1043,12 +1191,17 @@ hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_ce
     if (per_cu < 1) per_cu = 1;
     u64 grid = (u64)cfg.num_cus * per_cu;
     if (grid > nblocks) grid = nblocks;
-    if (layout == 0)
-      hipLaunchKernelGGL(k_migrate_lds<0>, dim3((uint32_t)grid), dim3(256), lds, s, old_cells, log2_old,
-                         new_cells, g, crc_hi, crc_lo, mb, st);
-    else
-      hipLaunchKernelGGL(k_migrate_lds<1>, dim3((uint32_t)grid), dim3(256), lds, s, old_cells, log2_old,
-                         new_cells, g, crc_hi, crc_lo, mb, st);
+#define LPHT_MIG_LAUNCH(L, Q)                                                                    \
+  hipLaunchKernelGGL((k_migrate_lds<L, Q>), dim3((uint32_t)grid), dim3(MIG_THREADS), lds, s, old_cells, \
+                     log2_old, new_cells, g, crc_hi, crc_lo, mb, st)
+    switch (mig_window(mb) / MIG_THREADS) {
+      case 2: if (layout == 0) LPHT_MIG_LAUNCH(0, 2); else LPHT_MIG_LAUNCH(1, 2); break;
+      case 3: if (layout == 0) LPHT_MIG_LAUNCH(0, 3); else LPHT_MIG_LAUNCH(1, 3); break;
+      case 5: if (layout == 0) LPHT_MIG_LAUNCH(0, 5); else LPHT_MIG_LAUNCH(1, 5); break;
+      case 9: if (layout == 0) LPHT_MIG_LAUNCH(0, 9); else LPHT_MIG_LAUNCH(1, 9); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef LPHT_MIG_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // fallback, a no-op unless a workgroup reported overflow

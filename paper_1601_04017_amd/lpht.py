@@ -74,6 +74,24 @@ class lpht_stats(ctypes.Structure):
     ]
 
 
+class lpht_batch_op(ctypes.Structure):
+    _fields_ = [
+        ("table", ctypes.c_void_p),
+        ("op", ctypes.c_uint32),
+        ("up", ctypes.c_uint32),
+        ("keys", ctypes.c_void_p),
+        ("vals", ctypes.c_void_p),
+        ("n", ctypes.c_uint64),
+        ("vals_out", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p),
+        ("kinds", ctypes.c_void_p),
+        ("kind_sel", ctypes.c_uint32),
+        ("count_sel", ctypes.c_uint32),
+    ]
+
+
+OP_FIND, OP_INSERT, OP_UPSERT, OP_UPDATE, OP_ERASE = 0, 1, 2, 3, 4
+
 # name -> (restype, argtypes); names are the C ABI's
 _VP = ctypes.c_void_p
 _U64 = ctypes.c_uint64
@@ -99,6 +117,9 @@ _SIGS = {
     "lpht_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_tuning)]),
     "lpht_set_timing": (ctypes.c_int, [_VP, ctypes.c_int]),
     "lpht_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_stats)]),
+    "lpht_batch_create": (ctypes.c_int, [_U32, ctypes.POINTER(_VP)]),
+    "lpht_batch_destroy": (ctypes.c_int, [_VP]),
+    "lpht_batch_run": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_batch_op), _U32, _VP]),
     "lpht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lpht_version": (ctypes.c_char_p, []),
 }
@@ -294,3 +315,44 @@ class Table:
         s = lpht_stats()
         _check(load().lpht_get_stats(self._h, ctypes.byref(s)), "lpht_get_stats")
         return {k: getattr(s, k) for k, _ in lpht_stats._fields_}
+
+
+class Batch:
+    """Descriptor staging context for lpht_batch_run."""
+
+    def __init__(self, max_ops: int = 256):
+        h = ctypes.c_void_p()
+        _check(load().lpht_batch_create(max_ops, ctypes.byref(h)), "lpht_batch_create")
+        self._h = h
+        self.max_ops = max_ops
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lpht_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, ops, stream=None):
+        """ops: list of dicts with keys table, op, up, keys, vals, vals_out,
+        flags, kinds, kind_sel (tensors or None)."""
+        arr = (lpht_batch_op * len(ops))()
+        for j, o in enumerate(ops):
+            t = o["table"]
+            keys = o["keys"]
+            arr[j].table = t._h
+            arr[j].op = o["op"]
+            arr[j].up = o.get("up", ASSIGN)
+            arr[j].keys = _ptr(keys)
+            arr[j].vals = _ptr(o.get("vals"))
+            arr[j].n = keys.numel()
+            arr[j].vals_out = _ptr(o.get("vals_out"))
+            arr[j].flags = _ptr(o.get("flags"))
+            arr[j].kinds = _ptr(o.get("kinds"))
+            arr[j].kind_sel = o.get("kind_sel", 0)
+            arr[j].count_sel = o.get("count_sel", 0)
+        _check(load().lpht_batch_run(self._h, arr, len(ops), _stream_handle(stream)), "lpht_batch_run")

@@ -103,6 +103,8 @@ def canonical_flags(keys: np.ndarray, flags: np.ndarray) -> np.ndarray:
     Asserts that no key carries more than one true flag."""
     keys = np.asarray(keys)
     flags = np.asarray(flags).astype(np.uint8).copy()
+    if keys.size == 0:
+        return flags
     truth = flags == 1
     order = np.argsort(keys, kind="stable")
     ks = keys[order]
