@@ -260,6 +260,97 @@ int lpht_batch_destroy(lpht_batch *b);
  * OOM (growth), DEVICE. */
 int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void *stream);
 
+/* ---- serving: a request loop over resident tables ----
+ *
+ * A server owns `ntables` tables kept on the device and a worker thread.
+ * Clients submit requests (from any thread); each request is a mixed batch of
+ * operations on one table, run in phase order: all finds (they see the table
+ * as it was when the request started), then all insert-or-increments (+1),
+ * then all erases.  The worker admits requests while request slots and the
+ * HBM budget allow, keeping per-table FIFO order (a table serves one request
+ * at a time; requests for other tables proceed meanwhile), and launches the
+ * admitted requests together:
+ *   LPHT_SERVE_WAVES  - continuous batching: all requests admitted at the same
+ *                       time form one wave, run as one multi-table launch per
+ *                       phase (lpht_batch_run); new requests are admitted and
+ *                       launched on another stream while earlier waves run;
+ *   LPHT_SERVE_SINGLE - the plain form: every request gets its own launches.
+ * Tables grow before a request's increments by the growth rule (bulk
+ * pre-growth, Sec. 5.5), which also removes tombstones (Sec. 5.4); the counts
+ * the rule needs are read back after every request without synchronising.
+ * Host buffers of a request should be pinned (hipHostMalloc); they must stay
+ * valid until the request completes. */
+#define LPHT_SERVE_WAVES 0u
+#define LPHT_SERVE_SINGLE 1u
+
+#define LPHT_KIND_FIND 0u
+#define LPHT_KIND_INCREMENT 1u
+#define LPHT_KIND_ERASE 2u
+
+typedef struct lpht_server_config {
+  uint32_t ntables;
+  uint32_t layout;                 /* LPHT_KV64 or LPHT_PACKED32 */
+  const uint32_t *log2_capacity;   /* host, ntables initial capacities (auto-growing tables) */
+  uint32_t mode;                   /* LPHT_SERVE_WAVES or LPHT_SERVE_SINGLE */
+  uint32_t max_inflight;           /* request slots, 1..4096 */
+  uint32_t streams;                /* device streams for launches, 1..8 */
+  uint32_t reserved;               /* must be 0 */
+  uint64_t hbm_budget;             /* bytes for tables, staging and growth; 0 = no limit */
+} lpht_server_config;
+
+typedef struct lpht_request {
+  uint32_t table;        /* 0..ntables-1 */
+  uint32_t reserved;     /* must be 0 */
+  uint64_t n;            /* operations, 1..2^31 */
+  const void *keys;      /* host, n keys */
+  const uint8_t *kinds;  /* host, n LPHT_KIND_* bytes */
+  void *vals_out;        /* host, n values: the found value for finds, else 0; may be NULL */
+  uint8_t *flags;        /* host, n flags (find: found; increment: inserted; erase: erased) */
+} lpht_request;
+
+typedef struct lpht_completion {
+  uint64_t ticket;
+  int status;            /* LPHT_OK, or LPHT_ERR_OOM when the request can never fit the budget */
+  uint32_t wave;         /* sequence number of the launch group that ran it */
+  double submit_us;      /* host steady clock, microseconds */
+  double admit_us;
+  double done_us;
+} lpht_completion;
+
+typedef struct lpht_server_stats {
+  uint64_t completed;
+  uint64_t waves;
+  uint64_t launches_phases;  /* phase launch groups issued */
+  uint64_t peak_hbm_bytes;   /* peak of tables + staging as accounted by admission */
+  uint64_t admission_waits;  /* times the head request waited for budget */
+  double busy_us;            /* time with at least one request on the device */
+} lpht_server_stats;
+
+typedef struct lpht_server lpht_server;
+
+int lpht_server_create(const lpht_server_config *cfg, lpht_server **out);
+/* Thread-safe, non-blocking.  Errors: INVALID. */
+int lpht_server_submit(lpht_server *srv, const lpht_request *req, uint64_t *ticket);
+/* LPHT_OK and *out filled when the request is done (the record is then
+ * released), 1 when it is still pending, INVALID for an unknown ticket. */
+int lpht_server_poll(lpht_server *srv, uint64_t ticket, lpht_completion *out);
+/* Blocks until the request is done. */
+int lpht_server_wait(lpht_server *srv, uint64_t ticket, lpht_completion *out);
+/* Blocks until every submitted request is done. */
+int lpht_server_drain(lpht_server *srv);
+/* The server's table `index` (use it only while the server is drained). */
+int lpht_server_table(lpht_server *srv, uint32_t index, lpht_table **out);
+int lpht_server_stats_get(lpht_server *srv, lpht_server_stats *out);
+/* Drains, stops the worker and destroys the tables. */
+int lpht_server_destroy(lpht_server *srv);
+
+/* Closed-loop driver: `nclients` clients, each submitting its next request
+ * when its previous one completes, walk through reqs[0..nreq) in order.
+ * Writes each request's completion to done[i] (latency = done_us -
+ * submit_us) and the wall time to *wall_us. */
+int lpht_server_run_closed_loop(lpht_server *srv, const lpht_request *reqs, uint32_t nreq,
+                                uint32_t nclients, lpht_completion *done, double *wall_us);
+
 /* Static description of an error code. */
 const char *lpht_strerror(int code);
 

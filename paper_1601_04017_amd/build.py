@@ -10,10 +10,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblpht.so")
-SOURCES = ["lpht_kernels.hip", "lpht_api.cpp"]
+SOURCES = ["lpht_kernels.hip", "lpht_api.cpp", "lpht_server.cpp"]
 ROOFLINE_OUT = os.path.join(PKG, "libroofline.so")
 ROOFLINE_SOURCES = ["lpht_roofline.hip"]
-HEADERS = ["lpht_internal.h", os.path.join("..", "..", "include", "lpht.h")]
+HEADERS = ["lpht_internal.h", "lpht_host.h", os.path.join("..", "..", "include", "lpht.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -24,6 +24,7 @@ FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
+    "-pthread",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

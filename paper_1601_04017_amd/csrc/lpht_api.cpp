@@ -9,8 +9,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/lpht.h"
-#include "lpht_internal.h"
+#include "lpht_host.h"
 
 using namespace lpht;
 
@@ -28,30 +27,14 @@ uint32_t crc0_bytes(uint64_t x, int nbytes) {
   return r;
 }
 
-struct Timing {
-  hipEvent_t start, stop;
-};
+
 
 }  // namespace
 
-struct lpht_table {
-  lpht_config cfg;
-  int device;
-  uint32_t log2c;
-  void *cells;
-  DevStatus *status;
-  uint32_t crc_hi, crc_lo;
-  // host view of the counts for the growth rule: exact at the last
-  // synchronisation, plus an upper bound of insertions since then
-  uint64_t known_used, known_live, pending;
-  lpht_tuning tuning;
-  LaunchCfg launch;
-  lpht_stats stats;
-  int timing;
-  std::vector<Timing> timed;
-};
 
-namespace {
+
+namespace lpht {
+namespace host {
 
 int from_hip(hipError_t e) {
   if (e == hipSuccess) return LPHT_OK;
@@ -88,13 +71,17 @@ hipMemPool_t device_pool(int dev) {
   return g_pools[dev];
 }
 
-void *dev_alloc(lpht_table *t, size_t bytes, hipStream_t s) {
-  if (t->cfg.alloc) return t->cfg.alloc(bytes, (void *)s, t->cfg.alloc_ctx);
-  hipMemPool_t pool = device_pool(t->device);
+void *pool_alloc(int device, size_t bytes, hipStream_t s) {
+  hipMemPool_t pool = device_pool(device);
   if (!pool) return nullptr;
   void *p = nullptr;
   if (hipMallocFromPoolAsync(&p, bytes, pool, s) != hipSuccess) return nullptr;
   return p;
+}
+
+void *dev_alloc(lpht_table *t, size_t bytes, hipStream_t s) {
+  if (t->cfg.alloc) return t->cfg.alloc(bytes, (void *)s, t->cfg.alloc_ctx);
+  return pool_alloc(t->device, bytes, s);
 }
 
 void dev_free(lpht_table *t, void *p, size_t bytes, hipStream_t s) {
@@ -155,12 +142,13 @@ int sync_counts(lpht_table *t, hipStream_t s) {
   t->known_used = u;
   t->known_live = l;
   t->pending = 0;
+  t->mods_since_exact = 0;
   return LPHT_OK;
 }
 
 // Replaces the cells by an all-empty table of 2^log2_new cells; `steps` is
 // the number of migrations of the growth rule this resize stands for.
-int resize_empty(lpht_table *t, uint32_t log2_new, hipStream_t s, uint32_t steps = 1) {
+int resize_empty(lpht_table *t, uint32_t log2_new, hipStream_t s, uint32_t steps) {
   const size_t nb = (size_t)cell_bytes(t->cfg.layout) << log2_new;
   void *nc = dev_alloc(t, nb, s);
   if (!nc) return LPHT_ERR_OOM;
@@ -175,6 +163,7 @@ int resize_empty(lpht_table *t, uint32_t log2_new, hipStream_t s, uint32_t steps
   t->log2c = log2_new;
   t->known_used = t->known_live = 0;
   t->pending = 0;
+  t->mods_since_exact = 0;
   t->stats.resizes += steps;
   return LPHT_OK;
 }
@@ -187,7 +176,7 @@ int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
   const size_t nb = (size_t)cell_bytes(t->cfg.layout) << log2_new;
   void *nc = dev_alloc(t, nb, s);
   if (!nc) return LPHT_ERR_OOM;
-  Timing tm{};
+  MigTiming tm{};
   if (t->timing) {
     if (hipEventCreate(&tm.start) != hipSuccess || hipEventCreate(&tm.stop) != hipSuccess)
       return LPHT_ERR_DEVICE;
@@ -214,6 +203,7 @@ int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
   t->log2c = log2_new;
   t->known_used = t->known_live;
   t->pending = 0;
+  t->mods_since_exact = 0;
   return LPHT_OK;
 }
 
@@ -239,9 +229,12 @@ int grow_before_batch(lpht_table *t, uint64_t b, hipStream_t s) {
     t->pending += b;
     return LPHT_OK;
   }
-  int rc = sync_counts(t, s);
-  if (rc) return rc;
-  t->stats.host_syncs++;
+  if (t->mods_since_exact != 0 || t->pending != 0) {
+    int rc = sync_counts(t, s);
+    if (rc) return rc;
+    t->stats.host_syncs++;
+  }
+  int rc = LPHT_OK;
   if (within_fill(t, t->known_used + b, c)) {
     t->pending = b;
     return LPHT_OK;
@@ -302,6 +295,7 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
     rc = grow_before_batch(t, n, s);
     if (rc) return rc;
   }
+  if (op != OP_FIND) t->mods_since_exact++;
   BulkArgs a = make_args(t);
   a.keys = keys;
   a.vals = vals;
@@ -318,19 +312,12 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
   return from_hip(launch_bulk(op, a, t->launch, s));
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace lpht
 
-struct lpht_batch {
-  static constexpr int kSlots = 16;
-  int device;
-  uint32_t max_ops;
-  size_t slot_bytes;
-  unsigned char *host[kSlots];  // pinned
-  unsigned char *dev[kSlots];
-  hipEvent_t ev[kSlots];
-  bool used[kSlots];
-  int next;
-};
+using namespace lpht::host;
+
+
 
 namespace {
 
@@ -459,6 +446,7 @@ int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void 
           if ((OpKind)o.op != op || o.table->cfg.layout != layout || o.n == 0) continue;
           if ((op == OP_UPSERT || op == OP_UPDATE) && o.up != up) continue;
           if (o.kinds && o.count_sel == 0) continue;
+          if (op != OP_FIND) o.table->mods_since_exact++;
           BulkArgs a = make_args(o.table);
           a.keys = o.keys;
           a.vals = o.vals;
@@ -566,6 +554,7 @@ int lpht_clear(lpht_table *t, void *stream) {
   if (e != hipSuccess) return from_hip(e);
   t->known_used = t->known_live = 0;
   t->pending = 0;
+  t->mods_since_exact = 0;
   return LPHT_OK;
 }
 
@@ -683,6 +672,7 @@ int lpht_status(lpht_table *t, void *stream) {
   t->known_used = u;
   t->known_live = l;
   t->pending = 0;
+  t->mods_since_exact = 0;
   if (h.err) {
     hipError_t e = launch_set_status(t->status, u, l, 1, s);
     if (e != hipSuccess) return from_hip(e);

@@ -76,6 +76,8 @@ hipError_t launch_bulk_multi(OpKind op, uint32_t up, uint32_t layout, const Bulk
 hipError_t launch_fill_zero(void *ptr, uint64_t bytes, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_set_status(DevStatus *st, uint64_t used, uint64_t live, int clear_err,
                              hipStream_t s);
+// out[0..2] = used, live, error bits of one table (out may be mapped host memory)
+hipError_t launch_count_totals(const DevStatus *st, uint64_t *out, hipStream_t s);
 hipError_t launch_recount(const void *cells, uint32_t log2c, uint32_t layout, DevStatus *st,
                           const LaunchCfg &cfg, hipStream_t s);
 // Block-parallel cluster migration of `old_cells` (2^log2_old cells) into

@@ -795,6 +795,21 @@ __global__ void k_fill_zero_if(u64x2 *p, u64 n16, DevStatus *st) {
     __builtin_nontemporal_store(z, p + i);
 }
 
+// Sums the count slots of one table into out[0] (used), out[1] (live) and
+// out[2] (error bits); `out` may be host memory mapped for the device.
+__global__ void k_count_totals(const DevStatus *st, u64 *out) {
+  const uint32_t t = threadIdx.x;
+  long long u = (t < kCountSlots) ? (long long)st->slot[t].used : 0;
+  long long l = (t < kCountSlots) ? (long long)st->slot[t].live : 0;
+  u = wave_sum(u);
+  l = wave_sum(l);
+  if (t == 0) {
+    out[0] = (u64)u;
+    out[1] = (u64)l;
+    out[2] = st->err;
+  }
+}
+
 template <int LAYOUT>
 __global__ void k_recount(const void *cells, u64 cap, DevStatus *st) {
   __shared__ long long s_acc[2];
@@ -1158,6 +1173,11 @@ hipError_t launch_fill_zero(void *ptr, uint64_t bytes, const LaunchCfg &cfg, hip
 hipError_t launch_set_status(DevStatus *st, uint64_t used, uint64_t live, int clear_err,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, st, (u64)used, (u64)live, clear_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_totals(const DevStatus *st, uint64_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_totals, dim3(1), dim3(64), 0, s, st, (u64 *)out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,562 @@
+// Serving runtime of liblpht: a request loop over tables kept resident on
+// one device.  See the "serving" part of include/lpht.h for the contract.
+//
+// One worker thread owns every HIP call of the server.  It admits requests
+// (request slots, one request per table at a time in submission order, HBM
+// budget), launches them (as one multi-table wave per admission round, or one
+// request at a time), and retires launch groups whose completion event has
+// fired.  After each group a one-wave kernel writes every touched table's
+// exact counts into pinned host memory, so the growth rule that runs before
+// the next request on that table decides on exact counts with no stream
+// synchronisation.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lpht_host.h"
+
+using namespace lpht;
+using namespace lpht::host;
+
+namespace {
+
+double now_us() {
+  return std::chrono::duration<double, std::micro>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Req {
+  lpht_request r;
+  uint32_t count[3];  // operations per kind
+  lpht_completion c;
+  bool done = false;
+  void *dbuf = nullptr;
+  size_t dbytes = 0;
+  uint64_t need = 0;  // bytes accounted by admission (staging and growth)
+};
+
+struct Group {
+  std::vector<Req *> reqs;
+  std::vector<uint32_t> tables;
+  hipEvent_t ev;
+  uint32_t stream;
+};
+
+}  // namespace
+
+struct lpht_server {
+  lpht_server_config cfg;
+  int device = 0;
+  uint32_t kb = 8;
+  std::vector<lpht_table *> tables;
+  // count readback areas, one per stream (a stream's groups copy its whole
+  // area; a table's entry is only read back after the group that wrote it):
+  // [stream][table][used, live, err, pad]
+  uint64_t *totals = nullptr;    // pinned
+  uint64_t *d_totals = nullptr;  // device, written by the count kernel
+  std::vector<uint8_t> busy;
+  std::vector<std::deque<Req *>> fifo;
+  std::deque<Req *> incoming;
+  std::unordered_map<uint64_t, Req *> reqs;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::vector<hipStream_t> streams;
+  std::vector<lpht_batch *> batches;
+  std::vector<Group> inflight;
+  std::vector<hipEvent_t> spare_events;
+  uint64_t next_ticket = 1;
+  uint64_t outstanding = 0;  // submitted, not done (under mu)
+  uint32_t inflight_reqs = 0;
+  uint64_t staging_bytes = 0;
+  lpht_server_stats st{};
+  double busy_since = 0;
+  bool stop = false;
+  uint32_t next_stream = 0;
+  uint32_t group_seq = 0;
+  std::thread worker;
+};
+
+namespace {
+
+uint64_t table_bytes(const lpht_server *S) {
+  uint64_t b = 0;
+  for (auto *t : S->tables) b += cell_bytes(t->cfg.layout) << t->log2c;
+  return b;
+}
+
+// Bytes a growth before `b` insertions would allocate for the new table.
+uint64_t growth_bytes(const lpht_table *t, uint64_t b) {
+  const uint64_t c = 1ull << t->log2c;
+  if (b == 0 || within_fill(t, t->known_used + t->pending + b, c)) return 0;
+  uint32_t target = t->log2c;
+  if ((unsigned __int128)(t->known_live + b) * 2 * t->cfg.max_fill_den >
+      (unsigned __int128)c * t->cfg.max_fill_num) {
+    do {
+      ++target;
+    } while (target < 34 && !within_fill(t, t->known_live + b, 1ull << target));
+  }
+  // the old and the new table coexist during a migration; a chain of
+  // doublings peaks at the last one
+  return cell_bytes(t->cfg.layout) << target;
+}
+
+size_t staging_size(const lpht_server *S, const Req *q) {
+  const size_t n = q->r.n;
+  return 2 * round256(n * S->kb) + 2 * round256(n);
+}
+
+void finish_locked(lpht_server *S, Req *q) {
+  q->done = true;
+  S->outstanding--;
+  S->st.completed++;
+}
+
+hipEvent_t get_event(lpht_server *S) {
+  if (!S->spare_events.empty()) {
+    hipEvent_t e = S->spare_events.back();
+    S->spare_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launches one group of admitted requests on the next stream.
+void launch_group(lpht_server *S, std::vector<Req *> &group) {
+  const uint32_t si = S->next_stream++ % (uint32_t)S->streams.size();
+  hipStream_t s = S->streams[si];
+  Group g;
+  g.ev = get_event(S);
+  std::vector<lpht_batch_op> ops;
+  ops.reserve(3 * group.size());
+  const double t_admit = now_us();
+  for (Req *q : group) {
+    q->c.admit_us = t_admit;
+    q->c.wave = S->group_seq;
+    const size_t n = q->r.n;
+    q->dbytes = staging_size(S, q);
+    q->dbuf = pool_alloc(S->device, q->dbytes, s);
+    unsigned char *base = (unsigned char *)q->dbuf;
+    void *dkeys = base;
+    void *dvals = base + round256(n * S->kb);
+    uint8_t *dkinds = base + 2 * round256(n * S->kb);
+    uint8_t *dflags = dkinds + round256(n);
+    lpht_table *t = S->tables[q->r.table];
+    g.tables.push_back(q->r.table);
+    g.reqs.push_back(q);
+    if (!q->dbuf) {
+      q->c.status = LPHT_ERR_OOM;
+      continue;
+    }
+    (void)hipMemcpyAsync(dkeys, q->r.keys, n * S->kb, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(dkinds, q->r.kinds, n, hipMemcpyHostToDevice, s);
+    const uint32_t kind_op[3] = {LPHT_OP_FIND, LPHT_OP_UPSERT, LPHT_OP_ERASE};
+    for (uint32_t k = 0; k < 3; ++k) {
+      if (q->count[k] == 0) continue;
+      lpht_batch_op o{};
+      o.table = t;
+      o.op = kind_op[k];
+      o.up = LPHT_ADD;
+      o.keys = dkeys;
+      o.vals = nullptr;  // increments by one
+      o.n = n;
+      o.vals_out = k == 0 ? dvals : nullptr;
+      o.flags = dflags;
+      o.kinds = dkinds;
+      o.kind_sel = k;
+      o.count_sel = q->count[k];
+      ops.push_back(o);
+    }
+  }
+  if (!ops.empty()) {
+    const int rc = lpht_batch_run(S->batches[si], ops.data(), (uint32_t)ops.size(), (void *)s);
+    S->st.launches_phases += 1;
+    if (rc != LPHT_OK)
+      for (Req *q : group)
+        if (q->c.status == LPHT_OK) q->c.status = rc;
+  }
+  const size_t area = 4 * S->tables.size();
+  for (uint32_t ti : g.tables)
+    (void)launch_count_totals(S->tables[ti]->status, S->d_totals + si * area + 4 * ti, s);
+  (void)hipMemcpyAsync(S->totals + si * area, S->d_totals + si * area, sizeof(uint64_t) * area,
+                       hipMemcpyDeviceToHost, s);
+  g.stream = si;
+  for (Req *q : group) {
+    if (!q->dbuf) continue;
+    const size_t n = q->r.n;
+    unsigned char *base = (unsigned char *)q->dbuf;
+    if (q->r.vals_out && q->count[0])
+      (void)hipMemcpyAsync(q->r.vals_out, base + round256(n * S->kb), n * S->kb,
+                           hipMemcpyDeviceToHost, s);
+    if (q->r.flags)
+      (void)hipMemcpyAsync(q->r.flags, base + 2 * round256(n * S->kb) + round256(n), n,
+                           hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(q->dbuf, s);
+    q->dbuf = nullptr;
+  }
+  (void)hipEventRecord(g.ev, s);
+  if (S->inflight.empty()) S->busy_since = now_us();
+  S->inflight_reqs += (uint32_t)group.size();
+  S->group_seq++;
+  S->st.waves++;
+  S->inflight.push_back(std::move(g));
+}
+
+void retire_group(lpht_server *S, Group &g) {
+  const double t = now_us();
+  for (uint32_t ti : g.tables) {
+    lpht_table *T = S->tables[ti];
+    const uint64_t *tot = S->totals + g.stream * 4 * S->tables.size() + 4 * ti;
+    T->known_used = tot[0];
+    T->known_live = tot[1];
+    T->pending = 0;
+    T->mods_since_exact = 0;
+    S->busy[ti] = 0;
+  }
+  for (Req *q : g.reqs) {
+    if (q->r.vals_out && q->count[0] == 0) std::memset(q->r.vals_out, 0, q->r.n * S->kb);
+    q->c.done_us = t;
+    S->staging_bytes -= q->need;
+  }
+  S->inflight_reqs -= (uint32_t)g.reqs.size();
+  S->spare_events.push_back(g.ev);
+  if (S->inflight.size() == 1) S->st.busy_us += t - S->busy_since;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (Req *q : g.reqs) finish_locked(S, q);
+  }
+  S->cv_done.notify_all();
+}
+
+// Picks requests to start now: oldest first among tables that are idle, while
+// slots and the HBM budget allow.
+void admit(lpht_server *S, std::vector<Req *> &out) {
+  std::vector<uint32_t> cand;
+  for (uint32_t t = 0; t < S->fifo.size(); ++t)
+    if (!S->busy[t] && !S->fifo[t].empty()) cand.push_back(t);
+  std::sort(cand.begin(), cand.end(), [&](uint32_t a, uint32_t b) {
+    return S->fifo[a].front()->c.ticket < S->fifo[b].front()->c.ticket;
+  });
+  uint64_t hbm = table_bytes(S) + S->staging_bytes;
+  for (uint32_t t : cand) {
+    if (S->inflight_reqs + out.size() >= S->cfg.max_inflight) break;
+    Req *q = S->fifo[t].front();
+    const uint64_t need = staging_size(S, q) + growth_bytes(S->tables[t], q->count[1]);
+    if (S->cfg.hbm_budget && hbm + need > S->cfg.hbm_budget) {
+      if (S->inflight.empty() && out.empty()) {
+        // nothing will free memory: this request can never run
+        S->fifo[t].pop_front();
+        q->c.status = LPHT_ERR_OOM;
+        q->c.admit_us = q->c.done_us = now_us();
+        {
+          std::lock_guard<std::mutex> lk(S->mu);
+          finish_locked(S, q);
+        }
+        S->cv_done.notify_all();
+        continue;
+      }
+      S->st.admission_waits++;
+      break;  // keep the order: the oldest waiting request goes first
+    }
+    S->fifo[t].pop_front();
+    S->busy[t] = 1;
+    q->need = need;
+    hbm += need;
+    S->staging_bytes += need;
+    out.push_back(q);
+  }
+  if (hbm > S->st.peak_hbm_bytes) S->st.peak_hbm_bytes = hbm;
+}
+
+void worker_loop(lpht_server *S) {
+  (void)hipSetDevice(S->device);
+  std::vector<Req *> admitted;
+  while (true) {
+    bool progressed = false;
+    for (size_t w = 0; w < S->inflight.size();) {
+      if (hipEventQuery(S->inflight[w].ev) == hipSuccess) {
+        retire_group(S, S->inflight[w]);
+        S->inflight.erase(S->inflight.begin() + w);
+        progressed = true;
+      } else {
+        ++w;
+      }
+    }
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      while (!S->incoming.empty()) {
+        Req *q = S->incoming.front();
+        S->incoming.pop_front();
+        S->fifo[q->r.table].push_back(q);
+      }
+      if (S->stop && S->outstanding == 0 && S->inflight.empty()) break;
+    }
+    admitted.clear();
+    admit(S, admitted);
+    if (!admitted.empty()) {
+      progressed = true;
+      if (S->cfg.mode == LPHT_SERVE_WAVES) {
+        launch_group(S, admitted);
+      } else {
+        for (Req *q : admitted) {
+          std::vector<Req *> one{q};
+          launch_group(S, one);
+        }
+      }
+    }
+    if (!progressed) {
+      if (S->inflight.empty()) {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_work.wait_for(lk, std::chrono::milliseconds(2),
+                            [&] { return S->stop || !S->incoming.empty(); });
+      } else {
+        std::this_thread::yield();
+      }
+    }
+  }
+}
+
+void destroy_all(lpht_server *S) {
+  for (auto *b : S->batches) lpht_batch_destroy(b);
+  for (auto *t : S->tables) lpht_destroy(t, S->streams.empty() ? nullptr : (void *)S->streams[0]);
+  for (auto s : S->streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  for (auto e : S->spare_events) (void)hipEventDestroy(e);
+  if (S->totals) (void)hipHostFree(S->totals);
+  if (S->d_totals) (void)hipFree(S->d_totals);
+  for (auto &kv : S->reqs) delete kv.second;
+  delete S;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lpht_server_create(const lpht_server_config *cfg, lpht_server **out) {
+  if (!out) return LPHT_ERR_INVALID;
+  *out = nullptr;
+  if (!cfg || cfg->ntables == 0 || cfg->ntables > 65536 || !cfg->log2_capacity) return LPHT_ERR_INVALID;
+  if (cfg->layout != LPHT_KV64 && cfg->layout != LPHT_PACKED32) return LPHT_ERR_INVALID;
+  if (cfg->mode > LPHT_SERVE_SINGLE || cfg->max_inflight < 1 || cfg->max_inflight > 4096) return LPHT_ERR_INVALID;
+  if (cfg->streams < 1 || cfg->streams > 8 || cfg->reserved) return LPHT_ERR_INVALID;
+  lpht_server *S = new (std::nothrow) lpht_server();
+  if (!S) return LPHT_ERR_OOM;
+  S->cfg = *cfg;
+  S->cfg.log2_capacity = nullptr;
+  S->kb = cfg->layout == LPHT_PACKED32 ? 4 : 8;
+  if (hipGetDevice(&S->device) != hipSuccess) {
+    delete S;
+    return LPHT_ERR_DEVICE;
+  }
+  for (uint32_t i = 0; i < cfg->streams; ++i) {
+    hipStream_t s;
+    lpht_batch *b = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      destroy_all(S);
+      return LPHT_ERR_DEVICE;
+    }
+    S->streams.push_back(s);
+    const int rc = lpht_batch_create(3 * cfg->max_inflight, &b);
+    if (rc) {
+      destroy_all(S);
+      return rc;
+    }
+    S->batches.push_back(b);
+  }
+  const size_t tot_bytes = sizeof(uint64_t) * 4 * cfg->ntables * cfg->streams;
+  if (hipHostMalloc((void **)&S->totals, tot_bytes, hipHostMallocDefault) != hipSuccess) {
+    destroy_all(S);
+    return LPHT_ERR_OOM;
+  }
+  std::memset(S->totals, 0, tot_bytes);
+  if (hipMalloc((void **)&S->d_totals, tot_bytes) != hipSuccess ||
+      hipMemset(S->d_totals, 0, tot_bytes) != hipSuccess) {
+    destroy_all(S);
+    return LPHT_ERR_OOM;
+  }
+  for (uint32_t i = 0; i < cfg->ntables; ++i) {
+    lpht_config tc;
+    lpht_config_default(&tc);
+    tc.layout = cfg->layout;
+    tc.log2_capacity = cfg->log2_capacity[i];
+    tc.auto_grow = 1;
+    lpht_table *t = nullptr;
+    const int rc = lpht_create(&tc, (void *)S->streams[0], &t);
+    if (rc) {
+      destroy_all(S);
+      return rc;
+    }
+    S->tables.push_back(t);
+  }
+  if (hipStreamSynchronize(S->streams[0]) != hipSuccess) {
+    destroy_all(S);
+    return LPHT_ERR_DEVICE;
+  }
+  S->busy.assign(cfg->ntables, 0);
+  S->fifo.resize(cfg->ntables);
+  S->worker = std::thread(worker_loop, S);
+  *out = S;
+  return LPHT_OK;
+}
+
+int lpht_server_submit(lpht_server *S, const lpht_request *req, uint64_t *ticket) {
+  if (!S || !req || !ticket) return LPHT_ERR_INVALID;
+  if (req->table >= S->tables.size() || req->reserved || req->n == 0 || req->n > (1ull << 31) ||
+      !req->keys || !req->kinds)
+    return LPHT_ERR_INVALID;
+  Req *q = new (std::nothrow) Req();
+  if (!q) return LPHT_ERR_OOM;
+  q->r = *req;
+  q->count[0] = q->count[1] = q->count[2] = 0;
+  for (uint64_t i = 0; i < req->n; ++i) {
+    const uint8_t k = req->kinds[i];
+    if (k > 2) {
+      delete q;
+      return LPHT_ERR_INVALID;
+    }
+    q->count[k]++;
+  }
+  q->c = lpht_completion{};
+  q->c.submit_us = now_us();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) {
+      delete q;
+      return LPHT_ERR_INVALID;
+    }
+    q->c.ticket = S->next_ticket++;
+    S->reqs[q->c.ticket] = q;
+    S->incoming.push_back(q);
+    S->outstanding++;
+    *ticket = q->c.ticket;
+  }
+  S->cv_work.notify_one();
+  return LPHT_OK;
+}
+
+int lpht_server_poll(lpht_server *S, uint64_t ticket, lpht_completion *out) {
+  if (!S) return LPHT_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return LPHT_ERR_INVALID;
+  if (!it->second->done) return 1;
+  if (out) *out = it->second->c;
+  delete it->second;
+  S->reqs.erase(it);
+  return LPHT_OK;
+}
+
+int lpht_server_wait(lpht_server *S, uint64_t ticket, lpht_completion *out) {
+  if (!S) return LPHT_ERR_INVALID;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return LPHT_ERR_INVALID;
+  Req *q = it->second;
+  S->cv_done.wait(lk, [&] { return q->done; });
+  if (out) *out = q->c;
+  delete q;
+  S->reqs.erase(it);
+  return LPHT_OK;
+}
+
+int lpht_server_drain(lpht_server *S) {
+  if (!S) return LPHT_ERR_INVALID;
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->cv_done.wait(lk, [&] { return S->outstanding == 0; });
+  return LPHT_OK;
+}
+
+int lpht_server_table(lpht_server *S, uint32_t index, lpht_table **out) {
+  if (!S || !out || index >= S->tables.size()) return LPHT_ERR_INVALID;
+  *out = S->tables[index];
+  return LPHT_OK;
+}
+
+int lpht_server_stats_get(lpht_server *S, lpht_server_stats *out) {
+  if (!S || !out) return LPHT_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  *out = S->st;
+  return LPHT_OK;
+}
+
+int lpht_server_destroy(lpht_server *S) {
+  if (!S) return LPHT_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  destroy_all(S);
+  return LPHT_OK;
+}
+
+int lpht_server_run_closed_loop(lpht_server *S, const lpht_request *reqs, uint32_t nreq,
+                                uint32_t nclients, lpht_completion *done, double *wall_us) {
+  if (!S || (nreq && (!reqs || !done)) || nclients == 0) return LPHT_ERR_INVALID;
+  std::vector<uint64_t> tickets(nreq, 0);
+  std::vector<uint32_t> open;  // request indices in flight
+  uint32_t next = 0, finished = 0;
+  const double t0 = now_us();
+  auto submit_next = [&]() -> int {
+    uint64_t tk = 0;
+    const int rc = lpht_server_submit(S, &reqs[next], &tk);
+    if (rc) return rc;
+    tickets[next] = tk;
+    open.push_back(next);
+    ++next;
+    return LPHT_OK;
+  };
+  while (next < nreq && open.size() < nclients) {
+    const int rc = submit_next();
+    if (rc) return rc;
+  }
+  while (finished < nreq) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_done.wait(lk, [&] {
+        for (uint32_t i : open)
+          if (S->reqs[tickets[i]]->done) return true;
+        return false;
+      });
+    }
+    std::vector<uint32_t> still;
+    std::vector<uint32_t> fin;
+    for (uint32_t i : open) {
+      lpht_completion c;
+      const int rc = lpht_server_poll(S, tickets[i], &c);
+      if (rc == LPHT_OK) {
+        done[i] = c;
+        fin.push_back(i);
+      } else {
+        still.push_back(i);
+      }
+    }
+    open.swap(still);
+    finished += (uint32_t)fin.size();
+    for (size_t k = 0; k < fin.size() && next < nreq; ++k) {
+      const int rc = submit_next();
+      if (rc) return rc;
+    }
+  }
+  if (wall_us) *wall_us = now_us() - t0;
+  return LPHT_OK;
+}
+
+}  // extern "C"

@@ -356,3 +356,167 @@ class Batch:
             arr[j].kind_sel = o.get("kind_sel", 0)
             arr[j].count_sel = o.get("count_sel", 0)
         _check(load().lpht_batch_run(self._h, arr, len(ops), _stream_handle(stream)), "lpht_batch_run")
+
+
+# ---------------------------------------------------------------- serving
+
+SERVE_WAVES = 0
+SERVE_SINGLE = 1
+KIND_FIND, KIND_INCREMENT, KIND_ERASE = 0, 1, 2
+
+
+class lpht_server_config(ctypes.Structure):
+    _fields_ = [
+        ("ntables", ctypes.c_uint32),
+        ("layout", ctypes.c_uint32),
+        ("log2_capacity", ctypes.POINTER(ctypes.c_uint32)),
+        ("mode", ctypes.c_uint32),
+        ("max_inflight", ctypes.c_uint32),
+        ("streams", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("hbm_budget", ctypes.c_uint64),
+    ]
+
+
+class lpht_request(ctypes.Structure):
+    _fields_ = [
+        ("table", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("n", ctypes.c_uint64),
+        ("keys", ctypes.c_void_p),
+        ("kinds", ctypes.c_void_p),
+        ("vals_out", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p),
+    ]
+
+
+class lpht_completion(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("status", ctypes.c_int),
+        ("wave", ctypes.c_uint32),
+        ("submit_us", ctypes.c_double),
+        ("admit_us", ctypes.c_double),
+        ("done_us", ctypes.c_double),
+    ]
+
+
+class lpht_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("completed", ctypes.c_uint64),
+        ("waves", ctypes.c_uint64),
+        ("launches_phases", ctypes.c_uint64),
+        ("peak_hbm_bytes", ctypes.c_uint64),
+        ("admission_waits", ctypes.c_uint64),
+        ("busy_us", ctypes.c_double),
+    ]
+
+
+_SIGS.update({
+    "lpht_server_create": (ctypes.c_int, [ctypes.POINTER(lpht_server_config), ctypes.POINTER(_VP)]),
+    "lpht_server_submit": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_request), ctypes.POINTER(_U64)]),
+    "lpht_server_poll": (ctypes.c_int, [_VP, _U64, ctypes.POINTER(lpht_completion)]),
+    "lpht_server_wait": (ctypes.c_int, [_VP, _U64, ctypes.POINTER(lpht_completion)]),
+    "lpht_server_drain": (ctypes.c_int, [_VP]),
+    "lpht_server_table": (ctypes.c_int, [_VP, _U32, ctypes.POINTER(_VP)]),
+    "lpht_server_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_server_stats)]),
+    "lpht_server_destroy": (ctypes.c_int, [_VP]),
+    "lpht_server_run_closed_loop": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_request), _U32, _U32,
+                                                   ctypes.POINTER(lpht_completion),
+                                                   ctypes.POINTER(ctypes.c_double)]),
+})
+
+
+class _TableView(Table):
+    """A table owned by a server (not destroyed by Python)."""
+
+    def __init__(self, handle, layout):
+        import torch
+        self._h = handle
+        self.layout = layout
+        self.word = 4 if layout == PACKED32 else 8
+        self.torch_dtype = torch.int32 if layout == PACKED32 else torch.int64
+        self._stream = None
+
+    def close(self, stream=None):
+        self._h = None
+
+
+class Server:
+    """Request loop over resident tables (lpht_server_*).  Requests carry
+    host arrays; they are copied into pinned buffers owned by this object."""
+
+    def __init__(self, log2_caps, layout=KV64, mode=SERVE_WAVES, max_inflight=64, streams=2,
+                 hbm_budget=0):
+        L = load()
+        self.layout = layout
+        self.kdt = "uint32" if layout == PACKED32 else "uint64"
+        caps = (ctypes.c_uint32 * len(log2_caps))(*log2_caps)
+        cfg = lpht_server_config(len(log2_caps), layout, caps, mode, max_inflight, streams, 0, hbm_budget)
+        h = ctypes.c_void_p()
+        _check(L.lpht_server_create(ctypes.byref(cfg), ctypes.byref(h)), "lpht_server_create")
+        self._h = h
+        self.ntables = len(log2_caps)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lpht_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def make_requests(self, reqs):
+        """reqs: list of (table, keys ndarray, kinds ndarray).  Returns
+        (ctypes request array, list of (vals, flags) pinned output tensors,
+        buffers to keep alive)."""
+        import numpy as np
+        import torch
+        arr = (lpht_request * len(reqs))()
+        outs, keep = [], []
+        kdt = torch.int32 if self.layout == PACKED32 else torch.int64
+        for j, (tab, keys, kinds) in enumerate(reqs):
+            n = len(keys)
+            kview = np.ascontiguousarray(keys).view(np.int32 if self.layout == PACKED32 else np.int64)
+            k = torch.from_numpy(kview).pin_memory()
+            kd = torch.from_numpy(np.ascontiguousarray(kinds, dtype=np.uint8)).pin_memory()
+            v = torch.empty(n, dtype=kdt).pin_memory()
+            f = torch.empty(n, dtype=torch.uint8).pin_memory()
+            arr[j] = lpht_request(tab, 0, n, k.data_ptr(), kd.data_ptr(), v.data_ptr(), f.data_ptr())
+            outs.append((v, f))
+            keep += [k, kd]
+        return arr, outs, keep
+
+    def run_closed_loop(self, req_array, nclients):
+        n = len(req_array)
+        done = (lpht_completion * n)()
+        wall = ctypes.c_double()
+        _check(load().lpht_server_run_closed_loop(self._h, req_array, n, nclients, done,
+                                                  ctypes.byref(wall)), "lpht_server_run_closed_loop")
+        return done, wall.value
+
+    def submit(self, req):
+        t = ctypes.c_uint64()
+        _check(load().lpht_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "lpht_server_submit")
+        return t.value
+
+    def wait(self, ticket):
+        c = lpht_completion()
+        _check(load().lpht_server_wait(self._h, ticket, ctypes.byref(c)), "lpht_server_wait")
+        return c
+
+    def drain(self):
+        _check(load().lpht_server_drain(self._h), "lpht_server_drain")
+
+    def table(self, i):
+        h = ctypes.c_void_p()
+        _check(load().lpht_server_table(self._h, i, ctypes.byref(h)), "lpht_server_table")
+        return _TableView(h, self.layout)
+
+    def stats(self):
+        s = lpht_server_stats()
+        _check(load().lpht_server_stats_get(self._h, ctypes.byref(s)), "lpht_server_stats_get")
+        return {k: getattr(s, k) for k, _ in lpht_server_stats._fields_}

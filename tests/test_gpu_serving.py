@@ -1,0 +1,142 @@
+"""The serving runtime: mixed requests (finds, insert-or-increments, erases in
+phase order) through the request loop, checked against the oracle replaying
+each table's requests in submission order; every result is the same whether a
+request runs in a wave with many others or strictly alone; admission under a
+tight HBM budget."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_04017_amd import inputs
+from tests import helpers as H
+from tests.gpu_util import cells_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def _trace(ntables, nreq, seed, lo=64, hi=30000, universe=50000):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for r in range(nreq):
+        tab = int(rng.integers(0, ntables))
+        n = int(np.clip(np.exp(rng.normal(np.log(3000), 1.2)), lo, hi))
+        keys = inputs.zipf_keys_u64(n, universe, 1.0, seed=seed * 1000 + r)
+        kinds = rng.choice(np.array([0, 1, 2], np.uint8), size=n, p=[0.6, 0.3, 0.1])
+        reqs.append((tab, keys, kinds))
+    return reqs
+
+
+def _run(caps, reqs, mode, max_inflight, nclients, budget=0, streams=2):
+    from paper_1601_04017_amd import lpht
+    srv = lpht.Server(caps, mode=mode, max_inflight=max_inflight, streams=streams, hbm_budget=budget)
+    arr, outs, keep = srv.make_requests(reqs)
+    done, wall = srv.run_closed_loop(arr, nclients)
+    res = [(o[0].numpy().view(np.uint64).copy(), o[1].numpy().copy()) for o in outs]
+    comps = [(d.status, d.wave, d.submit_us, d.admit_us, d.done_us) for d in done]
+    cells = [cells_host(srv.table(i)) for i in range(len(caps))]
+    counts = [srv.table(i).count() for i in range(len(caps))]
+    capsz = [srv.table(i).capacity for i in range(len(caps))]
+    stats = srv.stats()
+    srv.close()
+    return res, comps, cells, counts, capsz, stats
+
+
+def _oracle_replay(caps, reqs):
+    orcs = [oracle.OracleTable(oracle.KV64, c, auto_grow=True) for c in caps]
+    out = []
+    for tab, keys, kinds in reqs:
+        o = orcs[tab]
+        m0, m1, m2 = kinds == 0, kinds == 1, kinds == 2
+        vals = np.zeros(keys.size, np.uint64)
+        flags = np.zeros(keys.size, np.uint8)
+        v, f = o.find(keys[m0])
+        vals[m0], flags[m0] = v, f
+        flags[m1] = o.insert_or_update(keys[m1], None, oracle.ADD)
+        flags[m2] = o.erase(keys[m2])
+        out.append((vals, flags))
+    return out, orcs
+
+
+def _check_same(reqs, a, b):
+    for (tab, keys, kinds), (va, fa), (vb, fb) in zip(reqs, a, b):
+        m0 = kinds == 0
+        assert np.array_equal(va, vb)
+        assert np.array_equal(fa[m0], fb[m0])
+        for m in (kinds == 1, kinds == 2):
+            assert np.array_equal(H.canonical_flags(keys[m], fa[m]), H.canonical_flags(keys[m], fb[m]))
+
+
+CAPS = [10, 11, 12, 13, 14, 12, 10, 16]
+
+
+def test_serving_waves_match_oracle():
+    from paper_1601_04017_amd import lpht
+    reqs = _trace(len(CAPS), 120, seed=5)
+    res, comps, cells, counts, capsz, stats = _run(CAPS, reqs, lpht.SERVE_WAVES, 32, 24)
+    assert all(c[0] == 0 for c in comps)
+    ref, orcs = _oracle_replay(CAPS, reqs)
+    _check_same(reqs, res, ref)
+    for i, o in enumerate(orcs):
+        assert counts[i] == o.counts()
+        assert capsz[i] == o.capacity
+        H.assert_same_table_modulo_run_order(cells[i], o.cells(), oracle.KV64)
+    # several requests shared launch groups
+    assert stats["waves"] < len(reqs)
+    assert stats["completed"] == len(reqs)
+
+
+def test_serving_alone_equals_mix():
+    from paper_1601_04017_amd import lpht
+    reqs = _trace(len(CAPS), 100, seed=9)
+    mix, cm, cells_m, counts_m, caps_m, st_m = _run(CAPS, reqs, lpht.SERVE_WAVES, 64, 64, streams=4)
+    alone, ca, cells_a, counts_a, caps_a, st_a = _run(CAPS, reqs, lpht.SERVE_SINGLE, 1, 1, streams=1)
+    assert st_a["waves"] == len(reqs)
+    _check_same(reqs, mix, alone)
+    assert counts_m == counts_a and caps_m == caps_a
+    for i in range(len(CAPS)):
+        H.assert_same_table_modulo_run_order(cells_m[i], cells_a[i], oracle.KV64)
+
+
+def test_serving_single_mode_many_in_flight():
+    from paper_1601_04017_amd import lpht
+    reqs = _trace(len(CAPS), 80, seed=13)
+    res, comps, cells, counts, capsz, stats = _run(CAPS, reqs, lpht.SERVE_SINGLE, 16, 16, streams=3)
+    ref, orcs = _oracle_replay(CAPS, reqs)
+    _check_same(reqs, res, ref)
+    for i, o in enumerate(orcs):
+        assert counts[i] == o.counts()
+
+
+def test_serving_tight_budget_admission_waits():
+    from paper_1601_04017_amd import lpht
+    caps = [14] * 6
+    reqs = _trace(len(caps), 60, seed=17, lo=20000, hi=40000, universe=20000)
+    # room for the tables at their final size (at most 2^16 cells: at most
+    # 20000 distinct keys) and the staging of about two requests at a time,
+    # while six could run at once (one per table)
+    budget = len(caps) * (16 << 16) + 2 * 720_000 + (16 << 16)
+    res, comps, cells, counts, capsz, stats = _run(caps, reqs, lpht.SERVE_WAVES, 32, 32, budget=budget)
+    assert all(c[0] == 0 for c in comps)
+    assert stats["admission_waits"] > 0
+    assert stats["peak_hbm_bytes"] <= budget
+    ref, orcs = _oracle_replay(caps, reqs)
+    _check_same(reqs, res, ref)
+    for i, o in enumerate(orcs):
+        assert counts[i] == o.counts() and capsz[i] == o.capacity
+
+
+def test_serving_request_over_budget_is_rejected():
+    from paper_1601_04017_amd import lpht
+    caps = [12, 12]
+    big = (0, inputs.zipf_keys_u64(100000, 50000, 1.0, seed=3), np.ones(100000, np.uint8))
+    small = (1, inputs.zipf_keys_u64(100, 50000, 1.0, seed=4), np.zeros(100, np.uint8))
+    budget = (16 << 12) * 2 + 100000
+    res, comps, *_ = _run(caps, [big, small], lpht.SERVE_WAVES, 4, 2, budget=budget)
+    assert comps[0][0] == lpht.ERR_OOM
+    assert comps[1][0] == 0
