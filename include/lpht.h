@@ -274,7 +274,16 @@ int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void 
  *                       time form one wave, run as one multi-table launch per
  *                       phase (lpht_batch_run); new requests are admitted and
  *                       launched on another stream while earlier waves run;
- *   LPHT_SERVE_SINGLE - the plain form: every request gets its own launches.
+ *   LPHT_SERVE_SINGLE - the plain form: every request gets its own launches;
+ *   LPHT_SERVE_PERSISTENT - one resident kernel serves all requests: the
+ *                       worker posts each admitted request into a ring in
+ *                       pinned host memory, the kernel's wavefronts take its
+ *                       128-operation rounds phase by phase, read keys and
+ *                       write results directly in the request's pinned host
+ *                       buffers, and publish completions in host memory.  The
+ *                       kernel exits when idle and is relaunched on new work;
+ *                       for table growth it is stopped, the table migrates,
+ *                       and it is relaunched.  Host buffers must be pinned.
  * Tables grow before a request's increments by the growth rule (bulk
  * pre-growth, Sec. 5.5), which also removes tombstones (Sec. 5.4); the counts
  * the rule needs are read back after every request without synchronising.
@@ -282,6 +291,7 @@ int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void 
  * valid until the request completes. */
 #define LPHT_SERVE_WAVES 0u
 #define LPHT_SERVE_SINGLE 1u
+#define LPHT_SERVE_PERSISTENT 2u
 
 #define LPHT_KIND_FIND 0u
 #define LPHT_KIND_INCREMENT 1u

@@ -88,4 +88,53 @@ hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_ce
                           uint32_t log2_new, uint32_t layout, uint32_t crc_hi, uint32_t crc_lo,
                           int old_is_full, DevStatus *st, const LaunchCfg &cfg, hipStream_t s);
 
+// ---- persistent serving kernel ----
+// Requests are posted by the host into a ring in pinned host memory; one
+// resident kernel deals every request's 128-operation rounds to its
+// wavefronts, phase by phase (finds, insert-or-increments, erases), reading
+// keys and writing results directly in pinned host memory, and reports each
+// completed request (with its table's exact counts) in another host ring.
+constexpr uint32_t kPersistRing = 256;
+
+struct alignas(64) PersistCtl {   // host memory, written by the host
+  unsigned long long posted;      // requests posted so far
+  unsigned long long stop;        // 1: every wave exits after its current round
+  unsigned long long pad[6];
+};
+
+struct alignas(64) PersistReq {   // host memory, one per ring entry
+  BulkArgs a;                     // table fields; keys, kinds, vals_out, flags in host memory
+  unsigned long long rounds[3];   // rounds per phase (0 for a phase without operations)
+  unsigned long long seq;         // q + 1 once the entry holds request q (written last)
+};
+
+struct alignas(64) PersistDone {  // host memory, written by the device
+  unsigned long long seq;         // q + 1 when request q has completed (written last)
+  unsigned long long used, live, err;
+  unsigned long long pad[4];
+};
+
+struct alignas(128) PersistDev {  // device memory, one per ring entry
+  unsigned long long claim;       // (generation << 32) | rounds claimed; generation = q + 1
+  unsigned long long done[3];     // rounds finished per phase
+  unsigned long long pad[12];
+};
+
+struct alignas(64) PersistState { // device memory
+  unsigned long long error;       // nonzero: a wait exceeded its bound (a bug, reported)
+  unsigned long long posted;      // requests whose descriptors are in the device ring
+  unsigned long long stop;        // the host's stop flag, mirrored by the poller
+  unsigned long long alive;       // serving wavefronts still running
+  unsigned long long pad[4];
+};
+
+// Arms the device ring for requests first_q .. first_q + kPersistRing - 1.
+hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first_q, hipStream_t s);
+// The resident kernel (after a one-wave kernel that arms st): wavefronts
+// serve requests from `base_q` on until ctl->stop is set or they found no work
+// for `idle_polls` polls.  `ring` is the host ring, `dring` its device copy.
+hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
+                          PersistDone *done, PersistDev *dev, PersistState *st, uint64_t base_q,
+                          uint64_t idle_polls, uint32_t grid, hipStream_t s);
+
 }  // namespace lpht

@@ -177,6 +177,28 @@ __device__ __forceinline__ u64 load_key_in(const void *keys, u64 i) {
   return ((const u64 *)keys)[i];
 }
 
+// Loads of caller arrays.  Host memory read by a long-running kernel is read
+// with volatile loads, so that no value is reused from an earlier read (the
+// pinned host buffers are coherent and not kept in the GPU caches).
+template <int LAYOUT, bool HOSTMEM>
+__device__ __forceinline__ u64 ld_word(const void *a, u64 i) {
+  if (!HOSTMEM) return load_key_in<LAYOUT>(a, i);
+  if (LAYOUT == 0) return ((const volatile uint32_t *)a)[i];
+  return ((const volatile u64 *)a)[i];
+}
+
+template <bool HOSTMEM>
+__device__ __forceinline__ uint8_t ld_kind(const uint8_t *a, u64 i) {
+  if (!HOSTMEM) return a[i];
+  return ((const volatile uint8_t *)a)[i];
+}
+
+template <bool HOSTMEM>
+__device__ __forceinline__ u64 ld_u64(const u64 *a) {
+  if (!HOSTMEM) return *a;
+  return *(const volatile u64 *)a;
+}
+
 template <int LAYOUT>
 __device__ __forceinline__ void store_val_out(void *out, u64 i, u64 v) {
   if (LAYOUT == 0)
@@ -224,7 +246,7 @@ constexpr uint8_t kSkipFlag = 0xFD;
 // With A.kinds set, only operations whose kind byte equals A.kind_sel are
 // performed (phase order of mixed requests: finds, then insert-or-increments,
 // then erases); a find phase writes value 0 for the other operations.
-template <int LAYOUT, int OP, int UP, int G>
+template <int LAYOUT, int OP, int UP, int G, bool HOSTMEM = false>
 __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T)[256], uint8_t *wflag,
                                            u64 *wout, const u64 rbase, const uint32_t cnt,
                                            long long &d_used, long long &d_live, uint32_t &err) {
@@ -255,7 +277,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         break;
       }
       i = rbase + loc;
-      if (A.kinds && A.kinds[i] != A.kind_sel) {
+      if (A.kinds && ld_kind<HOSTMEM>(A.kinds, i) != A.kind_sel) {
         // an operation of another phase of a mixed request
         if (gl == 0) {
           wflag[loc] = kSkipFlag;
@@ -264,7 +286,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         ++j;
         continue;
       }
-      k = load_key_in<LAYOUT>(A.keys, i);
+      k = ld_word<LAYOUT, HOSTMEM>(A.keys, i);
       if (k == kEmpty || k == kTomb) {
         err |= kErrReserved;
         if (gl == 0) {
@@ -274,7 +296,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         ++j;
         continue;
       }
-      d = A.vals ? load_key_in<LAYOUT>(A.vals, i) : 1;
+      d = A.vals ? ld_word<LAYOUT, HOSTMEM>(A.vals, i) : 1;
       const u64 h = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
       base = h & ~(u64)(G - 1);
       first = (uint32_t)(h & (G - 1));
@@ -471,7 +493,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         u64 w = ((const u64 *)wflag)[lane];
         if (A.kinds) {
           // keep the flags other phases wrote
-          const u64 old = ((const u64 *)(A.flags + rbase))[lane];
+          const u64 old = ld_u64<HOSTMEM>((const u64 *)(A.flags + rbase) + lane);
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const u64 m = 0xFFull << (8 * b);
@@ -1053,6 +1075,284 @@ __global__ void __launch_bounds__(MIG_THREADS) k_migrate_lds(const void *old_cel
   flush_counts(st, moved, moved, 0, s_acc, &s_err);
 }
 
+// ---------------------------------------------------------------- persistent serving kernel
+//
+// Requests q = 0, 1, 2, ... are posted by the host into ring entry
+// q % kPersistRing (pinned host memory) before ctl->posted passes q.  One
+// poller wavefront (block 0, wavefront 0) is the only reader of the host's
+// control words: it copies new descriptors into the device ring and then
+// publishes st->posted, and it mirrors the host's stop flag into st->stop.
+// Every other wavefront serves: a request has three phases (finds,
+// insert-or-increments, erases; the paper's operations on one table, run in
+// phase order) of ceil(n/128) rounds each when the phase has operations.
+// Rounds are numbered through the phases and claimed with a compare-and-swap
+// on the entry's device word (generation << 32 | rounds claimed), so a claim
+// for a recycled entry fails.  A wavefront that claims a round of phase p first
+// waits until every round of the earlier phases is finished (the wavefronts
+// holding them are running, so the wait ends; its bound only guards against
+// bugs and is reported in st->error).  The wavefront that finishes the last
+// round sums the table's counts, re-arms the entry for request
+// q + kPersistRing, and then publishes the completion in host memory.
+// Serving wavefronts exit when st->stop is set (after their current round) or
+// after `idle_polls` polls that found no work; the poller exits on stop, when
+// no serving wavefront is left, or after 4 * idle_polls polls with nothing
+// new, so the kernel always finishes.
+
+__device__ __forceinline__ u64 sys_load(const u64 *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ u64 dev_load(const u64 *p, int order) {
+  return order == 0 ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr uint32_t kPersistWords = sizeof(PersistReq) / sizeof(u64);
+static_assert(kPersistWords <= 64, "a descriptor is copied by one wavefront");
+
+__global__ void k_persist_init(PersistDev *dev, PersistState *st, u64 first_q) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < kPersistRing) {
+    // the entry serves the first request q >= first_q with q % ring == e
+    u64 q = first_q + ((e + kPersistRing - (uint32_t)(first_q % kPersistRing)) % kPersistRing);
+    dev[e].done[0] = dev[e].done[1] = dev[e].done[2] = 0;
+    dev[e].claim = (q + 1) << 32;
+  }
+  if (e == 0) {
+    st->error = 0;
+    st->posted = first_q;
+    st->stop = 0;
+    st->alive = 0;
+  }
+}
+
+// Before each launch of the resident kernel: clear the stop mirror and count
+// the serving wavefronts.
+__global__ void k_persist_arm(PersistState *st, u64 serving) {
+  if (threadIdx.x == 0) {
+    st->stop = 0;
+    st->alive = serving;
+  }
+}
+
+__device__ void persist_poller(const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
+                               PersistState *st, u64 idle_polls) {
+  const uint32_t lane = threadIdx.x & 63;
+  u64 pub = 0;
+  if (lane == 0) pub = dev_load(&st->posted, 0);
+  pub = __shfl(pub, 0, 64);
+  u64 quiet = 0;
+  while (true) {
+    u64 stop = 0, posted = 0, alive = 0;
+    if (lane == 0) {
+      stop = sys_load(&ctl->stop);
+      posted = sys_load(&ctl->posted);
+      alive = dev_load(&st->alive, 1);
+    }
+    stop = __shfl(stop, 0, 64);
+    posted = __shfl(posted, 0, 64);
+    alive = __shfl(alive, 0, 64);
+    if (stop) {
+      if (lane == 0) __hip_atomic_store(&st->stop, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    if (posted > pub) {
+      // the host posts at most kPersistRing requests beyond the oldest open one
+      if (posted - pub > kPersistRing) pub = posted - kPersistRing;
+      for (u64 q = pub; q < posted; ++q) {
+        const uint32_t e = (uint32_t)(q % kPersistRing);
+        if (lane < kPersistWords)
+          ((u64 *)&dring[e])[lane] = ((const volatile u64 *)&ring[e])[lane];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane == 0) __hip_atomic_store(&st->posted, posted, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      pub = posted;
+      quiet = 0;
+    } else {
+      if (alive == 0) break;
+      if (++quiet > 4 * idle_polls) break;
+      __builtin_amdgcn_s_sleep(16);
+    }
+  }
+}
+
+template <int LAYOUT>
+__global__ void __launch_bounds__(256) k_persist(const PersistCtl *ctl, const PersistReq *ring,
+                                                 PersistReq *dring, PersistDone *done_ring,
+                                                 PersistDev *dev, PersistState *st, u64 base_q,
+                                                 u64 idle_polls) {
+  __shared__ uint32_t T[8][256];
+  __shared__ u64 s_req[4][kPersistWords];  // per wave: the request it works on
+  __shared__ u64 s_q[4];
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
+  crc_tables_build(T);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = threadIdx.x >> 6;
+  if (blockIdx.x == 0 && wave == 0) {
+    persist_poller(ctl, ring, dring, st, idle_polls);
+    return;
+  }
+  const uint32_t nwb = blockDim.x >> 6;
+  uint8_t *wflag = dyn_lds + nwb * ROUND * 8 + wave * ROUND;
+  u64 *wout = (u64 *)dyn_lds + wave * ROUND;
+  const u64 gw = (u64)blockIdx.x * nwb + wave;
+  if (lane == 0) s_q[wave] = ~0ull;
+  wave_sync();
+  u64 lo = base_q;
+  u64 idle = 0;
+  while (true) {
+    u64 posted = 0, stop = 0;
+    if (lane == 0) {
+      stop = dev_load(&st->stop, 0);
+      posted = dev_load(&st->posted, 1);
+    }
+    stop = __shfl(stop, 0, 64);
+    posted = __shfl(posted, 0, 64);
+    if (stop) break;
+    bool worked = false;
+    u64 q = lo;
+    uint32_t rounds_since_check = 0;
+    while (q < posted) {
+      if (++rounds_since_check == 8) {
+        // look at the stop flag now and then while there is work
+        rounds_since_check = 0;
+        u64 sp = 0;
+        if (lane == 0) sp = dev_load(&st->stop, 0);
+        if (__shfl(sp, 0, 64)) break;
+      }
+      const uint32_t e = (uint32_t)(q % kPersistRing);
+      u64 c = 0;
+      if (lane == 0) c = dev_load(&dev[e].claim, 0);
+      c = __shfl(c, 0, 64);
+      if ((c >> 32) != q + 1) {
+        // generation q + 1 + kPersistRing: request q has completed
+        if ((c >> 32) > q + 1 && q == lo) ++lo;
+        ++q;
+        continue;
+      }
+      if (s_q[wave] != q) {
+        // the request's descriptor, copied into the device ring by the poller
+        if (lane < kPersistWords) s_req[wave][lane] = ((const u64 *)&dring[e])[lane];
+        wave_sync();
+        if (lane == 0) s_q[wave] = q;
+        wave_sync();
+      }
+      const BulkArgs *RA = (const BulkArgs *)&s_req[wave][0];
+      const u64 *R = &s_req[wave][sizeof(BulkArgs) / sizeof(u64)];
+      const u64 total = R[0] + R[1] + R[2];
+      int status = 2;  // 0 claimed, 1 no rounds left, 2 not now
+      u64 t = 0;
+      if (lane == 0) {
+        for (int tries = 0; tries < 256; ++tries) {
+          const u64 gen = c >> 32, cnt = c & 0xFFFFFFFFull;
+          if (gen != q + 1) {
+            status = gen > q + 1 ? 1 : 2;
+            break;
+          }
+          if (cnt >= total) {
+            status = 1;
+            break;
+          }
+          // acquire: the entry's phase counters were cleared before it was re-armed
+          if (__hip_atomic_compare_exchange_strong(&dev[e].claim, &c, c + 1, __ATOMIC_ACQUIRE,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            status = 0;
+            t = cnt;
+            break;
+          }
+        }
+      }
+      status = __shfl(status, 0, 64);
+      t = __shfl(t, 0, 64);
+      if (status == 1) {
+        if (q == lo) ++lo;
+        ++q;
+        continue;
+      }
+      if (status == 2) {
+        ++q;
+        continue;
+      }
+      int p = 0;
+      u64 r = t;
+      while (p < 2 && r >= R[p]) {
+        r -= R[p];
+        ++p;
+      }
+      int last = 2;
+      while (last > 0 && R[last] == 0) --last;
+      if (lane == 0) {
+        for (int pp = 0; pp < p; ++pp) {
+          u64 spins = 0;
+          while (dev_load(&dev[e].done[pp], 1) < R[pp]) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1ull << 26)) {
+              atomicOr(&st->error, 1ull);
+              break;
+            }
+          }
+        }
+      }
+      wave_sync();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      BulkArgs A = *RA;
+      A.kind_sel = (uint32_t)p;
+      const u64 rbase = r * ROUND;
+      const uint32_t cnt = (uint32_t)((A.n - rbase) < ROUND ? (A.n - rbase) : ROUND);
+      long long du = 0, dl = 0;
+      uint32_t err = 0;
+      if (p == 0) {
+        bulk_round<LAYOUT, OP_FIND, 0, 1, true>(A, T, wflag, wout, rbase, cnt, du, dl, err);
+      } else if (p == 1) {
+        bulk_round<LAYOUT, OP_UPSERT, 1, 1, true>(A, T, wflag, wout, rbase, cnt, du, dl, err);
+      } else {
+        bulk_round<LAYOUT, OP_ERASE, 0, 1, true>(A, T, wflag, wout, rbase, cnt, du, dl, err);
+      }
+      const long long u = wave_sum(du), l = wave_sum(dl);
+      uint32_t ee = err;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) ee |= __shfl_xor(ee, o, 64);
+      if (lane == 0) {
+        CountSlot *cs = &A.status->slot[gw % kCountSlots];
+        if (u) add64(&cs->used, (u64)u);
+        if (l) add64(&cs->live, (u64)l);
+        if (ee) atomicOr(&A.status->err, ee);
+      }
+      // the round's table updates and its results in host memory are
+      // performed before the round counts as finished
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      if (lane == 0) {
+        const u64 d = __hip_atomic_fetch_add(&dev[e].done[p], 1ull, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (d == R[p] && p == last) {
+          u64 used = 0, live = 0;
+          for (int k = 0; k < kCountSlots; ++k) {
+            used += dev_load(&A.status->slot[k].used, 0);
+            live += dev_load(&A.status->slot[k].live, 0);
+          }
+          const u64 errbits = __hip_atomic_load(&A.status->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int k = 0; k < 3; ++k)
+            __hip_atomic_store(&dev[e].done[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&dev[e].claim, (q + kPersistRing + 1) << 32, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          PersistDone *dn = &done_ring[e];
+          __hip_atomic_store(&dn->used, used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          __hip_atomic_store(&dn->live, live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          __hip_atomic_store(&dn->err, errbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          __hip_atomic_store(&dn->seq, q + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+      worked = true;
+    }
+    if (!worked) {
+      if (++idle > idle_polls) break;
+      __builtin_amdgcn_s_sleep(32);
+    } else {
+      idle = 0;
+    }
+  }
+  if (lane == 0) __hip_atomic_fetch_add(&st->alive, ~0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline uint32_t grid_for(u64 work_items, const LaunchCfg &cfg) {
@@ -1178,6 +1478,28 @@ hipError_t launch_set_status(DevStatus *st, uint64_t used, uint64_t live, int cl
 
 hipError_t launch_count_totals(const DevStatus *st, uint64_t *out, hipStream_t s) {
   hipLaunchKernelGGL(k_count_totals, dim3(1), dim3(64), 0, s, st, (u64 *)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first_q, hipStream_t s) {
+  hipLaunchKernelGGL(k_persist_init, dim3(1), dim3(kPersistRing), 0, s, dev, st, (u64)first_q);
+  return hipGetLastError();
+}
+
+hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
+                          PersistDone *done, PersistDev *dev, PersistState *st, uint64_t base_q,
+                          uint64_t idle_polls, uint32_t grid, hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  const size_t lds = 4 * (size_t)ROUND * 9;
+  hipLaunchKernelGGL(k_persist_arm, dim3(1), dim3(64), 0, s, st, (u64)grid * 4 - 1);
+  hipError_t rc = hipGetLastError();
+  if (rc != hipSuccess) return rc;
+  if (layout == 0)
+    hipLaunchKernelGGL(k_persist<0>, dim3(grid), dim3(256), lds, s, ctl, ring, dring, done, dev, st,
+                       (u64)base_q, (u64)idle_polls);
+  else
+    hipLaunchKernelGGL(k_persist<1>, dim3(grid), dim3(256), lds, s, ctl, ring, dring, done, dev, st,
+                       (u64)base_q, (u64)idle_polls);
   return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Serving runtime of liblpht: a request loop over tables kept resident on
 // one device.  See the "serving" part of include/lpht.h for the contract.
 //
-// One worker thread owns every HIP call of the server.  It admits requests
+// One worker thread owns every HIP call of the server that touches a stream.  It admits requests
 // (request slots, one request per table at a time in submission order, HBM
 // budget), launches them (as one multi-table wave per admission round, or one
 // request at a time), and retires launch groups whose completion event has
@@ -37,6 +37,20 @@ double now_us() {
 }
 
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// True when the first and the last byte of [p, p + bytes) lie in pinned host
+// memory or in device memory (memory a kernel can address).
+bool gpu_accessible(const void *p, size_t bytes) {
+  for (const void *x : {p, (const void *)((const char *)p + bytes - 1)}) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, x) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    if (at.type != hipMemoryTypeHost && at.type != hipMemoryTypeDevice) return false;
+  }
+  return true;
+}
 
 struct Req {
   lpht_request r;
@@ -87,6 +101,22 @@ struct lpht_server {
   uint32_t next_stream = 0;
   uint32_t group_seq = 0;
   std::thread worker;
+  // persistent mode
+  PersistCtl *pctl = nullptr;      // pinned
+  PersistReq *pring = nullptr;     // pinned
+  PersistDone *pdone = nullptr;    // pinned
+  PersistReq *pdring = nullptr;   // device copy of the ring
+  PersistDev *pdev = nullptr;      // device
+  PersistState *pst = nullptr;     // device
+  Req *pentry[kPersistRing] = {};  // request held by each ring entry
+  uint64_t next_q = 0;             // requests posted
+  uint64_t oldest_q = 0;           // oldest request not yet retired
+  bool running = false;
+  hipEvent_t persist_ev = nullptr;
+  std::vector<Req *> grow_wait;    // admitted, waiting for their table to grow
+  uint32_t persist_grid = 0;
+  uint64_t persist_launches = 0;
+  bool persist_failed = false;     // a bounded wait in the kernel expired
 };
 
 namespace {
@@ -252,12 +282,19 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
     return S->fifo[a].front()->c.ticket < S->fifo[b].front()->c.ticket;
   });
   uint64_t hbm = table_bytes(S) + S->staging_bytes;
+  const uint32_t slots = S->cfg.mode == LPHT_SERVE_PERSISTENT
+                            ? std::min<uint32_t>(S->cfg.max_inflight, kPersistRing)
+                            : S->cfg.max_inflight;
   for (uint32_t t : cand) {
-    if (S->inflight_reqs + out.size() >= S->cfg.max_inflight) break;
+    if (S->inflight_reqs + S->grow_wait.size() + out.size() >= slots) break;
+    if (S->cfg.mode == LPHT_SERVE_PERSISTENT &&
+        S->next_q + S->grow_wait.size() + out.size() >= S->oldest_q + kPersistRing)
+      break;  // the ring entry of the oldest request is still in use
     Req *q = S->fifo[t].front();
-    const uint64_t need = staging_size(S, q) + growth_bytes(S->tables[t], q->count[1]);
+    const uint64_t staging = S->cfg.mode == LPHT_SERVE_PERSISTENT ? 0 : staging_size(S, q);
+    const uint64_t need = staging + growth_bytes(S->tables[t], q->count[1]);
     if (S->cfg.hbm_budget && hbm + need > S->cfg.hbm_budget) {
-      if (S->inflight.empty() && out.empty()) {
+      if (S->inflight_reqs == 0 && S->grow_wait.empty() && out.empty()) {
         // nothing will free memory: this request can never run
         S->fifo[t].pop_front();
         q->c.status = LPHT_ERR_OOM;
@@ -282,11 +319,182 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
   if (hbm > S->st.peak_hbm_bytes) S->st.peak_hbm_bytes = hbm;
 }
 
+// ---- persistent mode ----
+
+uint64_t idle_polls() { return 20000; }
+
+void persist_launch(lpht_server *S) {
+  hipStream_t s = S->streams[0];
+  __atomic_store_n(&S->pctl->stop, 0ull, __ATOMIC_RELEASE);
+  if (launch_persist(S->cfg.layout, S->pctl, S->pring, S->pdring, S->pdone, S->pdev, S->pst,
+                     S->oldest_q, idle_polls(), S->persist_grid, s) == hipSuccess) {
+    (void)hipEventRecord(S->persist_ev, s);
+    S->running = true;
+    S->persist_launches++;
+    S->st.waves++;
+    S->st.launches_phases++;
+  } else {
+    S->persist_failed = true;
+  }
+}
+
+// Called once the resident kernel has ended: reads its error word.
+void persist_ended(lpht_server *S) {
+  S->running = false;
+  uint64_t err = 0;
+  if (hipMemcpyAsync(&err, &S->pst->error, sizeof(err), hipMemcpyDeviceToHost, S->streams[0]) !=
+          hipSuccess ||
+      hipStreamSynchronize(S->streams[0]) != hipSuccess || err)
+    S->persist_failed = true;
+}
+
+// Posts an admitted request into the device ring.
+void persist_post(lpht_server *S, Req *q) {
+  const uint64_t qn = S->next_q;
+  const uint32_t e = (uint32_t)(qn % kPersistRing);
+  lpht_table *t = S->tables[q->r.table];
+  PersistReq &R = S->pring[e];
+  BulkArgs a = make_args(t);
+  a.keys = q->r.keys;
+  a.vals = nullptr;  // increments by one
+  a.n = q->r.n;
+  a.vals_out = q->r.vals_out;
+  a.flags = q->r.flags;
+  a.up = LPHT_ADD;
+  a.kinds = q->r.kinds;
+  a.kind_sel = 0;
+  R.a = a;
+  for (int k = 0; k < 3; ++k) R.rounds[k] = q->count[k] ? (q->r.n + kRound - 1) / kRound : 0;
+  __atomic_store_n(&R.seq, qn + 1, __ATOMIC_RELEASE);
+  t->mods_since_exact++;
+  S->pentry[e] = q;
+  q->c.admit_us = now_us();
+  q->c.wave = (uint32_t)S->persist_launches;
+  S->next_q = qn + 1;
+  if (S->inflight_reqs++ == 0) S->busy_since = now_us();
+  __atomic_store_n(&S->pctl->posted, qn + 1, __ATOMIC_RELEASE);
+}
+
+// Retires requests whose completion the kernel has published.
+bool persist_retire(lpht_server *S) {
+  bool any = false;
+  std::vector<Req *> fin;
+  for (uint64_t qn = S->oldest_q; qn < S->next_q; ++qn) {
+    const uint32_t e = (uint32_t)(qn % kPersistRing);
+    Req *q = S->pentry[e];
+    if (!q) continue;
+    if (__atomic_load_n(&S->pdone[e].seq, __ATOMIC_ACQUIRE) != qn + 1) continue;
+    lpht_table *T = S->tables[q->r.table];
+    if (S->persist_failed && q->c.status == LPHT_OK) q->c.status = LPHT_ERR_DEVICE;
+    T->known_used = S->pdone[e].used;
+    T->known_live = S->pdone[e].live;
+    T->pending = 0;
+    T->mods_since_exact = 0;
+    S->busy[q->r.table] = 0;
+    if (q->r.vals_out && q->count[0] == 0) std::memset(q->r.vals_out, 0, q->r.n * S->kb);
+    q->c.done_us = now_us();
+    S->staging_bytes -= q->need;
+    S->pentry[e] = nullptr;
+    if (--S->inflight_reqs == 0) S->st.busy_us += now_us() - S->busy_since;
+    fin.push_back(q);
+    any = true;
+  }
+  while (S->oldest_q < S->next_q && !S->pentry[S->oldest_q % kPersistRing]) S->oldest_q++;
+  if (!fin.empty()) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (Req *q : fin) finish_locked(S, q);
+    }
+    S->cv_done.notify_all();
+  }
+  return any;
+}
+
+bool needs_growth(const lpht_server *S, const Req *q) {
+  const lpht_table *t = S->tables[q->r.table];
+  return q->count[1] && !within_fill(t, t->known_used + q->count[1], 1ull << t->log2c);
+}
+
+// One pass of the worker in persistent mode.
+bool persist_step(lpht_server *S, std::vector<Req *> &admitted) {
+  bool progressed = persist_retire(S);
+  if (S->running && hipEventQuery(S->persist_ev) == hipSuccess) persist_ended(S);
+  // requests whose table must grow first: stop the kernel, migrate, restart
+  if (!S->grow_wait.empty()) {
+    if (S->running) {
+      __atomic_store_n(&S->pctl->stop, 1ull, __ATOMIC_RELEASE);
+    } else {
+      hipStream_t s = S->streams[0];
+      for (Req *q : S->grow_wait) {
+        lpht_table *t = S->tables[q->r.table];
+        const int rc = grow_before_batch(t, q->count[1], s);
+        t->pending = 0;  // the posted request accounts for its insertions itself
+        if (rc) {
+          // the table could not grow: the request fails as a whole
+          q->c.status = rc;
+          q->c.admit_us = q->c.done_us = now_us();
+          S->busy[q->r.table] = 0;
+          S->staging_bytes -= q->need;
+          {
+            std::lock_guard<std::mutex> lk(S->mu);
+            finish_locked(S, q);
+          }
+          S->cv_done.notify_all();
+          continue;
+        }
+        persist_post(S, q);
+      }
+      S->grow_wait.clear();
+      persist_launch(S);
+      progressed = true;
+    }
+    return progressed;
+  }
+  admitted.clear();
+  admit(S, admitted);
+  for (Req *q : admitted) {
+    if (needs_growth(S, q)) {
+      S->grow_wait.push_back(q);
+    } else {
+      persist_post(S, q);
+    }
+    progressed = true;
+  }
+  if (!S->running && S->oldest_q < S->next_q && S->grow_wait.empty()) {
+    persist_launch(S);
+    progressed = true;
+  }
+  return progressed;
+}
+
 void worker_loop(lpht_server *S) {
   (void)hipSetDevice(S->device);
   std::vector<Req *> admitted;
+  const bool persistent = S->cfg.mode == LPHT_SERVE_PERSISTENT;
   while (true) {
     bool progressed = false;
+    if (persistent) {
+      {
+        std::unique_lock<std::mutex> lk(S->mu);
+        while (!S->incoming.empty()) {
+          Req *q = S->incoming.front();
+          S->incoming.pop_front();
+          S->fifo[q->r.table].push_back(q);
+        }
+        if (S->stop && S->outstanding == 0) break;
+      }
+      progressed = persist_step(S, admitted);
+      if (!progressed) {
+        if (!S->running && S->oldest_q == S->next_q) {
+          std::unique_lock<std::mutex> lk(S->mu);
+          S->cv_work.wait_for(lk, std::chrono::milliseconds(2),
+                              [&] { return S->stop || !S->incoming.empty(); });
+        } else {
+          std::this_thread::yield();
+        }
+      }
+      continue;
+    }
     for (size_t w = 0; w < S->inflight.size();) {
       if (hipEventQuery(S->inflight[w].ev) == hipSuccess) {
         retire_group(S, S->inflight[w]);
@@ -331,6 +539,11 @@ void worker_loop(lpht_server *S) {
 }
 
 void destroy_all(lpht_server *S) {
+  if (S->running && S->pctl) {
+    __atomic_store_n(&S->pctl->stop, 1ull, __ATOMIC_RELEASE);
+    (void)hipEventSynchronize(S->persist_ev);
+    S->running = false;
+  }
   for (auto *b : S->batches) lpht_batch_destroy(b);
   for (auto *t : S->tables) lpht_destroy(t, S->streams.empty() ? nullptr : (void *)S->streams[0]);
   for (auto s : S->streams) {
@@ -340,6 +553,13 @@ void destroy_all(lpht_server *S) {
   for (auto e : S->spare_events) (void)hipEventDestroy(e);
   if (S->totals) (void)hipHostFree(S->totals);
   if (S->d_totals) (void)hipFree(S->d_totals);
+  if (S->pctl) (void)hipHostFree(S->pctl);
+  if (S->pring) (void)hipHostFree(S->pring);
+  if (S->pdone) (void)hipHostFree(S->pdone);
+  if (S->pdring) (void)hipFree(S->pdring);
+  if (S->pdev) (void)hipFree(S->pdev);
+  if (S->pst) (void)hipFree(S->pst);
+  if (S->persist_ev) (void)hipEventDestroy(S->persist_ev);
   for (auto &kv : S->reqs) delete kv.second;
   delete S;
 }
@@ -353,7 +573,8 @@ int lpht_server_create(const lpht_server_config *cfg, lpht_server **out) {
   *out = nullptr;
   if (!cfg || cfg->ntables == 0 || cfg->ntables > 65536 || !cfg->log2_capacity) return LPHT_ERR_INVALID;
   if (cfg->layout != LPHT_KV64 && cfg->layout != LPHT_PACKED32) return LPHT_ERR_INVALID;
-  if (cfg->mode > LPHT_SERVE_SINGLE || cfg->max_inflight < 1 || cfg->max_inflight > 4096) return LPHT_ERR_INVALID;
+  if (cfg->mode > LPHT_SERVE_PERSISTENT || cfg->max_inflight < 1 || cfg->max_inflight > 4096)
+    return LPHT_ERR_INVALID;
   if (cfg->streams < 1 || cfg->streams > 8 || cfg->reserved) return LPHT_ERR_INVALID;
   lpht_server *S = new (std::nothrow) lpht_server();
   if (!S) return LPHT_ERR_OOM;
@@ -408,6 +629,31 @@ int lpht_server_create(const lpht_server_config *cfg, lpht_server **out) {
     destroy_all(S);
     return LPHT_ERR_DEVICE;
   }
+  if (cfg->mode == LPHT_SERVE_PERSISTENT) {
+    if (hipHostMalloc((void **)&S->pctl, sizeof(PersistCtl), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&S->pring, sizeof(PersistReq) * kPersistRing, hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&S->pdone, sizeof(PersistDone) * kPersistRing, hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipMalloc((void **)&S->pdring, sizeof(PersistReq) * kPersistRing) != hipSuccess ||
+        hipMalloc((void **)&S->pdev, sizeof(PersistDev) * kPersistRing) != hipSuccess ||
+        hipMalloc((void **)&S->pst, sizeof(PersistState)) != hipSuccess ||
+        hipEventCreateWithFlags(&S->persist_ev, hipEventDisableTiming) != hipSuccess) {
+      destroy_all(S);
+      return LPHT_ERR_OOM;
+    }
+    std::memset(S->pctl, 0, sizeof(PersistCtl));
+    std::memset(S->pring, 0, sizeof(PersistReq) * kPersistRing);
+    std::memset(S->pdone, 0, sizeof(PersistDone) * kPersistRing);
+    int ncu = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, S->device);
+    S->persist_grid = (uint32_t)(ncu > 0 ? 2 * ncu : 512);
+    if (launch_persist_init(S->pdev, S->pst, 0, S->streams[0]) != hipSuccess ||
+        hipStreamSynchronize(S->streams[0]) != hipSuccess) {
+      destroy_all(S);
+      return LPHT_ERR_DEVICE;
+    }
+  }
   S->busy.assign(cfg->ntables, 0);
   S->fifo.resize(cfg->ntables);
   S->worker = std::thread(worker_loop, S);
@@ -420,6 +666,13 @@ int lpht_server_submit(lpht_server *S, const lpht_request *req, uint64_t *ticket
   if (req->table >= S->tables.size() || req->reserved || req->n == 0 || req->n > (1ull << 31) ||
       !req->keys || !req->kinds)
     return LPHT_ERR_INVALID;
+  if (S->cfg.mode == LPHT_SERVE_PERSISTENT) {
+    // the resident kernel reads and writes the caller's buffers directly
+    if (!gpu_accessible(req->keys, req->n * S->kb) || !gpu_accessible(req->kinds, req->n) ||
+        (req->vals_out && !gpu_accessible(req->vals_out, req->n * S->kb)) ||
+        (req->flags && !gpu_accessible(req->flags, req->n)))
+      return LPHT_ERR_INVALID;
+  }
   Req *q = new (std::nothrow) Req();
   if (!q) return LPHT_ERR_OOM;
   q->r = *req;

@@ -362,6 +362,7 @@ class Batch:
 
 SERVE_WAVES = 0
 SERVE_SINGLE = 1
+SERVE_PERSISTENT = 2
 KIND_FIND, KIND_INCREMENT, KIND_ERASE = 0, 1, 2
 
 
@@ -448,6 +449,8 @@ class Server:
 
     def __init__(self, log2_caps, layout=KV64, mode=SERVE_WAVES, max_inflight=64, streams=2,
                  hbm_budget=0):
+        import torch
+        torch.cuda.init()  # torch's device state first: the binding hands out torch tensors
         L = load()
         self.layout = layout
         self.kdt = "uint32" if layout == PACKED32 else "uint64"
@@ -471,24 +474,31 @@ class Server:
 
     def make_requests(self, reqs):
         """reqs: list of (table, keys ndarray, kinds ndarray).  Returns
-        (ctypes request array, list of (vals, flags) pinned output tensors,
-        buffers to keep alive)."""
+        (ctypes request array, list of (vals, flags) output tensors, buffers
+        to keep alive).  All host arrays live in four pinned buffers."""
         import numpy as np
         import torch
-        arr = (lpht_request * len(reqs))()
-        outs, keep = [], []
+        sizes = [len(k) for _, k, _ in reqs]
+        total = int(sum(sizes))
+        w = 4 if self.layout == PACKED32 else 8
         kdt = torch.int32 if self.layout == PACKED32 else torch.int64
-        for j, (tab, keys, kinds) in enumerate(reqs):
-            n = len(keys)
-            kview = np.ascontiguousarray(keys).view(np.int32 if self.layout == PACKED32 else np.int64)
-            k = torch.from_numpy(kview).pin_memory()
-            kd = torch.from_numpy(np.ascontiguousarray(kinds, dtype=np.uint8)).pin_memory()
-            v = torch.empty(n, dtype=kdt).pin_memory()
-            f = torch.empty(n, dtype=torch.uint8).pin_memory()
-            arr[j] = lpht_request(tab, 0, n, k.data_ptr(), kd.data_ptr(), v.data_ptr(), f.data_ptr())
-            outs.append((v, f))
-            keep += [k, kd]
-        return arr, outs, keep
+        keys = torch.empty(total, dtype=kdt).pin_memory()
+        kinds = torch.empty(total, dtype=torch.uint8).pin_memory()
+        vals = torch.empty(total, dtype=kdt).pin_memory()
+        flags = torch.empty(total, dtype=torch.uint8).pin_memory()
+        knp, kdnp = keys.numpy(), kinds.numpy()
+        arr = (lpht_request * len(reqs))()
+        outs = []
+        off = 0
+        for j, (tab, k, kd) in enumerate(reqs):
+            n = len(k)
+            knp[off:off + n] = np.ascontiguousarray(k).view(np.int32 if w == 4 else np.int64)
+            kdnp[off:off + n] = kd
+            arr[j] = lpht_request(tab, 0, n, keys.data_ptr() + off * w, kinds.data_ptr() + off,
+                                  vals.data_ptr() + off * w, flags.data_ptr() + off)
+            outs.append((vals[off:off + n], flags[off:off + n]))
+            off += n
+        return arr, outs, [keys, kinds, vals, flags]
 
     def run_closed_loop(self, req_array, nclients):
         n = len(req_array)

@@ -1,8 +1,8 @@
 """The serving runtime: mixed requests (finds, insert-or-increments, erases in
 phase order) through the request loop, checked against the oracle replaying
 each table's requests in submission order; every result is the same whether a
-request runs in a wave with many others or strictly alone; admission under a
-tight HBM budget."""
+request runs in a wave with many others, in the resident kernel, or strictly
+alone; admission under a tight HBM budget."""
 import numpy as np
 import pytest
 
@@ -20,14 +20,14 @@ def _gpu():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
 
 
-def _trace(ntables, nreq, seed, lo=64, hi=30000, universe=50000):
+def _trace(ntables, nreq, seed, lo=64, hi=30000, universe=50000, mix=(0.6, 0.3, 0.1)):
     rng = np.random.default_rng(seed)
     reqs = []
     for r in range(nreq):
         tab = int(rng.integers(0, ntables))
         n = int(np.clip(np.exp(rng.normal(np.log(3000), 1.2)), lo, hi))
         keys = inputs.zipf_keys_u64(n, universe, 1.0, seed=seed * 1000 + r)
-        kinds = rng.choice(np.array([0, 1, 2], np.uint8), size=n, p=[0.6, 0.3, 0.1])
+        kinds = rng.choice(np.array([0, 1, 2], np.uint8), size=n, p=list(mix))
         reqs.append((tab, keys, kinds))
     return reqs
 
@@ -115,12 +115,13 @@ def test_serving_single_mode_many_in_flight():
 
 def test_serving_tight_budget_admission_waits():
     from paper_1601_04017_amd import lpht
-    caps = [14] * 6
-    reqs = _trace(len(caps), 60, seed=17, lo=20000, hi=40000, universe=20000)
-    # room for the tables at their final size (at most 2^16 cells: at most
-    # 20000 distinct keys) and the staging of about two requests at a time,
-    # while six could run at once (one per table)
-    budget = len(caps) * (16 << 16) + 2 * 720_000 + (16 << 16)
+    caps = [16] * 6
+    reqs = _trace(len(caps), 60, seed=17, lo=30000, hi=40000, universe=20000, mix=(0.7, 0.3, 0.0))
+    # 2^16 cells hold 20000 distinct keys plus a request's <= 12000 increments
+    # without growing (no erases, so no tombstones); the budget leaves room for
+    # the staging (18 bytes per operation, >= 540 kB here) of one request at a
+    # time, while six could run at once (one per table)
+    budget = len(caps) * (16 << 16) + 1_000_000
     res, comps, cells, counts, capsz, stats = _run(caps, reqs, lpht.SERVE_WAVES, 32, 32, budget=budget)
     assert all(c[0] == 0 for c in comps)
     assert stats["admission_waits"] > 0
@@ -140,3 +141,60 @@ def test_serving_request_over_budget_is_rejected():
     res, comps, *_ = _run(caps, [big, small], lpht.SERVE_WAVES, 4, 2, budget=budget)
     assert comps[0][0] == lpht.ERR_OOM
     assert comps[1][0] == 0
+
+
+def test_serving_persistent_matches_oracle():
+    # the resident kernel: requests on eight tables with growth (small
+    # starting capacities) and erases; every table stops and restarts the
+    # kernel for its migrations
+    from paper_1601_04017_amd import lpht
+    reqs = _trace(len(CAPS), 120, seed=21)
+    res, comps, cells, counts, capsz, stats = _run(CAPS, reqs, lpht.SERVE_PERSISTENT, 32, 24)
+    assert all(c[0] == 0 for c in comps)
+    ref, orcs = _oracle_replay(CAPS, reqs)
+    _check_same(reqs, res, ref)
+    for i, o in enumerate(orcs):
+        assert counts[i] == o.counts()
+        assert capsz[i] == o.capacity
+        H.assert_same_table_modulo_run_order(cells[i], o.cells(), oracle.KV64)
+    assert stats["completed"] == len(reqs)
+    assert 1 <= stats["waves"] <= len(reqs)
+
+
+def test_serving_persistent_equals_alone_packed32():
+    from paper_1601_04017_amd import lpht
+    caps = [12, 14, 16, 13]
+    reqs = _trace(len(caps), 80, seed=23, universe=30000)
+    reqs = [(t, k.astype(np.uint32) | np.uint32(2), kd) for t, k, kd in reqs]
+
+    def run(mode, inflight, clients):
+        srv = lpht.Server(caps, layout=lpht.PACKED32, mode=mode, max_inflight=inflight, streams=1)
+        arr, outs, keep = srv.make_requests(reqs)
+        done, _ = srv.run_closed_loop(arr, clients)
+        out = [(o[0].numpy().view(np.uint32).copy(), o[1].numpy().copy()) for o in outs]
+        st = [d.status for d in done]
+        tabs = [(cells_host(srv.table(i)), srv.table(i).count(), srv.table(i).capacity)
+                for i in range(len(caps))]
+        srv.close()
+        return out, st, tabs
+
+    pm, sm, tm = run(lpht.SERVE_PERSISTENT, 64, 64)
+    pa, sa, ta = run(lpht.SERVE_SINGLE, 1, 1)
+    assert all(x == 0 for x in sm) and all(x == 0 for x in sa)
+    _check_same(reqs, pm, pa)
+    for (cm, nm, capm), (ca, na, capa) in zip(tm, ta):
+        assert nm == na and capm == capa
+        H.assert_same_table_modulo_run_order(cm, ca, oracle.PACKED32)
+
+
+def test_serving_persistent_rejects_pageable_buffers():
+    import ctypes
+    from paper_1601_04017_amd import lpht
+    srv = lpht.Server([10], mode=lpht.SERVE_PERSISTENT, max_inflight=4, streams=1)
+    keys = np.arange(2, 66, dtype=np.uint64)
+    kinds = np.ones(64, np.uint8)
+    req = lpht.lpht_request(0, 0, 64, keys.ctypes.data, kinds.ctypes.data, 0, 0)
+    t = ctypes.c_uint64()
+    rc = lpht.load().lpht_server_submit(srv._h, ctypes.byref(req), ctypes.byref(t))
+    srv.close()
+    assert rc == lpht.ERR_INVALID
