@@ -161,17 +161,18 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
     return out
 
 
-def serving_trace(nreq, seed=500):
+def serving_trace(nreq, seed=500, median=16384, lo=1024, hi=1 << 20):
     """64 tables with 2^e cells, e uniform in 12..26; requests to uniformly
     random tables; sizes lognormal (median 16384, sigma 1.35) clipped to
-    [1024, 2^20]; kinds find / insert-or-increment / erase = 60/30/10 %; keys
-    Zipf(1.0) over 10^8 (key = rank + 1)."""
+    [1024, 2^20] (the small-request trace: median 1024 in [64, 16384]); kinds
+    find / insert-or-increment / erase = 60/30/10 %; keys Zipf(1.0) over 10^8
+    (key = rank + 1)."""
     from paper_1601_04017_amd import inputs
 
     rng_caps = np.random.default_rng(seed + 1)
     caps = [int(e) for e in rng_caps.integers(12, 27, size=64)]
     tabs = np.random.default_rng(seed + 2).integers(0, 64, size=nreq)
-    sizes = inputs.lognormal_sizes(nreq, 16384, 1.35, 1024, 1 << 20, seed=seed + 3)
+    sizes = inputs.lognormal_sizes(nreq, median, 1.35, lo, hi, seed=seed + 3)
     total = int(sizes.sum())
     kinds = np.random.default_rng(seed + 4).choice(np.array([0, 1, 2], np.uint8), size=total,
                                                    p=[0.6, 0.3, 0.1])
@@ -181,9 +182,29 @@ def serving_trace(nreq, seed=500):
     return caps, reqs, total
 
 
+def _serve(caps, reqs, total, mode, slots, streams, budget, nclients):
+    from paper_1601_04017_amd import lpht
+
+    srv = lpht.Server(caps, mode=mode, max_inflight=slots, streams=streams, hbm_budget=budget)
+    arr, outs, keep = srv.make_requests(reqs)
+    done, wall_us = srv.run_closed_loop(arr, nclients)
+    lat = np.array([d.done_us - d.submit_us for d in done])
+    ok = sum(1 for d in done if d.status == 0)
+    st = srv.stats()
+    srv.close()
+    del arr, outs, keep
+    return {"mops": round(total / wall_us, 1), "wall_ms": round(wall_us / 1e3, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)) / 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) / 1e3, 3),
+            "completed_ok": ok, "launch_groups": st["waves"],
+            "admission_waits": st["admission_waits"], "hbm_budget": budget,
+            "peak_hbm_bytes": st["peak_hbm_bytes"]}
+
+
 def run_serving(nreq=2000, nclients=256):
-    """Closed-loop serving of the mixed trace: continuous batching waves vs
-    one launch per request, and waves under a tight HBM budget."""
+    """Closed-loop serving of the mixed trace: continuous batching waves, the
+    resident kernel, one launch per request, and waves and the resident
+    kernel under a tight HBM budget; then the small-request trace."""
     from paper_1601_04017_amd import lpht
 
     log(f"suite: serving trace ({nreq} requests)")
@@ -192,24 +213,21 @@ def run_serving(nreq=2000, nclients=256):
     res = {"requests": nreq, "ops": total, "clients": nclients, "tables": len(caps),
            "initial_table_bytes": init_bytes}
     runs = [("waves", lpht.SERVE_WAVES, 256, 4, 2 * init_bytes),
+            ("persistent", lpht.SERVE_PERSISTENT, 256, 1, 2 * init_bytes),
             ("one_launch_per_request", lpht.SERVE_SINGLE, 256, 4, 2 * init_bytes),
-            ("waves_tight_budget", lpht.SERVE_WAVES, 256, 4, int(1.25 * init_bytes))]
+            ("waves_tight_budget", lpht.SERVE_WAVES, 256, 4, int(1.25 * init_bytes)),
+            ("persistent_tight_budget", lpht.SERVE_PERSISTENT, 256, 1, int(1.25 * init_bytes))]
     for name, mode, slots, streams, budget in runs:
         log(f"suite: serving {name}")
-        srv = lpht.Server(caps, mode=mode, max_inflight=slots, streams=streams, hbm_budget=budget)
-        arr, outs, keep = srv.make_requests(reqs)
-        done, wall_us = srv.run_closed_loop(arr, nclients)
-        lat = np.array([d.done_us - d.submit_us for d in done])
-        ok = sum(1 for d in done if d.status == 0)
-        st = srv.stats()
-        srv.close()
-        res[name] = {"mops": round(total / wall_us, 1), "wall_ms": round(wall_us / 1e3, 2),
-                     "p50_ms": round(float(np.percentile(lat, 50)) / 1e3, 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)) / 1e3, 3),
-                     "completed_ok": ok, "launch_groups": st["waves"],
-                     "admission_waits": st["admission_waits"], "hbm_budget": budget,
-                     "peak_hbm_bytes": st["peak_hbm_bytes"]}
-        del arr, outs, keep
+        res[name] = _serve(caps, reqs, total, mode, slots, streams, budget, nclients)
+    nsmall = 2 * nreq
+    caps, reqs, total = serving_trace(nsmall, seed=600, median=1024, lo=64, hi=16384)
+    small = {"requests": nsmall, "ops": total, "clients": nclients}
+    for name, mode, streams in (("waves", lpht.SERVE_WAVES, 4), ("persistent", lpht.SERVE_PERSISTENT, 1),
+                                ("one_launch_per_request", lpht.SERVE_SINGLE, 4)):
+        log(f"suite: serving small requests {name}")
+        small[name] = _serve(caps, reqs, total, mode, 256, streams, 0, nclients)
+    res["small_requests"] = small
     return res
 
 

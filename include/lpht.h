@@ -277,13 +277,22 @@ int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void 
  *   LPHT_SERVE_SINGLE - the plain form: every request gets its own launches;
  *   LPHT_SERVE_PERSISTENT - one resident kernel serves all requests: the
  *                       worker posts each admitted request into a ring in
- *                       pinned host memory, the kernel's wavefronts take its
- *                       128-operation rounds phase by phase, read keys and
- *                       write results directly in the request's pinned host
- *                       buffers, and publish completions in host memory.  The
- *                       kernel exits when idle and is relaunched on new work;
- *                       for table growth it is stopped, the table migrates,
- *                       and it is relaunched.  Host buffers must be pinned.
+ *                       pinned host memory; the kernel's wavefronts copy its
+ *                       keys and kinds into a device staging arena, run its
+ *                       128-operation rounds phase by phase, copy values and
+ *                       flags back into the request's host arrays, and
+ *                       publish the completion in host memory.  No HIP call
+ *                       is made per request.  The kernel exits when idle and
+ *                       is relaunched on new work; for table growth it is
+ *                       stopped, the table migrates, and it is relaunched.
+ *                       Request arrays must be pinned host memory (or device
+ *                       memory); submit rejects others with
+ *                       LPHT_ERR_INVALID.  The staging arena is 1 GiB, or a
+ *                       quarter of what hbm_budget leaves beside the initial
+ *                       tables (at least 16 MiB); a request needs
+ *                       about (2 * key bytes + 2) * n of it while in flight,
+ *                       and one that can never fit completes with
+ *                       LPHT_ERR_OOM.
  * Tables grow before a request's increments by the growth rule (bulk
  * pre-growth, Sec. 5.5), which also removes tombstones (Sec. 5.4); the counts
  * the rule needs are read back after every request without synchronising.

@@ -102,9 +102,20 @@ struct alignas(64) PersistCtl {   // host memory, written by the host
   unsigned long long pad[6];
 };
 
+// A request's phases in the resident kernel: copy its keys and kinds from the
+// caller's pinned host arrays into device staging, finds, insert-or-increments,
+// erases, copy the values and flags back.  Rounds of the copy phases cover
+// kCopyRound operations, the others kRound.
+constexpr uint32_t kPersistPhases = 5;
+constexpr uint32_t kCopyRound = 1024;
+
 struct alignas(64) PersistReq {   // host memory, one per ring entry
-  BulkArgs a;                     // table fields; keys, kinds, vals_out, flags in host memory
-  unsigned long long rounds[3];   // rounds per phase (0 for a phase without operations)
+  BulkArgs a;                     // table fields; keys, kinds, vals_out, flags: the device staging
+  const void *hkeys;              // the caller's pinned host arrays
+  const uint8_t *hkinds;
+  void *hvals;                    // may be null
+  uint8_t *hflags;                // may be null
+  unsigned long long rounds[kPersistPhases];  // rounds per phase (0 for a phase without operations)
   unsigned long long seq;         // q + 1 once the entry holds request q (written last)
 };
 
@@ -116,25 +127,41 @@ struct alignas(64) PersistDone {  // host memory, written by the device
 
 struct alignas(128) PersistDev {  // device memory, one per ring entry
   unsigned long long claim;       // (generation << 32) | rounds claimed; generation = q + 1
-  unsigned long long done[3];     // rounds finished per phase
-  unsigned long long pad[12];
+  unsigned long long done[kPersistPhases];  // (generation << 32) | rounds finished, per phase
+  unsigned long long pad[10];
 };
 
-struct alignas(64) PersistState { // device memory
-  unsigned long long error;       // nonzero: a wait exceeded its bound (a bug, reported)
+// Serving wavefronts are split into kPersistGroups groups by workgroup index
+// (consecutive workgroups go to different XCDs, so a group is one XCD's
+// share); group g serves the requests q with q % kPersistGroups == g and
+// polls its own copy of the control words.
+constexpr uint32_t kPersistGroups = 8;
+
+struct alignas(128) PersistGroupCtl {
   unsigned long long posted;      // requests whose descriptors are in the device ring
   unsigned long long stop;        // the host's stop flag, mirrored by the poller
+  unsigned long long pad[14];
+};
+
+struct alignas(128) PersistState { // device memory
+  unsigned long long error;       // nonzero: a wait exceeded its bound (a bug, reported)
   unsigned long long alive;       // serving wavefronts still running
-  unsigned long long pad[4];
+  unsigned long long published;   // ctl->posted as last copied by the poller
+  unsigned long long completed;   // requests completed
+  unsigned long long pad[12];
+  PersistGroupCtl group[kPersistGroups];
 };
 
 // Arms the device ring for requests first_q .. first_q + kPersistRing - 1.
 hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first_q, hipStream_t s);
 // The resident kernel (after a one-wave kernel that arms st): wavefronts
-// serve requests from `base_q` on until ctl->stop is set or they found no work
-// for `idle_polls` polls.  `ring` is the host ring, `dring` its device copy.
+// serve requests from `base_q` on until ctl->stop is set, or until one of them
+// has found no work for `idle_ticks` ticks of the device's constant-rate clock
+// while every published request has completed.  `ring` is the
+// host ring, `dring` its device copy.  `grid` must be a positive multiple of
+// kPersistGroups.
 hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
                           PersistDone *done, PersistDev *dev, PersistState *st, uint64_t base_q,
-                          uint64_t idle_polls, uint32_t grid, hipStream_t s);
+                          uint64_t idle_ticks, uint32_t grid, hipStream_t s);
 
 }  // namespace lpht

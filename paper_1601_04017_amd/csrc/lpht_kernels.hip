@@ -32,6 +32,9 @@
 // single store (Sec. 4).  All table atomics are device (agent) scope.
 
 #include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <type_traits>
 #include <stdint.h>
 
 #include "lpht_internal.h"
@@ -144,10 +147,18 @@ __device__ __forceinline__ void flush_counts(DevStatus *st, long long d_used, lo
 template <int LAYOUT>
 struct Cells;
 
+// COH: device-coherent reads (agent-scope relaxed atomic loads, which bypass
+// the per-CU and per-XCD caches), used by the resident serving kernel whose
+// phases synchronise without cache maintenance.
+__device__ __forceinline__ u64 coh_load(const u64 *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <>
 struct Cells<0> {
+  template <bool COH = false>
   static __device__ __forceinline__ u64 word(const void *c, u64 i) {
-    return ((const u64 *)c)[i];
+    return COH ? coh_load((const u64 *)c + i) : ((const u64 *)c)[i];
   }
   static __device__ __forceinline__ u64 key_of(u64 w) { return w & 0xFFFFFFFFull; }
   static __device__ __forceinline__ u64 val_of(u64 w) { return w >> 32; }
@@ -155,11 +166,19 @@ struct Cells<0> {
 
 template <>
 struct Cells<1> {
+  template <bool COH = false>
   static __device__ __forceinline__ u64x2 cell(const void *c, u64 i) {
+    if (COH) {
+      u64x2 v;
+      v.x = coh_load((const u64 *)c + 2 * i);
+      v.y = coh_load((const u64 *)c + 2 * i + 1);
+      return v;
+    }
     return ((const u64x2 *)c)[i];
   }
+  template <bool COH = false>
   static __device__ __forceinline__ u64 key(const void *c, u64 i) {
-    return ((const u64 *)c)[2 * i];
+    return COH ? coh_load((const u64 *)c + 2 * i) : ((const u64 *)c)[2 * i];
   }
 };
 
@@ -177,42 +196,64 @@ __device__ __forceinline__ u64 load_key_in(const void *keys, u64 i) {
   return ((const u64 *)keys)[i];
 }
 
-// Loads of caller arrays.  Host memory read by a long-running kernel is read
-// with volatile loads, so that no value is reused from an earlier read (the
-// pinned host buffers are coherent and not kept in the GPU caches).
-template <int LAYOUT, bool HOSTMEM>
+// Loads and stores of caller arrays.  RESIDENT: the arrays are the device
+// staging of the resident serving kernel, which other wavefronts (on other
+// XCDs) write and read during the same launch; accesses are device-coherent
+// (agent-scope relaxed atomics, which bypass the per-CU and per-XCD caches).
+template <int LAYOUT, bool RESIDENT>
 __device__ __forceinline__ u64 ld_word(const void *a, u64 i) {
-  if (!HOSTMEM) return load_key_in<LAYOUT>(a, i);
-  if (LAYOUT == 0) return ((const volatile uint32_t *)a)[i];
-  return ((const volatile u64 *)a)[i];
+  if (!RESIDENT) return load_key_in<LAYOUT>(a, i);
+  if (LAYOUT == 0) return __hip_atomic_load((const uint32_t *)a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const u64 *)a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool HOSTMEM>
+template <bool RESIDENT>
 __device__ __forceinline__ uint8_t ld_kind(const uint8_t *a, u64 i) {
-  if (!HOSTMEM) return a[i];
-  return ((const volatile uint8_t *)a)[i];
+  if (!RESIDENT) return a[i];
+  return __hip_atomic_load(a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool HOSTMEM>
+template <bool RESIDENT>
 __device__ __forceinline__ u64 ld_u64(const u64 *a) {
-  if (!HOSTMEM) return *a;
-  return *(const volatile u64 *)a;
+  if (!RESIDENT) return *a;
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int LAYOUT>
+template <bool RESIDENT, typename W>
+__device__ __forceinline__ void st_out(W *p, W v) {
+  if (!RESIDENT)
+    *p = v;
+  else
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int LAYOUT, bool RESIDENT = false>
 __device__ __forceinline__ void store_val_out(void *out, u64 i, u64 v) {
   if (LAYOUT == 0)
-    ((uint32_t *)out)[i] = (uint32_t)v;
+    st_out<RESIDENT>((uint32_t *)out + i, (uint32_t)v);
   else
-    ((u64 *)out)[i] = v;
+    st_out<RESIDENT>((u64 *)out + i, v);
 }
 
 // Writes of values into cells.  Plain stores: a value is written either by
 // the lane whose CAS claimed the cell (no other lane writes it in that call)
 // or as an overwrite whose result may be any one of the concurrent values;
 // the line stays in L2 and is written back whole.
-__device__ __forceinline__ void put64(u64 *p, u64 v) { *p = v; }
-__device__ __forceinline__ void put32(uint32_t *p, uint32_t v) { *p = v; }
+// (COH: a device-coherent store, for the resident serving kernel.)
+template <bool COH = false>
+__device__ __forceinline__ void put64(u64 *p, u64 v) {
+  if (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+template <bool COH = false>
+__device__ __forceinline__ void put32(uint32_t *p, uint32_t v) {
+  if (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
 
 // Orders LDS accesses of the lanes of one wavefront.
 __device__ __forceinline__ void wave_sync() {
@@ -246,10 +287,15 @@ constexpr uint8_t kSkipFlag = 0xFD;
 // With A.kinds set, only operations whose kind byte equals A.kind_sel are
 // performed (phase order of mixed requests: finds, then insert-or-increments,
 // then erases); a find phase writes value 0 for the other operations.
-template <int LAYOUT, int OP, int UP, int G, bool HOSTMEM = false>
+//
+// RESIDENT: a round of the resident serving kernel (device-coherent accesses
+// to cells and staging); the round's keys and kinds are first read into LDS
+// (skeys, skinds: ROUND entries each) with one coalesced load per lane.
+template <int LAYOUT, int OP, int UP, int G, bool RESIDENT = false>
 __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T)[256], uint8_t *wflag,
                                            u64 *wout, const u64 rbase, const uint32_t cnt,
-                                           long long &d_used, long long &d_live, uint32_t &err) {
+                                           long long &d_used, long long &d_live, uint32_t &err,
+                                           u64 *skeys = nullptr, uint8_t *skinds = nullptr) {
   constexpr uint32_t NGW = 64 / G;            // groups per wavefront
   constexpr uint32_t PER_GROUP = ROUND / NGW; // operations per group per round
   const uint32_t lane = threadIdx.x & 63;
@@ -265,6 +311,23 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
   u64 i = 0, k = 0, d = 1, base = 0, windows = 0, limit = 0;
   uint32_t first = 0;
   bool active = false;
+  if (RESIDENT) {
+    static_assert(ROUND == 128, "two operations per lane");
+    u64 k0 = 0, k1 = 0;
+    uint8_t c0 = 0, c1 = 0;
+    const bool in0 = lane < cnt, in1 = lane + 64 < cnt;
+    if (in0) k0 = ld_word<LAYOUT, true>(A.keys, rbase + lane);
+    if (in1) k1 = ld_word<LAYOUT, true>(A.keys, rbase + lane + 64);
+    if (A.kinds) {
+      if (in0) c0 = ld_kind<true>(A.kinds, rbase + lane);
+      if (in1) c1 = ld_kind<true>(A.kinds, rbase + lane + 64);
+    }
+    skeys[lane] = k0;
+    skeys[lane + 64] = k1;
+    skinds[lane] = c0;
+    skinds[lane + 64] = c1;
+    wave_sync();
+  }
 
   // Takes the group's next operation of the round (reserved keys are
   // answered at once).
@@ -277,7 +340,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         break;
       }
       i = rbase + loc;
-      if (A.kinds && ld_kind<HOSTMEM>(A.kinds, i) != A.kind_sel) {
+      if (A.kinds && (RESIDENT ? skinds[loc] : A.kinds[i]) != A.kind_sel) {
         // an operation of another phase of a mixed request
         if (gl == 0) {
           wflag[loc] = kSkipFlag;
@@ -286,7 +349,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         ++j;
         continue;
       }
-      k = ld_word<LAYOUT, HOSTMEM>(A.keys, i);
+      k = RESIDENT ? skeys[loc] : load_key_in<LAYOUT>(A.keys, i);
       if (k == kEmpty || k == kTomb) {
         err |= kErrReserved;
         if (gl == 0) {
@@ -296,7 +359,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         ++j;
         continue;
       }
-      d = A.vals ? ld_word<LAYOUT, HOSTMEM>(A.vals, i) : 1;
+      d = A.vals ? ld_word<LAYOUT, RESIDENT>(A.vals, i) : 1;
       const u64 h = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
       base = h & ~(u64)(G - 1);
       first = (uint32_t)(h & (G - 1));
@@ -323,15 +386,15 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
       const u64 idx = base + gl;
       u64 ck, cv = 0;
       if (LAYOUT == 0) {
-        const u64 w = Cells<0>::word(A.cells, idx);
+        const u64 w = Cells<0>::word<RESIDENT>(A.cells, idx);
         ck = Cells<0>::key_of(w);
         cv = Cells<0>::val_of(w);
       } else if (OP == OP_FIND) {
-        const u64x2 c = Cells<1>::cell(A.cells, idx);
+        const u64x2 c = Cells<1>::cell<RESIDENT>(A.cells, idx);
         ck = c.x;
         cv = c.y;
       } else {
-        ck = Cells<1>::key(A.cells, idx);
+        ck = Cells<1>::key<RESIDENT>(A.cells, idx);
       }
       bool done = false;
       uint8_t flag = 0;
@@ -362,13 +425,13 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
                 if (UP == 1)
                   add64(w, d << 32);
                 else
-                  put32((uint32_t *)w + 1, (uint32_t)d);
+                  put32<RESIDENT>((uint32_t *)w + 1, (uint32_t)d);
               } else {
                 u64 *v = (u64 *)A.cells + 2 * idx + 1;
                 if (UP == 1)
                   add64(v, d);
                 else
-                  put64(v, d);
+                  put64<RESIDENT>(v, d);
               }
             }
             flag = (OP == OP_UPDATE) ? 1 : 0;
@@ -398,7 +461,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
               if (gl == jl) ck = old;
               if (LAYOUT == 0 && gl == jl && old == k) {
                 // only the value changed: reload the word and retry
-                const u64 w = Cells<0>::word(A.cells, idx);
+                const u64 w = Cells<0>::word<RESIDENT>(A.cells, idx);
                 ck = Cells<0>::key_of(w);
                 cv = Cells<0>::val_of(w);
               }
@@ -428,7 +491,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
                   if (OP == OP_UPSERT && UP == 1)
                     add64(v, d);  // concurrent increments of the same key also add
                   else
-                    put64(v, d);
+                    put64<RESIDENT>(v, d);
                   d_used += 1;
                   d_live += 1;
                 }
@@ -447,13 +510,13 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
                   if (UP == 1)
                     add64(w, d << 32);
                   else
-                    put32((uint32_t *)w + 1, (uint32_t)d);
+                    put32<RESIDENT>((uint32_t *)w + 1, (uint32_t)d);
                 } else {
                   u64 *v = (u64 *)A.cells + 2 * idx + 1;
                   if (UP == 1)
                     add64(v, d);
                   else
-                    put64(v, d);
+                    put64<RESIDENT>(v, d);
                 }
               }
               flag = 0;
@@ -493,22 +556,22 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         u64 w = ((const u64 *)wflag)[lane];
         if (A.kinds) {
           // keep the flags other phases wrote
-          const u64 old = ld_u64<HOSTMEM>((const u64 *)(A.flags + rbase) + lane);
+          const u64 old = ld_u64<RESIDENT>((const u64 *)(A.flags + rbase) + lane);
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const u64 m = 0xFFull << (8 * b);
             if (((w & m) >> (8 * b)) == kSkipFlag) w = (w & ~m) | (old & m);
           }
         }
-        ((u64 *)(A.flags + rbase))[lane] = w;
+        st_out<RESIDENT>((u64 *)(A.flags + rbase) + lane, w);
       }
     } else {
       for (uint32_t t = lane; t < cnt; t += 64)
-        if (wflag[t] != kSkipFlag) A.flags[rbase + t] = wflag[t];
+        if (wflag[t] != kSkipFlag) st_out<RESIDENT>(A.flags + rbase + t, wflag[t]);
     }
   }
   if (OP == OP_FIND && A.vals_out) {
-    if (cnt == ROUND && vals_vec) {
+    if (cnt == ROUND && vals_vec && !RESIDENT) {
       if (LAYOUT == 0) {
         typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
         u32x2 v = {(uint32_t)wout[2 * lane], (uint32_t)wout[2 * lane + 1]};
@@ -518,7 +581,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         ((u64x2 *)((u64 *)A.vals_out + rbase))[lane] = v;
       }
     } else {
-      for (uint32_t t = lane; t < cnt; t += 64) store_val_out<LAYOUT>(A.vals_out, rbase + t, wout[t]);
+      for (uint32_t t = lane; t < cnt; t += 64) store_val_out<LAYOUT, RESIDENT>(A.vals_out, rbase + t, wout[t]);
     }
   }
   wave_sync();
@@ -1081,30 +1144,76 @@ __global__ void __launch_bounds__(MIG_THREADS) k_migrate_lds(const void *old_cel
 // q % kPersistRing (pinned host memory) before ctl->posted passes q.  One
 // poller wavefront (block 0, wavefront 0) is the only reader of the host's
 // control words: it copies new descriptors into the device ring and then
-// publishes st->posted, and it mirrors the host's stop flag into st->stop.
-// Every other wavefront serves: a request has three phases (finds,
-// insert-or-increments, erases; the paper's operations on one table, run in
-// phase order) of ceil(n/128) rounds each when the phase has operations.
-// Rounds are numbered through the phases and claimed with a compare-and-swap
-// on the entry's device word (generation << 32 | rounds claimed), so a claim
-// for a recycled entry fails.  A wavefront that claims a round of phase p first
-// waits until every round of the earlier phases is finished (the wavefronts
-// holding them are running, so the wait ends; its bound only guards against
-// bugs and is reported in st->error).  The wavefront that finishes the last
-// round sums the table's counts, re-arms the entry for request
-// q + kPersistRing, and then publishes the completion in host memory.
-// Serving wavefronts exit when st->stop is set (after their current round) or
-// after `idle_polls` polls that found no work; the poller exits on stop, when
-// no serving wavefront is left, or after 4 * idle_polls polls with nothing
-// new, so the kernel always finishes.
+// publishes the new count in every group's control line, and it mirrors the
+// host's stop flag there.
+//
+// Every other wavefront serves the requests of its group (q % kPersistGroups
+// equal to the workgroup index % kPersistGroups).  A request has five phases:
+// copy-in (its keys and kinds from the caller's pinned host arrays into its
+// device staging, kCopyRound operations per round), then the paper's
+// operations on one table in phase order (finds, insert-or-increments, erases;
+// ceil(n/128) rounds each when the phase has operations), then copy-out (values
+// and flags to the host).  Only the copy phases touch host memory, in long
+// sequential runs: rounds that read and wrote the caller's host arrays
+// directly were bound by GPU accesses to scattered host pages.  Rounds are
+// numbered through the phases and claimed, up to four at a time, with a
+// compare-and-swap on the entry's claim word (generation << 32 | rounds
+// claimed; generation q + 1), so a claim for a recycled entry fails.  Each phase's finished rounds are counted in a word tagged the same
+// way, so the counters need no reset between the requests an entry serves.  A
+// wavefront that holds a round of phase p first waits until every round of the
+// earlier phases is finished (the wavefronts holding them are running, so the
+// wait ends; its bound only guards against bugs and is reported in st->error).
+// The wavefront that finishes the last copy-out round sums the table's counts,
+// re-arms the entry for request q + kPersistRing, and then publishes the
+// completion in host memory.
+//
+// Memory ordering without cache maintenance.  An agent- or system-scope
+// fence writes back or invalidates the whole L2 of the wavefront's XCD; issued
+// per round by thousands of wavefronts it would stall every access.  So here
+// every access to shared state is device-coherent by itself: table cells and
+// staging are read with agent-scope relaxed atomic loads and written with
+// agent-scope atomics, descriptors and counters likewise, host arrays are read
+// with volatile (uncached) loads, and results go to host memory as
+// system-scope (written-through) stores.  What orders one wavefront's accesses before a
+// counter update that another wavefront waits for is then only their
+// completion: `wait_mem` (all of the wavefront's memory operations
+// acknowledged) comes before each counter update and each publication, and a
+// waiting wavefront issues its dependent loads after it has seen the counter.
+// A request's rounds only become claimable when it is posted, so a wavefront
+// whose scan found nothing sleeps (with growing pauses) until its group's
+// posted count moves.
+//
+// Serving wavefronts exit when their group's stop flag is set (after their
+// current claim).  The flags are set by the poller when the host asks for a
+// stop, and by a serving wavefront that has found no work for `idle_ticks`
+// while every published request has completed: the kernel exits as a whole,
+// so no group loses its wavefronts while requests of that group can still be
+// posted.  Every posted request completes (its group's wavefronts are running
+// and its waits end), so the idle exit comes once the host stops posting.  The
+// poller exits on the host's stop or when no serving wavefront is left.
 
-__device__ __forceinline__ u64 sys_load(const u64 *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+__device__ __forceinline__ u64 sys_relaxed(const u64 *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
-__device__ __forceinline__ u64 dev_load(const u64 *p, int order) {
-  return order == 0 ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                    : __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ u64 dev_relaxed(const u64 *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void dev_store(u64 *p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A wavefront-uniform value (taken from the first active lane) in scalar
+// registers, which keeps the serving loop's state out of vector registers.
+__device__ __forceinline__ u64 uni(u64 v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((u64)hi << 32) | lo;
+}
+
+// Waits until every memory operation the wavefront has issued is acknowledged
+// at its point of coherence; the "memory" clobber keeps the compiler from
+// moving accesses across it.
+__device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 constexpr uint32_t kPersistWords = sizeof(PersistReq) / sizeof(u64);
 static_assert(kPersistWords <= 64, "a descriptor is copied by one wavefront");
@@ -1114,176 +1223,272 @@ __global__ void k_persist_init(PersistDev *dev, PersistState *st, u64 first_q) {
   if (e < kPersistRing) {
     // the entry serves the first request q >= first_q with q % ring == e
     u64 q = first_q + ((e + kPersistRing - (uint32_t)(first_q % kPersistRing)) % kPersistRing);
-    dev[e].done[0] = dev[e].done[1] = dev[e].done[2] = 0;
+    dev[e].done[0] = dev[e].done[1] = dev[e].done[2] = 0;  // generation 0: no request
     dev[e].claim = (q + 1) << 32;
+  }
+  if (e < kPersistGroups) {
+    st->group[e].posted = first_q;
+    st->group[e].stop = 0;
   }
   if (e == 0) {
     st->error = 0;
-    st->posted = first_q;
-    st->stop = 0;
     st->alive = 0;
+    st->published = first_q;
+    st->completed = first_q;
   }
 }
 
-// Before each launch of the resident kernel: clear the stop mirror and count
+// Before each launch of the resident kernel: clear the stop mirrors and count
 // the serving wavefronts.
 __global__ void k_persist_arm(PersistState *st, u64 serving) {
-  if (threadIdx.x == 0) {
-    st->stop = 0;
-    st->alive = serving;
-  }
+  if (threadIdx.x < kPersistGroups) st->group[threadIdx.x].stop = 0;
+  if (threadIdx.x == 0) st->alive = serving;
 }
 
 __device__ void persist_poller(const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
-                               PersistState *st, u64 idle_polls) {
+                               PersistState *st) {
   const uint32_t lane = threadIdx.x & 63;
   u64 pub = 0;
-  if (lane == 0) pub = dev_load(&st->posted, 0);
-  pub = __shfl(pub, 0, 64);
-  u64 quiet = 0;
+  if (lane == 0) pub = dev_relaxed(&st->published);
+  pub = uni(pub);
   while (true) {
     u64 stop = 0, posted = 0, alive = 0;
     if (lane == 0) {
-      stop = sys_load(&ctl->stop);
-      posted = sys_load(&ctl->posted);
-      alive = dev_load(&st->alive, 1);
+      stop = sys_relaxed(&ctl->stop);
+      posted = sys_relaxed(&ctl->posted);
+      alive = dev_relaxed(&st->alive);
     }
-    stop = __shfl(stop, 0, 64);
-    posted = __shfl(posted, 0, 64);
-    alive = __shfl(alive, 0, 64);
+    stop = uni(stop);
+    posted = uni(posted);
+    alive = uni(alive);
     if (stop) {
-      if (lane == 0) __hip_atomic_store(&st->stop, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane < kPersistGroups) dev_store(&st->group[lane].stop, 1ull);
       break;
     }
     if (posted > pub) {
+      // the descriptors were written before ctl->posted; the volatile loads
+      // below read host memory after the load of ctl->posted returned
       // the host posts at most kPersistRing requests beyond the oldest open one
       if (posted - pub > kPersistRing) pub = posted - kPersistRing;
       for (u64 q = pub; q < posted; ++q) {
         const uint32_t e = (uint32_t)(q % kPersistRing);
-        if (lane < kPersistWords)
-          ((u64 *)&dring[e])[lane] = ((const volatile u64 *)&ring[e])[lane];
+        if (lane < kPersistWords) dev_store((u64 *)&dring[e] + lane, ((const volatile u64 *)&ring[e])[lane]);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      if (lane == 0) __hip_atomic_store(&st->posted, posted, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      wait_mem();
+      if (lane < kPersistGroups) dev_store(&st->group[lane].posted, posted);
+      if (lane == 0) dev_store(&st->published, posted);
       pub = posted;
-      quiet = 0;
     } else {
       if (alive == 0) break;
-      if (++quiet > 4 * idle_polls) break;
       __builtin_amdgcn_s_sleep(16);
     }
   }
 }
 
-template <int LAYOUT>
-__global__ void __launch_bounds__(256) k_persist(const PersistCtl *ctl, const PersistReq *ring,
-                                                 PersistReq *dring, PersistDone *done_ring,
-                                                 PersistDev *dev, PersistState *st, u64 base_q,
-                                                 u64 idle_polls) {
-  __shared__ uint32_t T[8][256];
-  __shared__ u64 s_req[4][kPersistWords];  // per wave: the request it works on
-  __shared__ u64 s_q[4];
-  extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
-  crc_tables_build(T);
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = threadIdx.x >> 6;
-  if (blockIdx.x == 0 && wave == 0) {
-    persist_poller(ctl, ring, dring, st, idle_polls);
-    return;
+// Rounds [r, r + seg) of one table phase (operation OP) of the request whose
+// descriptor is at `req` (LDS).  One function per operation, out of line: each
+// then needs only its own registers, and the serving loop's state does not add
+// to them; that sets how many wavefronts fit on a CU.
+struct RoundTotals {
+  u64 used, live;  // changes of the table's counts (two's complement)
+  uint32_t err;    // kErr* bits
+};
+
+__device__ __forceinline__ void load_args(BulkArgs &A, const u64 *req) {
+  u64 *aw = (u64 *)&A;
+#pragma unroll
+  for (uint32_t i = 0; i < sizeof(BulkArgs) / sizeof(u64); ++i) aw[i] = uni(req[i]);
+}
+
+template <int LAYOUT, int OP, int UP>
+__device__ __attribute__((noinline)) RoundTotals persist_rounds(const uint32_t (*T)[256], uint8_t *wflag,
+                                                                u64 *wout, u64 *skeys, uint8_t *skinds,
+                                                                const u64 *req, uint32_t kind, u64 r, u64 seg) {
+  BulkArgs A;
+  load_args(A, req);
+  A.kind_sel = __builtin_amdgcn_readfirstlane(kind);
+  r = uni(r);
+  seg = uni(seg);
+  long long du = 0, dl = 0;
+  uint32_t err = 0;
+  for (u64 rr = r; rr < r + seg; ++rr) {
+    const u64 rbase = rr * ROUND;
+    const uint32_t cnt = (uint32_t)((A.n - rbase) < ROUND ? (A.n - rbase) : ROUND);
+    bulk_round<LAYOUT, OP, UP, 1, true>(A, T, wflag, wout, rbase, cnt, du, dl, err, skeys, skinds);
   }
-  const uint32_t nwb = blockDim.x >> 6;
-  uint8_t *wflag = dyn_lds + nwb * ROUND * 8 + wave * ROUND;
-  u64 *wout = (u64 *)dyn_lds + wave * ROUND;
-  const u64 gw = (u64)blockIdx.x * nwb + wave;
-  if (lane == 0) s_q[wave] = ~0ull;
-  wave_sync();
-  u64 lo = base_q;
-  u64 idle = 0;
-  while (true) {
-    u64 posted = 0, stop = 0;
-    if (lane == 0) {
-      stop = dev_load(&st->stop, 0);
-      posted = dev_load(&st->posted, 1);
+  const long long u = wave_sum(du), l = wave_sum(dl);
+  uint32_t ee = err;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ee |= __shfl_xor(ee, o, 64);
+  return RoundTotals{(u64)u, (u64)l, ee};
+}
+
+// The host-array pointers of a descriptor (after the BulkArgs words).
+struct HostArrays {
+  const void *keys;
+  const uint8_t *kinds;
+  void *vals;
+  uint8_t *flags;
+};
+
+__device__ __forceinline__ HostArrays load_host_arrays(const u64 *req) {
+  constexpr uint32_t w = sizeof(BulkArgs) / sizeof(u64);
+  return HostArrays{(const void *)uni(req[w]), (const uint8_t *)uni(req[w + 1]), (void *)uni(req[w + 2]),
+                    (uint8_t *)uni(req[w + 3])};
+}
+
+// Copy-in round r: operations [r * kCopyRound, ...) of the request's keys and
+// kinds from the caller's pinned host arrays into its device staging.  Each
+// lane issues all of its (volatile, uncached) host loads before it stores, so
+// a wavefront streams kCopyRound keys with one round trip of latency.
+template <int LAYOUT>
+__device__ __attribute__((noinline)) void persist_copy_in(const u64 *req, u64 r) {
+  typedef typename std::conditional<LAYOUT == 0, uint32_t, u64>::type K;
+  constexpr uint32_t PER = kCopyRound / 64;
+  const uint32_t lane = threadIdx.x & 63;
+  BulkArgs A;
+  load_args(A, req);
+  const HostArrays H = load_host_arrays(req);
+  r = uni(r);
+  const u64 lo = r * kCopyRound;
+  const u64 hi = A.n - lo < kCopyRound ? A.n : lo + kCopyRound;
+  K kv[PER];
+  uint8_t cv[PER];
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    const u64 i = lo + j * 64 + lane;
+    kv[j] = i < hi ? ((const volatile K *)H.keys)[i] : 0;
+    cv[j] = i < hi ? ((const volatile uint8_t *)H.kinds)[i] : 0;
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    const u64 i = lo + j * 64 + lane;
+    if (i < hi) {
+      st_out<true>((K *)A.keys + i, kv[j]);
+      st_out<true>((uint8_t *)A.kinds + i, cv[j]);
     }
-    stop = __shfl(stop, 0, 64);
-    posted = __shfl(posted, 0, 64);
-    if (stop) break;
-    bool worked = false;
-    u64 q = lo;
-    uint32_t rounds_since_check = 0;
-    while (q < posted) {
-      if (++rounds_since_check == 8) {
-        // look at the stop flag now and then while there is work
-        rounds_since_check = 0;
-        u64 sp = 0;
-        if (lane == 0) sp = dev_load(&st->stop, 0);
-        if (__shfl(sp, 0, 64)) break;
+  }
+}
+
+// Copy-out round r: the request's values (zeros when it has no finds) and
+// flags from its staging to the caller's pinned host arrays, as system-scope
+// stores (written through to the host).
+template <int LAYOUT>
+__device__ __attribute__((noinline)) void persist_copy_out(const u64 *req, u64 r, bool has_finds) {
+  typedef typename std::conditional<LAYOUT == 0, uint32_t, u64>::type K;
+  constexpr uint32_t PER = kCopyRound / 64;
+  const uint32_t lane = threadIdx.x & 63;
+  BulkArgs A;
+  load_args(A, req);
+  const HostArrays H = load_host_arrays(req);
+  r = uni(r);
+  const u64 lo = r * kCopyRound;
+  const u64 hi = A.n - lo < kCopyRound ? A.n : lo + kCopyRound;
+  if (H.vals) {
+    K vv[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+      const u64 i = lo + j * 64 + lane;
+      vv[j] = (has_finds && i < hi)
+                  ? (K)__hip_atomic_load((const K *)A.vals_out + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  : (K)0;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+      const u64 i = lo + j * 64 + lane;
+      if (i < hi) __hip_atomic_store((K *)H.vals + i, vv[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+  if (H.flags) {
+    uint8_t fv[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+      const u64 i = lo + j * 64 + lane;
+      fv[j] = i < hi ? __hip_atomic_load(A.flags + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (uint8_t)0;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+      const u64 i = lo + j * 64 + lane;
+      if (i < hi) __hip_atomic_store(H.flags + i, fv[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
+__device__ __forceinline__ u64 pick(int p, u64 a, u64 b, u64 c, u64 d, u64 e) {
+  return p == 0 ? a : p == 1 ? b : p == 2 ? c : p == 3 ? d : e;
+}
+
+// Claims and runs rounds of request q (ring entry e) until none is left to
+// claim or the stop flag is seen.  Returns whether any round was run.
+template <int LAYOUT>
+__device__ bool persist_serve(const uint32_t (*T)[256], uint8_t *wflag, u64 *wout, u64 *skeys,
+                              uint8_t *skinds, const u64 *req, PersistDev *dev, PersistDone *done_ring,
+                              PersistState *st, const u64 *stop_word, u64 q, uint32_t e, u64 gw,
+                              uint32_t &rounds_since_check, bool &stop_seen) {
+  const uint32_t lane = threadIdx.x & 63;
+  constexpr uint32_t w = sizeof(BulkArgs) / sizeof(u64) + 4;  // the rounds after the host arrays
+  const u64 R0 = uni(req[w]), R1 = uni(req[w + 1]), R2 = uni(req[w + 2]), R3 = uni(req[w + 3]),
+            R4 = uni(req[w + 4]);
+  const u64 total = R0 + R1 + R2 + R3 + R4;
+  DevStatus *status = (DevStatus *)uni(req[offsetof(BulkArgs, status) / sizeof(u64)]);
+  const u64 tag = (q + 1) << 32;
+  bool worked = false;
+  while (true) {
+    if (++rounds_since_check >= 8) {
+      // look at the stop flag now and then while there is work
+      rounds_since_check = 0;
+      u64 sp = 0;
+      if (lane == 0) sp = dev_relaxed(stop_word);
+      if (uni(sp)) {
+        stop_seen = true;
+        return worked;
       }
-      const uint32_t e = (uint32_t)(q % kPersistRing);
-      u64 c = 0;
-      if (lane == 0) c = dev_load(&dev[e].claim, 0);
-      c = __shfl(c, 0, 64);
-      if ((c >> 32) != q + 1) {
-        // generation q + 1 + kPersistRing: request q has completed
-        if ((c >> 32) > q + 1 && q == lo) ++lo;
-        ++q;
-        continue;
-      }
-      if (s_q[wave] != q) {
-        // the request's descriptor, copied into the device ring by the poller
-        if (lane < kPersistWords) s_req[wave][lane] = ((const u64 *)&dring[e])[lane];
-        wave_sync();
-        if (lane == 0) s_q[wave] = q;
-        wave_sync();
-      }
-      const BulkArgs *RA = (const BulkArgs *)&s_req[wave][0];
-      const u64 *R = &s_req[wave][sizeof(BulkArgs) / sizeof(u64)];
-      const u64 total = R[0] + R[1] + R[2];
-      int status = 2;  // 0 claimed, 1 no rounds left, 2 not now
-      u64 t = 0;
-      if (lane == 0) {
-        for (int tries = 0; tries < 256; ++tries) {
-          const u64 gen = c >> 32, cnt = c & 0xFFFFFFFFull;
-          if (gen != q + 1) {
-            status = gen > q + 1 ? 1 : 2;
-            break;
-          }
-          if (cnt >= total) {
-            status = 1;
-            break;
-          }
-          // acquire: the entry's phase counters were cleared before it was re-armed
-          if (__hip_atomic_compare_exchange_strong(&dev[e].claim, &c, c + 1, __ATOMIC_ACQUIRE,
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            status = 0;
-            t = cnt;
-            break;
-          }
+    }
+    // claim up to 4 consecutive rounds (fewer near the end of the request)
+    u64 t0 = 0, k = 0;
+    if (lane == 0) {
+      u64 c = dev_relaxed(&dev[e].claim);
+      for (int tries = 0; tries < 4; ++tries) {
+        const u64 cnt = c & 0xFFFFFFFFull;
+        if ((c >> 32) != q + 1 || cnt >= total) break;
+        u64 want = (total - cnt) >> 5;
+        want = want < 1 ? 1 : (want > 4 ? 4 : want);
+        if (__hip_atomic_compare_exchange_strong(&dev[e].claim, &c, c + want, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          t0 = cnt;
+          k = want;
+          break;
         }
       }
-      status = __shfl(status, 0, 64);
-      t = __shfl(t, 0, 64);
-      if (status == 1) {
-        if (q == lo) ++lo;
-        ++q;
-        continue;
-      }
-      if (status == 2) {
-        ++q;
-        continue;
-      }
+    }
+    k = uni(k);
+    if (k == 0) return worked;
+    t0 = uni(t0);
+    worked = true;
+    // the claimed rounds, phase by phase
+    u64 t = t0;
+    while (t < t0 + k) {
+      // phase p of round t, its index r in the phase, the phase's end pend
       int p = 0;
-      u64 r = t;
-      while (p < 2 && r >= R[p]) {
-        r -= R[p];
-        ++p;
+      u64 r = t, pend = R0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const u64 Ri = pick(i, R0, R1, R2, R3, R4);
+        if (p == i && r >= Ri) {
+          r -= Ri;
+          p = i + 1;
+          pend += pick(i + 1, R0, R1, R2, R3, R4);
+        }
       }
-      int last = 2;
-      while (last > 0 && R[last] == 0) --last;
-      if (lane == 0) {
-        for (int pp = 0; pp < p; ++pp) {
+      const u64 rp = pick(p, R0, R1, R2, R3, R4);
+      const u64 seg = (t0 + k < pend ? t0 + k : pend) - t;
+      // wait until every round of the earlier phases is finished
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        const u64 need = pick(pp, R0, R1, R2, R3, R4);
+        if (pp < p && need != 0 && lane == 0) {
           u64 spins = 0;
-          while (dev_load(&dev[e].done[pp], 1) < R[pp]) {
+          while (dev_relaxed(&dev[e].done[pp]) != (tag | need)) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins > (1ull << 26)) {
               atomicOr(&st->error, 1ull);
@@ -1292,65 +1497,175 @@ __global__ void __launch_bounds__(256) k_persist(const PersistCtl *ctl, const Pe
           }
         }
       }
+      // (their writes completed before their counters moved; the loads below
+      // are issued after that was seen)
       wave_sync();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      BulkArgs A = *RA;
-      A.kind_sel = (uint32_t)p;
-      const u64 rbase = r * ROUND;
-      const uint32_t cnt = (uint32_t)((A.n - rbase) < ROUND ? (A.n - rbase) : ROUND);
-      long long du = 0, dl = 0;
-      uint32_t err = 0;
       if (p == 0) {
-        bulk_round<LAYOUT, OP_FIND, 0, 1, true>(A, T, wflag, wout, rbase, cnt, du, dl, err);
-      } else if (p == 1) {
-        bulk_round<LAYOUT, OP_UPSERT, 1, 1, true>(A, T, wflag, wout, rbase, cnt, du, dl, err);
+        for (u64 rr = r; rr < r + seg; ++rr) persist_copy_in<LAYOUT>(req, rr);
+      } else if (p == 4) {
+        for (u64 rr = r; rr < r + seg; ++rr) persist_copy_out<LAYOUT>(req, rr, R1 != 0);
       } else {
-        bulk_round<LAYOUT, OP_ERASE, 0, 1, true>(A, T, wflag, wout, rbase, cnt, du, dl, err);
+        RoundTotals rt;
+        if (p == 1)
+          rt = persist_rounds<LAYOUT, OP_FIND, 0>(T, wflag, wout, skeys, skinds, req, 0, r, seg);
+        else if (p == 2)
+          rt = persist_rounds<LAYOUT, OP_UPSERT, 1>(T, wflag, wout, skeys, skinds, req, 1, r, seg);
+        else
+          rt = persist_rounds<LAYOUT, OP_ERASE, 0>(T, wflag, wout, skeys, skinds, req, 2, r, seg);
+        const u64 u = uni(rt.used), l = uni(rt.live), ee = uni(rt.err);
+        if (lane == 0) {
+          CountSlot *cs = &status->slot[gw % kCountSlots];
+          if (u) add64(&cs->used, u);
+          if (l) add64(&cs->live, l);
+          if (ee) atomicOr(&status->err, (uint32_t)ee);
+        }
       }
-      const long long u = wave_sum(du), l = wave_sum(dl);
-      uint32_t ee = err;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) ee |= __shfl_xor(ee, o, 64);
+      // the rounds' writes (staging, table, counts, host results) complete
+      // before the rounds are counted as finished
+      wait_mem();
+      wave_sync();
       if (lane == 0) {
-        CountSlot *cs = &A.status->slot[gw % kCountSlots];
-        if (u) add64(&cs->used, (u64)u);
-        if (l) add64(&cs->live, (u64)l);
-        if (ee) atomicOr(&A.status->err, ee);
-      }
-      // the round's table updates and its results in host memory are
-      // performed before the round counts as finished
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-      if (lane == 0) {
-        const u64 d = __hip_atomic_fetch_add(&dev[e].done[p], 1ull, __ATOMIC_ACQ_REL,
-                                             __HIP_MEMORY_SCOPE_AGENT) + 1;
-        if (d == R[p] && p == last) {
+        u64 cur = dev_relaxed(&dev[e].done[p]), nv;
+        do {
+          nv = ((cur & ~0xFFFFFFFFull) == tag) ? cur + seg : (tag | seg);
+        } while (!__hip_atomic_compare_exchange_weak(&dev[e].done[p], &cur, nv, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if ((nv & 0xFFFFFFFFull) == rp && p == kPersistPhases - 1) {
+          // the last copy-out round: the request is complete
           u64 used = 0, live = 0;
-          for (int k = 0; k < kCountSlots; ++k) {
-            used += dev_load(&A.status->slot[k].used, 0);
-            live += dev_load(&A.status->slot[k].live, 0);
+          for (int kk = 0; kk < kCountSlots; ++kk) {
+            used += dev_relaxed(&status->slot[kk].used);
+            live += dev_relaxed(&status->slot[kk].live);
           }
-          const u64 errbits = __hip_atomic_load(&A.status->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          for (int k = 0; k < 3; ++k)
-            __hip_atomic_store(&dev[e].done[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&dev[e].claim, (q + kPersistRing + 1) << 32, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
+          const u64 errbits = __hip_atomic_load(&status->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          dev_store(&dev[e].claim, (q + kPersistRing + 1) << 32);
           PersistDone *dn = &done_ring[e];
           __hip_atomic_store(&dn->used, used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           __hip_atomic_store(&dn->live, live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           __hip_atomic_store(&dn->err, errbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-          __hip_atomic_store(&dn->seq, q + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+          wait_mem();  // the counts before the sequence number
+          __hip_atomic_store(&dn->seq, q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          __hip_atomic_fetch_add(&st->completed, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
-      worked = true;
-    }
-    if (!worked) {
-      if (++idle > idle_polls) break;
-      __builtin_amdgcn_s_sleep(32);
-    } else {
-      idle = 0;
+      t += seg;
     }
   }
-  if (lane == 0) __hip_atomic_fetch_add(&st->alive, ~0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int LAYOUT>
+__global__ void __launch_bounds__(256, 4) k_persist(const PersistCtl *ctl, const PersistReq *ring,
+                                                 PersistReq *dring, PersistDone *done_ring,
+                                                 PersistDev *dev, PersistState *st, u64 base_q,
+                                                 u64 idle_ticks) {
+  __shared__ uint32_t T[8][256];
+  __shared__ u64 s_req[4][kPersistWords];  // per wave: the request it works on
+  __shared__ u64 s_q[4];
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
+  crc_tables_build(T);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (blockIdx.x == 0 && wave == 0) {
+    persist_poller(ctl, ring, dring, st);
+    return;
+  }
+  const uint32_t nwb = blockDim.x >> 6;
+  // per wave: values (ROUND u64), staged keys (ROUND u64), flags, kinds (ROUND bytes each)
+  u64 *wout = (u64 *)dyn_lds + wave * ROUND;
+  u64 *skeys = (u64 *)dyn_lds + (nwb + wave) * ROUND;
+  uint8_t *wflag = dyn_lds + 2 * nwb * ROUND * 8 + wave * ROUND;
+  uint8_t *skinds = dyn_lds + 2 * nwb * ROUND * 8 + (nwb + wave) * ROUND;
+  const u64 gw = (u64)blockIdx.x * nwb + wave;
+  const uint32_t g = blockIdx.x % kPersistGroups;
+  const u64 *posted_word = &st->group[g].posted;
+  const u64 *stop_word = &st->group[g].stop;
+  // where this wavefront starts among its group's open requests (a hash of its
+  // index), so that few wavefronts contend for one claim word
+  const uint32_t spread = (uint32_t)((gw * 0x9E3779B97F4A7C15ull) >> 58);
+  if (lane == 0) s_q[wave] = ~0ull;
+  wave_sync();
+  // the group's requests: q = g, g + G, g + 2G, ... (G = kPersistGroups)
+  u64 lo = base_q + (g + kPersistGroups - (uint32_t)(base_q % kPersistGroups)) % kPersistGroups;
+  u64 seen = 0;        // the largest posted count acquired so far
+  bool rescan = true;  // something may be claimable
+  u64 idle_since = 0;
+  uint32_t pause = 1;
+  uint32_t rounds_since_check = 0;
+  while (true) {
+    u64 posted = 0, stop = 0;
+    if (lane == 0) {
+      stop = dev_relaxed(stop_word);
+      posted = dev_relaxed(posted_word);
+    }
+    stop = uni(stop);
+    posted = uni(posted);
+    if (stop) break;
+    if (posted > seen) {
+      // the poller stored the new descriptors before the count
+      seen = posted;
+      rescan = true;
+    }
+    bool worked = false, stop_seen = false;
+    if (rescan) {
+      // scan the group's open requests 64 at a time, one claim word per lane;
+      // requests whose generation moved on have completed
+      for (u64 base = lo; base < seen && !stop_seen; base += 64 * kPersistGroups) {
+        const u64 qv = base + (u64)lane * kPersistGroups;
+        const bool valid = qv < seen;
+        u64 cw = 0;
+        if (valid) cw = dev_relaxed(&dev[qv % kPersistRing].claim);
+        const u64 notfin = __ballot(!(valid && (cw >> 32) > qv + 1));
+        if (base == lo) lo += (notfin ? (u64)__builtin_ctzll(notfin) : 64) * kPersistGroups;
+        u64 cand = __ballot(valid && (cw >> 32) == qv + 1);
+        while (cand && !stop_seen) {
+          const u64 from = cand & (~0ull << spread);
+          const uint32_t j = (uint32_t)__builtin_ctzll(from ? from : cand);
+          cand &= ~(1ull << j);
+          const u64 q = base + (u64)j * kPersistGroups;
+          const uint32_t e = (uint32_t)(q % kPersistRing);
+          if (s_q[wave] != q) {
+            // the request's descriptor, copied into the device ring by the poller
+            if (lane < kPersistWords) s_req[wave][lane] = coh_load((const u64 *)&dring[e] + lane);
+            wave_sync();
+            if (lane == 0) s_q[wave] = q;
+            wave_sync();
+          }
+          worked |= persist_serve<LAYOUT>(T, wflag, wout, skeys, skinds, &s_req[wave][0], dev, done_ring, st, stop_word,
+                                          q, e, gw, rounds_since_check, stop_seen);
+        }
+      }
+    }
+    if (stop_seen) break;
+    if (worked) {
+      rescan = true;
+      idle_since = 0;
+      pause = 1;
+      continue;
+    }
+    // a full scan found nothing to claim: nothing new until more is posted
+    rescan = false;
+    const u64 now = wall_clock64();
+    if (idle_since == 0) {
+      idle_since = now;
+    } else if (now - idle_since > idle_ticks) {
+      u64 pub = 0, comp = 0;
+      if (lane == 0) {
+        pub = dev_relaxed(&st->published);
+        comp = dev_relaxed(&st->completed);
+      }
+      pub = uni(pub);
+      comp = uni(comp);
+      if (pub == comp) {
+        // nothing open anywhere: the whole kernel exits
+        if (lane < kPersistGroups) dev_store(&st->group[lane].stop, 1ull);
+        break;
+      }
+      idle_since = now;  // requests of other groups are open: keep serving
+    }
+    for (uint32_t i = 0; i < pause; ++i) __builtin_amdgcn_s_sleep(127);
+    if (pause < 8) pause *= 2;
+  }
+  if (lane == 0) __hip_atomic_fetch_add(&st->alive, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1488,18 +1803,18 @@ hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first
 
 hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
                           PersistDone *done, PersistDev *dev, PersistState *st, uint64_t base_q,
-                          uint64_t idle_polls, uint32_t grid, hipStream_t s) {
-  if (grid < 1) return hipErrorInvalidValue;
-  const size_t lds = 4 * (size_t)ROUND * 9;
+                          uint64_t idle_ticks, uint32_t grid, hipStream_t s) {
+  if (grid < kPersistGroups || grid % kPersistGroups) return hipErrorInvalidValue;
+  const size_t lds = 4 * (size_t)ROUND * 18;
   hipLaunchKernelGGL(k_persist_arm, dim3(1), dim3(64), 0, s, st, (u64)grid * 4 - 1);
   hipError_t rc = hipGetLastError();
   if (rc != hipSuccess) return rc;
   if (layout == 0)
     hipLaunchKernelGGL(k_persist<0>, dim3(grid), dim3(256), lds, s, ctl, ring, dring, done, dev, st,
-                       (u64)base_q, (u64)idle_polls);
+                       (u64)base_q, (u64)idle_ticks);
   else
     hipLaunchKernelGGL(k_persist<1>, dim3(grid), dim3(256), lds, s, ctl, ring, dring, done, dev, st,
-                       (u64)base_q, (u64)idle_polls);
+                       (u64)base_q, (u64)idle_ticks);
   return hipGetLastError();
 }
 

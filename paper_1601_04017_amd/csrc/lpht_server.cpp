@@ -17,6 +17,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -60,6 +61,7 @@ struct Req {
   void *dbuf = nullptr;
   size_t dbytes = 0;
   uint64_t need = 0;  // bytes accounted by admission (staging and growth)
+  uint64_t arena_off = ~0ull;  // resident mode: the request's staging in the arena
 };
 
 struct Group {
@@ -115,6 +117,10 @@ struct lpht_server {
   hipEvent_t persist_ev = nullptr;
   std::vector<Req *> grow_wait;    // admitted, waiting for their table to grow
   uint32_t persist_grid = 0;
+  unsigned char *arena = nullptr;  // resident mode: device staging of requests in flight
+  uint64_t arena_bytes = 0;
+  std::map<uint64_t, uint64_t> arena_free;  // offset -> length of free ranges
+  uint64_t idle_ticks = 0;         // kIdleExitMs in ticks of the device's constant clock
   uint64_t persist_launches = 0;
   bool persist_failed = false;     // a bounded wait in the kernel expired
 };
@@ -122,7 +128,7 @@ struct lpht_server {
 namespace {
 
 uint64_t table_bytes(const lpht_server *S) {
-  uint64_t b = 0;
+  uint64_t b = S->arena_bytes;
   for (auto *t : S->tables) b += cell_bytes(t->cfg.layout) << t->log2c;
   return b;
 }
@@ -146,6 +152,36 @@ uint64_t growth_bytes(const lpht_table *t, uint64_t b) {
 size_t staging_size(const lpht_server *S, const Req *q) {
   const size_t n = q->r.n;
   return 2 * round256(n * S->kb) + 2 * round256(n);
+}
+
+// Resident mode: best fit in the staging arena (256-byte granules).
+uint64_t arena_alloc(lpht_server *S, uint64_t bytes) {
+  bytes = round256(bytes);
+  auto best = S->arena_free.end();
+  for (auto it = S->arena_free.begin(); it != S->arena_free.end(); ++it)
+    if (it->second >= bytes && (best == S->arena_free.end() || it->second < best->second)) best = it;
+  if (best == S->arena_free.end()) return ~0ull;
+  const uint64_t off = best->first, len = best->second;
+  S->arena_free.erase(best);
+  if (len > bytes) S->arena_free[off + bytes] = len - bytes;
+  return off;
+}
+
+void arena_release(lpht_server *S, uint64_t off, uint64_t bytes) {
+  bytes = round256(bytes);
+  auto next = S->arena_free.lower_bound(off);
+  if (next != S->arena_free.end() && off + bytes == next->first) {
+    bytes += next->second;
+    next = S->arena_free.erase(next);
+  }
+  if (next != S->arena_free.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += bytes;
+      return;
+    }
+  }
+  S->arena_free[off] = bytes;
 }
 
 void finish_locked(lpht_server *S, Req *q) {
@@ -291,9 +327,15 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
         S->next_q + S->grow_wait.size() + out.size() >= S->oldest_q + kPersistRing)
       break;  // the ring entry of the oldest request is still in use
     Req *q = S->fifo[t].front();
-    const uint64_t staging = S->cfg.mode == LPHT_SERVE_PERSISTENT ? 0 : staging_size(S, q);
+    const bool resident = S->cfg.mode == LPHT_SERVE_PERSISTENT;
+    // resident mode: the staging comes from the arena, which the budget
+    // already counts
+    const uint64_t staging = resident ? 0 : staging_size(S, q);
     const uint64_t need = staging + growth_bytes(S->tables[t], q->count[1]);
-    if (S->cfg.hbm_budget && hbm + need > S->cfg.hbm_budget) {
+    uint64_t off = ~0ull;
+    const bool fits_arena = !resident || (off = arena_alloc(S, staging_size(S, q))) != ~0ull;
+    if (!fits_arena || (S->cfg.hbm_budget && hbm + need > S->cfg.hbm_budget)) {
+      if (off != ~0ull) arena_release(S, off, staging_size(S, q));
       if (S->inflight_reqs == 0 && S->grow_wait.empty() && out.empty()) {
         // nothing will free memory: this request can never run
         S->fifo[t].pop_front();
@@ -312,6 +354,7 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
     S->fifo[t].pop_front();
     S->busy[t] = 1;
     q->need = need;
+    q->arena_off = off;
     hbm += need;
     S->staging_bytes += need;
     out.push_back(q);
@@ -321,13 +364,15 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
 
 // ---- persistent mode ----
 
-uint64_t idle_polls() { return 20000; }
+// The resident kernel exits after this long without work (a new request then
+// relaunches it).
+constexpr double kIdleExitMs = 20.0;
 
 void persist_launch(lpht_server *S) {
   hipStream_t s = S->streams[0];
   __atomic_store_n(&S->pctl->stop, 0ull, __ATOMIC_RELEASE);
   if (launch_persist(S->cfg.layout, S->pctl, S->pring, S->pdring, S->pdone, S->pdev, S->pst,
-                     S->oldest_q, idle_polls(), S->persist_grid, s) == hipSuccess) {
+                     S->oldest_q, S->idle_ticks, S->persist_grid, s) == hipSuccess) {
     (void)hipEventRecord(S->persist_ev, s);
     S->running = true;
     S->persist_launches++;
@@ -354,17 +399,26 @@ void persist_post(lpht_server *S, Req *q) {
   const uint32_t e = (uint32_t)(qn % kPersistRing);
   lpht_table *t = S->tables[q->r.table];
   PersistReq &R = S->pring[e];
+  const size_t n = q->r.n;
+  unsigned char *base = S->arena + q->arena_off;
   BulkArgs a = make_args(t);
-  a.keys = q->r.keys;
+  a.keys = base;
   a.vals = nullptr;  // increments by one
-  a.n = q->r.n;
-  a.vals_out = q->r.vals_out;
-  a.flags = q->r.flags;
+  a.n = n;
+  a.vals_out = base + round256(n * S->kb);
+  a.flags = base + 2 * round256(n * S->kb) + round256(n);
   a.up = LPHT_ADD;
-  a.kinds = q->r.kinds;
+  a.kinds = base + 2 * round256(n * S->kb);
   a.kind_sel = 0;
   R.a = a;
-  for (int k = 0; k < 3; ++k) R.rounds[k] = q->count[k] ? (q->r.n + kRound - 1) / kRound : 0;
+  R.hkeys = q->r.keys;
+  R.hkinds = q->r.kinds;
+  R.hvals = q->r.vals_out;
+  R.hflags = q->r.flags;
+  const unsigned long long copy_rounds = (n + kCopyRound - 1) / kCopyRound;
+  R.rounds[0] = copy_rounds;
+  for (int k = 0; k < 3; ++k) R.rounds[k + 1] = q->count[k] ? (n + kRound - 1) / kRound : 0;
+  R.rounds[4] = copy_rounds;
   __atomic_store_n(&R.seq, qn + 1, __ATOMIC_RELEASE);
   t->mods_since_exact++;
   S->pentry[e] = q;
@@ -391,9 +445,9 @@ bool persist_retire(lpht_server *S) {
     T->pending = 0;
     T->mods_since_exact = 0;
     S->busy[q->r.table] = 0;
-    if (q->r.vals_out && q->count[0] == 0) std::memset(q->r.vals_out, 0, q->r.n * S->kb);
     q->c.done_us = now_us();
     S->staging_bytes -= q->need;
+    arena_release(S, q->arena_off, staging_size(S, q));
     S->pentry[e] = nullptr;
     if (--S->inflight_reqs == 0) S->st.busy_us += now_us() - S->busy_since;
     fin.push_back(q);
@@ -435,6 +489,7 @@ bool persist_step(lpht_server *S, std::vector<Req *> &admitted) {
           q->c.admit_us = q->c.done_us = now_us();
           S->busy[q->r.table] = 0;
           S->staging_bytes -= q->need;
+          arena_release(S, q->arena_off, staging_size(S, q));
           {
             std::lock_guard<std::mutex> lk(S->mu);
             finish_locked(S, q);
@@ -557,6 +612,7 @@ void destroy_all(lpht_server *S) {
   if (S->pring) (void)hipHostFree(S->pring);
   if (S->pdone) (void)hipHostFree(S->pdone);
   if (S->pdring) (void)hipFree(S->pdring);
+  if (S->arena) (void)hipFree(S->arena);
   if (S->pdev) (void)hipFree(S->pdev);
   if (S->pst) (void)hipFree(S->pst);
   if (S->persist_ev) (void)hipEventDestroy(S->persist_ev);
@@ -642,12 +698,34 @@ int lpht_server_create(const lpht_server_config *cfg, lpht_server **out) {
       destroy_all(S);
       return LPHT_ERR_OOM;
     }
+    // staging arena: 1 GiB, or a quarter of what the budget leaves beside
+    // the tables (at least 16 MiB)
+    uint64_t ab = 1ull << 30;
+    if (cfg->hbm_budget) {
+      uint64_t tb = 0;
+      for (auto *t : S->tables) tb += cell_bytes(t->cfg.layout) << t->log2c;
+      const uint64_t spare = cfg->hbm_budget > tb ? cfg->hbm_budget - tb : 0;
+      ab = std::min<uint64_t>(ab, std::max<uint64_t>(16ull << 20, spare / 4));
+    }
+    if (hipMalloc((void **)&S->arena, ab) != hipSuccess) {
+      destroy_all(S);
+      return LPHT_ERR_OOM;
+    }
+    S->arena_bytes = ab;
+    S->arena_free[0] = ab;
     std::memset(S->pctl, 0, sizeof(PersistCtl));
     std::memset(S->pring, 0, sizeof(PersistReq) * kPersistRing);
     std::memset(S->pdone, 0, sizeof(PersistDone) * kPersistRing);
     int ncu = 0;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, S->device);
-    S->persist_grid = (uint32_t)(ncu > 0 ? 2 * ncu : 512);
+    // four workgroups of 256 per CU: the resident kernel is built for 4
+    // wavefronts per SIMD
+    S->persist_grid = (uint32_t)(ncu > 0 ? 4 * ncu : 1024);
+    S->persist_grid = std::max<uint32_t>(kPersistGroups, S->persist_grid / kPersistGroups * kPersistGroups);
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) != hipSuccess || khz <= 0)
+      khz = 100000;
+    S->idle_ticks = (uint64_t)(kIdleExitMs * khz);
     if (launch_persist_init(S->pdev, S->pst, 0, S->streams[0]) != hipSuccess ||
         hipStreamSynchronize(S->streams[0]) != hipSuccess) {
       destroy_all(S);
