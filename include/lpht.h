@@ -287,12 +287,14 @@ int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void 
  *                       stopped, the table migrates, and it is relaunched.
  *                       Request arrays must be pinned host memory (or device
  *                       memory); submit rejects others with
- *                       LPHT_ERR_INVALID.  The staging arena is 1 GiB, or a
- *                       quarter of what hbm_budget leaves beside the initial
- *                       tables (at least 16 MiB); a request needs
- *                       about (2 * key bytes + 2) * n of it while in flight,
- *                       and one that can never fit completes with
- *                       LPHT_ERR_OOM.
+ *                       LPHT_ERR_INVALID.
+ * Every mode stages a request's keys, kinds, values and flags in a device
+ * arena the server allocates once: 1 GiB, or what hbm_budget leaves beside the
+ * initial tables (at least 1 MiB).  A request needs about (2 * key bytes + 2)
+ * * n bytes of it while in flight; the budget counts tables, the staging in
+ * use and the memory a request's growth would allocate.  A request that could
+ * never be admitted (larger than the arena or the budget with nothing in
+ * flight) completes with LPHT_ERR_OOM.
  * Tables grow before a request's increments by the growth rule (bulk
  * pre-growth, Sec. 5.5), which also removes tombstones (Sec. 5.4); the counts
  * the rule needs are read back after every request without synchronising.
@@ -310,11 +312,11 @@ typedef struct lpht_server_config {
   uint32_t ntables;
   uint32_t layout;                 /* LPHT_KV64 or LPHT_PACKED32 */
   const uint32_t *log2_capacity;   /* host, ntables initial capacities (auto-growing tables) */
-  uint32_t mode;                   /* LPHT_SERVE_WAVES or LPHT_SERVE_SINGLE */
+  uint32_t mode;                   /* LPHT_SERVE_WAVES, _SINGLE or _PERSISTENT */
   uint32_t max_inflight;           /* request slots, 1..4096 */
   uint32_t streams;                /* device streams for launches, 1..8 */
   uint32_t reserved;               /* must be 0 */
-  uint64_t hbm_budget;             /* bytes for tables, staging and growth; 0 = no limit */
+  uint64_t hbm_budget;             /* bytes for tables, staging in use and growth; 0 = no limit */
 } lpht_server_config;
 
 typedef struct lpht_request {

@@ -58,8 +58,6 @@ struct Req {
   uint32_t count[3];  // operations per kind
   lpht_completion c;
   bool done = false;
-  void *dbuf = nullptr;
-  size_t dbytes = 0;
   uint64_t need = 0;  // bytes accounted by admission (staging and growth)
   uint64_t arena_off = ~0ull;  // resident mode: the request's staging in the arena
 };
@@ -128,7 +126,7 @@ struct lpht_server {
 namespace {
 
 uint64_t table_bytes(const lpht_server *S) {
-  uint64_t b = S->arena_bytes;
+  uint64_t b = 0;
   for (auto *t : S->tables) b += cell_bytes(t->cfg.layout) << t->log2c;
   return b;
 }
@@ -214,9 +212,7 @@ void launch_group(lpht_server *S, std::vector<Req *> &group) {
     q->c.admit_us = t_admit;
     q->c.wave = S->group_seq;
     const size_t n = q->r.n;
-    q->dbytes = staging_size(S, q);
-    q->dbuf = pool_alloc(S->device, q->dbytes, s);
-    unsigned char *base = (unsigned char *)q->dbuf;
+    unsigned char *base = S->arena + q->arena_off;  // the request's staging
     void *dkeys = base;
     void *dvals = base + round256(n * S->kb);
     uint8_t *dkinds = base + 2 * round256(n * S->kb);
@@ -224,10 +220,6 @@ void launch_group(lpht_server *S, std::vector<Req *> &group) {
     lpht_table *t = S->tables[q->r.table];
     g.tables.push_back(q->r.table);
     g.reqs.push_back(q);
-    if (!q->dbuf) {
-      q->c.status = LPHT_ERR_OOM;
-      continue;
-    }
     (void)hipMemcpyAsync(dkeys, q->r.keys, n * S->kb, hipMemcpyHostToDevice, s);
     (void)hipMemcpyAsync(dkinds, q->r.kinds, n, hipMemcpyHostToDevice, s);
     const uint32_t kind_op[3] = {LPHT_OP_FIND, LPHT_OP_UPSERT, LPHT_OP_ERASE};
@@ -262,17 +254,14 @@ void launch_group(lpht_server *S, std::vector<Req *> &group) {
                        hipMemcpyDeviceToHost, s);
   g.stream = si;
   for (Req *q : group) {
-    if (!q->dbuf) continue;
     const size_t n = q->r.n;
-    unsigned char *base = (unsigned char *)q->dbuf;
+    unsigned char *base = S->arena + q->arena_off;
     if (q->r.vals_out && q->count[0])
       (void)hipMemcpyAsync(q->r.vals_out, base + round256(n * S->kb), n * S->kb,
                            hipMemcpyDeviceToHost, s);
     if (q->r.flags)
       (void)hipMemcpyAsync(q->r.flags, base + 2 * round256(n * S->kb) + round256(n), n,
                            hipMemcpyDeviceToHost, s);
-    (void)hipFreeAsync(q->dbuf, s);
-    q->dbuf = nullptr;
   }
   (void)hipEventRecord(g.ev, s);
   if (S->inflight.empty()) S->busy_since = now_us();
@@ -297,6 +286,7 @@ void retire_group(lpht_server *S, Group &g) {
     if (q->r.vals_out && q->count[0] == 0) std::memset(q->r.vals_out, 0, q->r.n * S->kb);
     q->c.done_us = t;
     S->staging_bytes -= q->need;
+    arena_release(S, q->arena_off, staging_size(S, q));
   }
   S->inflight_reqs -= (uint32_t)g.reqs.size();
   S->spare_events.push_back(g.ev);
@@ -327,15 +317,12 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
         S->next_q + S->grow_wait.size() + out.size() >= S->oldest_q + kPersistRing)
       break;  // the ring entry of the oldest request is still in use
     Req *q = S->fifo[t].front();
-    const bool resident = S->cfg.mode == LPHT_SERVE_PERSISTENT;
-    // resident mode: the staging comes from the arena, which the budget
-    // already counts
-    const uint64_t staging = resident ? 0 : staging_size(S, q);
-    const uint64_t need = staging + growth_bytes(S->tables[t], q->count[1]);
+    // the staging comes from the arena; the budget counts it while in use
+    const uint64_t staging = staging_size(S, q);
+    const uint64_t need = round256(staging) + growth_bytes(S->tables[t], q->count[1]);
     uint64_t off = ~0ull;
-    const bool fits_arena = !resident || (off = arena_alloc(S, staging_size(S, q))) != ~0ull;
-    if (!fits_arena || (S->cfg.hbm_budget && hbm + need > S->cfg.hbm_budget)) {
-      if (off != ~0ull) arena_release(S, off, staging_size(S, q));
+    const bool over = S->cfg.hbm_budget && hbm + need > S->cfg.hbm_budget;
+    if (over || (off = arena_alloc(S, staging)) == ~0ull) {
       if (S->inflight_reqs == 0 && S->grow_wait.empty() && out.empty()) {
         // nothing will free memory: this request can never run
         S->fifo[t].pop_front();
@@ -685,6 +672,22 @@ int lpht_server_create(const lpht_server_config *cfg, lpht_server **out) {
     destroy_all(S);
     return LPHT_ERR_DEVICE;
   }
+  {
+    // staging arena: 1 GiB, or what the budget leaves beside the initial
+    // tables (at least 1 MiB)
+    uint64_t ab = 1ull << 30;
+    if (cfg->hbm_budget) {
+      const uint64_t tb = table_bytes(S);
+      const uint64_t spare = cfg->hbm_budget > tb ? cfg->hbm_budget - tb : 0;
+      ab = std::min<uint64_t>(ab, std::max<uint64_t>(1ull << 20, round256(spare)));
+    }
+    if (hipMalloc((void **)&S->arena, ab) != hipSuccess) {
+      destroy_all(S);
+      return LPHT_ERR_OOM;
+    }
+    S->arena_bytes = ab;
+    S->arena_free[0] = ab;
+  }
   if (cfg->mode == LPHT_SERVE_PERSISTENT) {
     if (hipHostMalloc((void **)&S->pctl, sizeof(PersistCtl), hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc((void **)&S->pring, sizeof(PersistReq) * kPersistRing, hipHostMallocCoherent) !=
@@ -698,21 +701,6 @@ int lpht_server_create(const lpht_server_config *cfg, lpht_server **out) {
       destroy_all(S);
       return LPHT_ERR_OOM;
     }
-    // staging arena: 1 GiB, or a quarter of what the budget leaves beside
-    // the tables (at least 16 MiB)
-    uint64_t ab = 1ull << 30;
-    if (cfg->hbm_budget) {
-      uint64_t tb = 0;
-      for (auto *t : S->tables) tb += cell_bytes(t->cfg.layout) << t->log2c;
-      const uint64_t spare = cfg->hbm_budget > tb ? cfg->hbm_budget - tb : 0;
-      ab = std::min<uint64_t>(ab, std::max<uint64_t>(16ull << 20, spare / 4));
-    }
-    if (hipMalloc((void **)&S->arena, ab) != hipSuccess) {
-      destroy_all(S);
-      return LPHT_ERR_OOM;
-    }
-    S->arena_bytes = ab;
-    S->arena_free[0] = ab;
     std::memset(S->pctl, 0, sizeof(PersistCtl));
     std::memset(S->pring, 0, sizeof(PersistReq) * kPersistRing);
     std::memset(S->pdone, 0, sizeof(PersistDone) * kPersistRing);
