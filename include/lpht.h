@@ -109,7 +109,13 @@ typedef struct lpht_tuning {
   uint32_t blocks_per_cu; /* resident workgroups per compute unit the grid is sized for, 1..32 */
   uint32_t migrate_block; /* old cells per migration workgroup, power of two 256..8192 */
   uint32_t aggregate;     /* 1 (default): combine equal keys in LDS before LPHT_ADD upserts */
-  uint32_t reserved[3];
+  /* Group width by fill quarter, used / capacity in [0, 1/4), [1/4, 1/2),
+   * [1/2, 3/4), [3/4, 1] (the host's bound on `used` after the call): for
+   * finds, and for the operations that modify the table.  0 = group_width.
+   * Long probe runs at high fill are scanned faster by wider groups. */
+  uint8_t g_find[4];
+  uint8_t g_modify[4];
+  uint32_t reserved;      /* must be 0 */
 } lpht_tuning;
 
 typedef struct lpht_stats {
@@ -203,6 +209,32 @@ int lpht_status(lpht_table *t, void *stream);
  * leaves the previous tuning in place.  `lpht_get_tuning` reads them back. */
 int lpht_set_tuning(lpht_table *t, const lpht_tuning *tuning);
 int lpht_get_tuning(const lpht_table *t, lpht_tuning *tuning);
+
+/* Autotuning.  Times candidate launch shapes on scratch tables of
+ * 2^log2_capacity cells of `layout` (auto_grow off), filled with synthetic
+ * distinct keys generated on the device, and returns in `out` the fastest:
+ *   - per fill quarter (fill 1/8, 3/8, 5/8, 7/8): the group width for finds
+ *     (half present, half absent keys, a quarter of the capacity) and for
+ *     inserts (the last capacity/16 keys before that fill), each over
+ *     {1, 2, 4, 8, 16} -> g_find, g_modify; group_width = the fill-3/8 finds'
+ *     choice;
+ *   - block_threads over {256, 512, 1024} at fill 3/8 with those widths;
+ *   - migrate_block over {256, 512, 1024, 2048}: doubling a table at fill 7/16
+ *     (lpht_grow);
+ *   - blocks_per_cu 8 and aggregate 1 as the defaults.
+ * Each candidate is the fastest of `reps` (>= 1) timed runs (HIP events on
+ * `stream`), each from a table rebuilt to the same state.  Needs about
+ * (cell bytes + 1.5 * key bytes + 1) * 2^log2_capacity + 2 * (cell bytes) *
+ * 2^log2_capacity bytes of device memory, all freed before it returns;
+ * log2_capacity 16..30.  `report` (may be NULL) receives the timings (ms). */
+typedef struct lpht_autotune_report {
+  double find_ms[4][5];   /* [fill quarter][group width 1, 2, 4, 8, 16] */
+  double insert_ms[4][5];
+  double block_ms[3];     /* block_threads 256, 512, 1024 */
+  double migrate_ms[4];   /* migrate_block 256, 512, 1024, 2048 */
+} lpht_autotune_report;
+int lpht_autotune(uint32_t layout, uint32_t log2_capacity, uint32_t reps, void *stream, lpht_tuning *out,
+                  lpht_autotune_report *report);
 
 /* Migration statistics.  With `timing` = 1 every data migration is bracketed
  * by HIP events on its stream and migrate_ms accumulates their elapsed time

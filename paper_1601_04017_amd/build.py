@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblpht.so")
-SOURCES = ["lpht_kernels.hip", "lpht_api.cpp", "lpht_server.cpp"]
+SOURCES = ["lpht_kernels.hip", "lpht_api.cpp", "lpht_server.cpp", "lpht_tune.cpp"]
 ROOFLINE_OUT = os.path.join(PKG, "libroofline.so")
 ROOFLINE_SOURCES = ["lpht_roofline.hip"]
 HEADERS = ["lpht_internal.h", "lpht_host.h", os.path.join("..", "..", "include", "lpht.h")]

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <mutex>
 #include <new>
 #include <vector>
@@ -112,7 +114,21 @@ bool tuning_ok(const lpht_tuning *u) {
       (u->migrate_block & (u->migrate_block - 1)))
     return false;
   if (u->aggregate > 1) return false;
+  for (int i = 0; i < 4; ++i)
+    for (uint8_t g : {u->g_find[i], u->g_modify[i]})
+      if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16) return false;
+  if (u->reserved) return false;
   return true;
+}
+
+// The group width for an operation on `t`: by the fill quarter of the host's
+// bound on `used` (after the call's insertions), else the table's default.
+uint32_t pick_group_width(const lpht_table *t, OpKind op) {
+  const uint64_t c = 1ull << t->log2c;
+  const uint64_t used = std::min<uint64_t>(c, t->known_used + t->pending);
+  const uint32_t qi = (uint32_t)std::min<uint64_t>(3, (unsigned __int128)used * 4 / c);
+  const uint8_t g = op == OP_FIND ? t->tuning.g_find[qi] : t->tuning.g_modify[qi];
+  return g ? g : t->tuning.group_width;
 }
 
 bool within_fill(const lpht_table *t, uint64_t x, uint64_t c) {
@@ -309,7 +325,9 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
                  t->known_used + t->pending <= (1ull << t->log2c))
                     ? 1u
                     : 0u;
-  return from_hip(launch_bulk(op, a, t->launch, s));
+  LaunchCfg cfg = t->launch;
+  cfg.group_width = pick_group_width(t, op);
+  return from_hip(launch_bulk(op, a, cfg, s));
 }
 
 }  // namespace host

@@ -152,6 +152,9 @@ struct alignas(128) PersistState { // device memory
   PersistGroupCtl group[kPersistGroups];
 };
 
+// Synthetic distinct keys for timing runs (layout 0: u32, 1: u64).
+hipError_t launch_gen_keys(void *out, uint64_t n, uint32_t layout, uint64_t seed, hipStream_t s);
+
 // Arms the device ring for requests first_q .. first_q + kPersistRing - 1.
 hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first_q, hipStream_t s);
 // The resident kernel (after a one-wave kernel that arms st): wavefronts

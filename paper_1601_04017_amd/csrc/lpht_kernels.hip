@@ -1668,6 +1668,33 @@ __global__ void __launch_bounds__(256, 4) k_persist(const PersistCtl *ctl, const
   if (lane == 0) __hip_atomic_fetch_add(&st->alive, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---------------------------------------------------------------- synthetic keys (autotuning)
+
+// keys[i] = a bijective mix of seed * 2^32 + i (SplitMix64's finaliser for
+// 64-bit keys, MurmurHash3's for 32-bit ones), so keys are distinct for
+// distinct i; the two reserved values are moved to 2 and 3 (a collision of
+// two keys at most, which a timing run does not care about).
+__global__ void k_gen_keys(void *out, u64 n, uint32_t layout, u64 seed) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (layout == 0) {
+      uint32_t x = (uint32_t)(i + seed * 0x9E3779B9u);
+      x ^= x >> 16;
+      x *= 0x85EBCA6Bu;
+      x ^= x >> 13;
+      x *= 0xC2B2AE35u;
+      x ^= x >> 16;
+      ((uint32_t *)out)[i] = x < 2 ? x + 2 : x;
+    } else {
+      u64 x = i + (seed << 32);
+      x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+      x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+      x ^= x >> 31;
+      ((u64 *)out)[i] = x < 2 ? x + 2 : x;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline uint32_t grid_for(u64 work_items, const LaunchCfg &cfg) {
@@ -1793,6 +1820,13 @@ hipError_t launch_set_status(DevStatus *st, uint64_t used, uint64_t live, int cl
 
 hipError_t launch_count_totals(const DevStatus *st, uint64_t *out, hipStream_t s) {
   hipLaunchKernelGGL(k_count_totals, dim3(1), dim3(64), 0, s, st, (u64 *)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_keys(void *out, uint64_t n, uint32_t layout, uint64_t seed, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const u64 blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_gen_keys, dim3((uint32_t)blocks), dim3(256), 0, s, out, (u64)n, layout, (u64)seed);
   return hipGetLastError();
 }
 

@@ -60,8 +60,22 @@ class lpht_tuning(ctypes.Structure):
         ("blocks_per_cu", ctypes.c_uint32),
         ("migrate_block", ctypes.c_uint32),
         ("aggregate", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 3),
+        ("g_find", ctypes.c_uint8 * 4),
+        ("g_modify", ctypes.c_uint8 * 4),
+        ("reserved", ctypes.c_uint32),
     ]
+
+
+class lpht_autotune_report(ctypes.Structure):
+    _fields_ = [
+        ("find_ms", (ctypes.c_double * 5) * 4),
+        ("insert_ms", (ctypes.c_double * 5) * 4),
+        ("block_ms", ctypes.c_double * 3),
+        ("migrate_ms", ctypes.c_double * 4),
+    ]
+
+TUNING_KEYS = ("block_threads", "group_width", "blocks_per_cu", "migrate_block", "aggregate",
+               "g_find", "g_modify")
 
 
 class lpht_stats(ctypes.Structure):
@@ -114,6 +128,8 @@ _SIGS = {
     "lpht_import_cells": (ctypes.c_int, [_VP, _VP, _U32, _VP]),
     "lpht_status": (ctypes.c_int, [_VP, _VP]),
     "lpht_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_tuning)]),
+    "lpht_autotune": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP,
+                                     ctypes.POINTER(lpht_tuning), ctypes.POINTER(lpht_autotune_report)]),
     "lpht_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_tuning)]),
     "lpht_set_timing": (ctypes.c_int, [_VP, ctypes.c_int]),
     "lpht_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_stats)]),
@@ -298,15 +314,21 @@ class Table:
         return load().lpht_status(self._h, _stream_handle(stream))
 
     def set_tuning(self, block_threads=256, group_width=1, blocks_per_cu=8, migrate_block=512,
-                   aggregate=1):
-        t = lpht_tuning(block_threads, group_width, blocks_per_cu, migrate_block, aggregate)
+                   aggregate=1, g_find=(0, 0, 0, 0), g_modify=(0, 0, 0, 0)):
+        """Launch shape; g_find / g_modify: group width by fill quarter (0 = group_width)."""
+        t = _tuning_struct(dict(block_threads=block_threads, group_width=group_width,
+                                blocks_per_cu=blocks_per_cu, migrate_block=migrate_block,
+                                aggregate=aggregate, g_find=g_find, g_modify=g_modify))
         _check(load().lpht_set_tuning(self._h, ctypes.byref(t)), "lpht_set_tuning")
+
+    def apply_tuning(self, tuning: dict):
+        """Sets a tuning dict as returned by autotune() or get_tuning()."""
+        self.set_tuning(**{k: tuning[k] for k in TUNING_KEYS if k in tuning})
 
     def get_tuning(self) -> dict:
         t = lpht_tuning()
         _check(load().lpht_get_tuning(self._h, ctypes.byref(t)), "lpht_get_tuning")
-        return {k: getattr(t, k) for k in ("block_threads", "group_width", "blocks_per_cu",
-                                            "migrate_block", "aggregate")}
+        return _tuning_dict(t)
 
     def set_timing(self, on: bool = True):
         _check(load().lpht_set_timing(self._h, 1 if on else 0), "lpht_set_timing")
@@ -315,6 +337,79 @@ class Table:
         s = lpht_stats()
         _check(load().lpht_get_stats(self._h, ctypes.byref(s)), "lpht_get_stats")
         return {k: getattr(s, k) for k, _ in lpht_stats._fields_}
+
+
+def _tuning_struct(d: dict) -> "lpht_tuning":
+    t = lpht_tuning(d["block_threads"], d["group_width"], d["blocks_per_cu"], d["migrate_block"],
+                    d["aggregate"])
+    for i in range(4):
+        t.g_find[i] = int(d.get("g_find", (0,) * 4)[i])
+        t.g_modify[i] = int(d.get("g_modify", (0,) * 4)[i])
+    return t
+
+
+def _tuning_dict(t: "lpht_tuning") -> dict:
+    d = {k: getattr(t, k) for k in TUNING_KEYS[:5]}
+    d["g_find"] = [int(x) for x in t.g_find]
+    d["g_modify"] = [int(x) for x in t.g_modify]
+    return d
+
+
+def _cache_path() -> str:
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "lpht", "autotune.json")
+
+
+def _device_key() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", p.name)
+    return f"{arch}|hip {torch.version.hip}|cus {p.multi_processor_count}"
+
+
+def autotune(layout: int = KV64, log2_capacity: int = 26, reps: int = 2, cache: bool = True,
+             stream=None):
+    """Runs lpht_autotune (see include/lpht.h) and returns (tuning dict,
+    report dict).  Results are cached per device architecture, HIP version,
+    layout and capacity in ~/.cache/lpht/autotune.json (XDG_CACHE_HOME
+    respected); cache=False measures again and overwrites the entry."""
+    import json
+    import torch
+    torch.cuda.init()
+    key = f"{_device_key()}|layout {layout}|log2c {log2_capacity}"
+    path = _cache_path()
+    db = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+    if cache and key in db:
+        e = db[key]
+        return e["tuning"], e["report"]
+    t = lpht_tuning()
+    r = lpht_autotune_report()
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(load().lpht_autotune(layout, log2_capacity, reps, ctypes.c_void_p(s), ctypes.byref(t),
+                                ctypes.byref(r)), "lpht_autotune")
+    tuning = _tuning_dict(t)
+    report = {"widths": [1, 2, 4, 8, 16], "fills": [0.125, 0.375, 0.625, 0.875],
+              "find_ms": [[round(r.find_ms[q][g], 4) for g in range(5)] for q in range(4)],
+              "insert_ms": [[round(r.insert_ms[q][g], 4) for g in range(5)] for q in range(4)],
+              "blocks": [256, 512, 1024], "block_ms": [round(x, 4) for x in r.block_ms],
+              "migrate_blocks": [256, 512, 1024, 2048],
+              "migrate_ms": [round(x, 4) for x in r.migrate_ms]}
+    db[key] = {"tuning": tuning, "report": report}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + f".{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return tuning, report
 
 
 class Batch:

@@ -67,3 +67,35 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.lpht_insert(None, None, None, 0, None, None) == lpht.ERR_INVALID
     assert lib.lpht_grow(None, 10, None) == lpht.ERR_INVALID
     assert lib.lpht_destroy(None, None) == lpht.OK
+
+
+def _c_sizes(tmp_path, types):
+    # compiles a C program against include/lpht.h and prints sizeof of each type
+    src = tmp_path / "sizes.c"
+    body = "".join(f'  printf("%zu\\n", sizeof({t}));\n' for t in types)
+    src.write_text('#include <stdio.h>\n#include "lpht.h"\nint main(void) {\n' + body + "  return 0;\n}\n")
+    exe = tmp_path / "sizes"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return [int(x) for x in out]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    pairs = [("lpht_config", lpht.lpht_config), ("lpht_tuning", lpht.lpht_tuning),
+             ("lpht_stats", lpht.lpht_stats), ("lpht_autotune_report", lpht.lpht_autotune_report),
+             ("lpht_batch_op", lpht.lpht_batch_op), ("lpht_server_config", lpht.lpht_server_config),
+             ("lpht_request", lpht.lpht_request), ("lpht_completion", lpht.lpht_completion),
+             ("lpht_server_stats", lpht.lpht_server_stats)]
+    sizes = _c_sizes(tmp_path, [c for c, _ in pairs])
+    for (cname, py), n in zip(pairs, sizes):
+        assert ctypes.sizeof(py) == n, cname
+
+
+def test_autotune_arguments_rejected_on_host(lib):
+    t = lpht.lpht_tuning()
+    assert lib.lpht_autotune(7, 20, 1, None, ctypes.byref(t), None) == lpht.ERR_INVALID
+    assert lib.lpht_autotune(lpht.KV64, 10, 1, None, ctypes.byref(t), None) == lpht.ERR_INVALID
+    assert lib.lpht_autotune(lpht.KV64, 20, 0, None, ctypes.byref(t), None) == lpht.ERR_INVALID
+    assert lib.lpht_autotune(lpht.KV64, 20, 1, None, None, None) == lpht.ERR_INVALID

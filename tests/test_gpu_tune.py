@@ -1,0 +1,88 @@
+"""The autotuner and fill-dependent group widths: the tuner returns a valid
+shape with finite timings for every candidate, and tables whose group width
+changes with their fill (across all four quarters, inserts, finds and erases)
+give exactly the oracle's results."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_04017_amd import inputs
+from tests import helpers as H
+from tests.gpu_util import cells_host, keys_dtype, make_table, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = {1, 2, 4, 8, 16}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def _keys(layout, n, seed, absent=False):
+    if layout == oracle.PACKED32:
+        return inputs.distinct_keys_u32(n, seed, absent=absent)
+    return inputs.distinct_keys_u64(n, seed, absent=absent)
+
+
+@pytest.mark.parametrize("layout", [oracle.KV64, oracle.PACKED32])
+def test_autotune_returns_valid_shape(layout, tmp_path, monkeypatch):
+    from paper_1601_04017_amd import lpht
+    monkeypatch.setenv("XDG_CACHE_HOME", str(tmp_path))
+    tuning, report = lpht.autotune(layout, 18, reps=1, cache=False)
+    assert tuning["block_threads"] in (256, 512, 1024)
+    assert tuning["migrate_block"] in (256, 512, 1024, 2048)
+    assert tuning["group_width"] in WIDTHS
+    assert all(g in WIDTHS for g in tuning["g_find"] + tuning["g_modify"])
+    for q in range(4):
+        assert all(0 < x < 1e4 for x in report["find_ms"][q] + report["insert_ms"][q])
+        # the choice is the fastest candidate
+        assert tuning["g_find"][q] == report["widths"][int(np.argmin(report["find_ms"][q]))]
+        assert tuning["g_modify"][q] == report["widths"][int(np.argmin(report["insert_ms"][q]))]
+    assert all(0 < x < 1e4 for x in report["block_ms"] + report["migrate_ms"])
+    # the cache answers the second call with the same entry
+    again, _ = lpht.autotune(layout, 18, reps=1, cache=True)
+    assert again == tuning
+    t = make_table(layout, 14)
+    t.apply_tuning(tuning)
+    assert t.get_tuning() == tuning
+
+
+@pytest.mark.parametrize("layout", [oracle.KV64, oracle.PACKED32])
+def test_fill_dependent_widths_match_oracle(layout):
+    log2c = 14
+    c = 1 << log2c
+    t = make_table(layout, log2c)  # bounded: fills to 15/16
+    t.set_tuning(g_find=(1, 4, 8, 16), g_modify=(16, 2, 1, 8), group_width=4)
+    orc = oracle.OracleTable(layout, log2c)
+    keys = _keys(layout, c, 11)
+    absent = _keys(layout, 3000, 11, absent=True)
+    vals = (np.arange(c) * 3 + 1).astype(keys_dtype(layout))
+    done = 0
+    for step, frac in enumerate((0.2, 0.3, 0.45, 0.6, 0.74, 0.8, 0.9, 0.94)):
+        end = int(frac * c)
+        kk, vv = keys[done:end], vals[done:end]
+        gf = t.insert(to_dev(kk), to_dev(vv))
+        assert np.array_equal(to_host(gf), orc.insert(kk, vv))
+        done = end
+        fk = np.concatenate([keys[: done : 5], absent])
+        gv, gfound = t.find(to_dev(fk))
+        ov, ofound = orc.find(fk)
+        assert np.array_equal(to_host(gfound), ofound)
+        assert np.array_equal(to_host(gv, keys_dtype(layout)), ov)
+        if step % 3 == 2:
+            ek = keys[step: done: 17]
+            assert np.array_equal(to_host(t.erase(to_dev(ek))), orc.erase(ek))
+        assert t.count() == orc.counts()
+    H.assert_same_table_modulo_run_order(cells_host(t), orc.cells(), layout)
+
+
+def test_invalid_fill_widths_rejected():
+    from paper_1601_04017_amd import lpht
+    t = make_table(oracle.KV64, 12)
+    with pytest.raises(lpht.LphtError):
+        t.set_tuning(g_find=(1, 3, 0, 0))
+    with pytest.raises(lpht.LphtError):
+        t.set_tuning(g_modify=(0, 0, 0, 32))
