@@ -32,8 +32,19 @@ LINE = 128
 CELLS_PER_LINE = 8  # 16-byte cells
 
 
+TUNING = None  # the autotuner's launch shape, applied to every measured table
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def new_table(**kw):
+    from paper_1601_04017_amd import lpht
+    t = lpht.Table(**kw)
+    if TUNING is not None:
+        t.apply_tuning(TUNING)
+    return t
 
 
 def knuth(alpha):
@@ -245,6 +256,8 @@ def _suite_packed32(dev, up, stream, reps):
     fk, _ = inputs.shuffled_mix(present, absent, 103)
     dk, dv, dfk = up(k), up(np.arange(n, dtype=np.uint32)), up(fk)
     t = lpht.Table(layout=lpht.PACKED32, log2_capacity=21)
+    if TUNING is not None:
+        t.apply_tuning(lpht.autotune(lpht.PACKED32, 21, reps=2)[0])
     res = []
     for r in range(reps + 1):
         t.clear()
@@ -267,7 +280,7 @@ def _suite_fill_sweep(dev, up, stream, reps, dkeys, dvals):
     log("suite: fill sweep")
     sweep = {}
     dmiss = up(inputs.distinct_keys_u64(10 ** 8, 201, absent=True))
-    t = lpht.Table(layout=lpht.KV64, log2_capacity=28)
+    t = new_table(layout=lpht.KV64, log2_capacity=28)
     outv = torch.empty(10 ** 8, dtype=torch.int64, device=dev)
     outf = torch.empty(10 ** 8, dtype=torch.uint8, device=dev)
     for nn in (67_108_864, 10 ** 8, 134_217_728, 201_326_592):
@@ -302,7 +315,7 @@ def _suite_growing(stream, reps, dkeys, dvals):
     b = 1 << 20
     res = []
     for r in range(reps + 1):
-        t = lpht.Table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+        t = new_table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
         t.set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -335,7 +348,7 @@ def _suite_zipf(up, stream, reps):
     for sx in (0.5, 1.0, 1.25, 1.5):
         log(f"suite: zipf s={sx}")
         z = up(inputs.zipf_keys_u64(N_OPS, ZIPF_N, sx, seed=400 + int(sx * 4)))
-        t = lpht.Table(layout=lpht.KV64, log2_capacity=28)
+        t = new_table(layout=lpht.KV64, log2_capacity=28)
         res = []
         for r in range(reps + 1):
             t.clear()
@@ -346,7 +359,7 @@ def _suite_zipf(up, stream, reps):
         t.close()
         gres = []
         for r in range(2):
-            g = lpht.Table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+            g = new_table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
             g.set_timing(True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -379,6 +392,8 @@ def main():
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads")
     ap.add_argument("--parts", default=",".join(SUITE_PARTS), help="suite parts to run")
     ap.add_argument("--suite-only", action="store_true", help="skip the headline step")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default launch shape instead of the autotuner's")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (tables shard by hash "
@@ -394,8 +409,19 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    global TUNING
+    tune_info = None
+    if not args.no_autotune:
+        # launch shape for 16-byte cells, tuned on 2^26-cell scratch tables
+        # (HBM-resident, unlike smaller ones), outside every timed region
+        log("autotune")
+        t0 = time.perf_counter()
+        TUNING, _ = lpht.autotune(lpht.KV64, 26, reps=2)
+        tune_info = {"shape": TUNING, "scratch_log2_capacity": 26,
+                     "seconds": round(time.perf_counter() - t0, 2)}
     if args.suite_only:
-        print(json.dumps({"suite": run_suite(dev, parts=tuple(args.parts.split(",")))}), flush=True)
+        print(json.dumps({"tuning": tune_info,
+                          "suite": run_suite(dev, parts=tuple(args.parts.split(",")))}), flush=True)
         return
 
     log("generating inputs")
@@ -415,8 +441,8 @@ def main():
     d_flags = torch.empty(N_OPS, dtype=torch.uint8, device=dev)
     d_found = torch.empty(N_OPS, dtype=torch.uint8, device=dev)
 
-    t1 = lpht.Table(layout=lpht.KV64, log2_capacity=LOG2C)
-    t2 = lpht.Table(layout=lpht.KV64, log2_capacity=LOG2C)
+    t1 = new_table(layout=lpht.KV64, log2_capacity=LOG2C)
+    t2 = new_table(layout=lpht.KV64, log2_capacity=LOG2C)
     if args.group_width or args.aggregate is not None:
         tun = t1.get_tuning()
         if args.group_width:
@@ -485,14 +511,20 @@ def main():
         "find_miss": bpo["find_miss"] * N_OPS / (ph_ms["find_miss"] / 1e3) / 1e9,
     }
     dominant = max(("insert", "find_hit", "find_miss"), key=lambda p: ph_ms[p])
+    # the group width each phase ran with (fill quarter of the table after it)
+    tun = t1.get_tuning()
+    q = min(3, int(4 * alpha))
+    width = {"insert": tun["g_modify"][q] or tun["group_width"],
+             "find_hit": tun["g_find"][q] or tun["group_width"],
+             "find_miss": tun["g_find"][q] or tun["group_width"]}
     roofline = {
         "bound": "hbm",
-        "kernel": f"k_bulk<KV64,{dominant},G={t1.get_tuning()['group_width']}>",
+        "kernel": f"k_bulk<KV64,{dominant},G={width[dominant]}>",
         "achieved": round(ach[dominant], 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(ach[dominant] / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(dominant, t1.get_tuning()["group_width"]),
+        "traffic": measured_traffic(dominant, width[dominant]),
         "algorithmic_bytes_per_launch": round(bpo[dominant] * N_OPS),
     }
 
@@ -516,9 +548,11 @@ def main():
             "ops": N_OPS,
             "fill": round(alpha, 4),
             "zipf_s": ZIPF_S,
-            "group_width": t1.get_tuning()["group_width"],
+            "group_width": width,
+            "block_threads": tun["block_threads"],
             "aggregate": t2.get_tuning()["aggregate"],
         },
+        "tuning": tune_info,
         "phases_ms": {k: round(v, 3) for k, v in ph_ms.items()},
         "phase_mops": {p: round(N_OPS / (ph_ms[p] / 1e3) / 1e6, 1)
                        for p in ("insert", "find_hit", "find_miss", "upsert_zipf")},

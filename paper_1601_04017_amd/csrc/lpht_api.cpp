@@ -121,15 +121,21 @@ bool tuning_ok(const lpht_tuning *u) {
   return true;
 }
 
-// The group width for an operation on `t`: by the fill quarter of the host's
-// bound on `used` (after the call's insertions), else the table's default.
-uint32_t pick_group_width(const lpht_table *t, OpKind op) {
+// The group width for an operation on `t` when `used` is the host's bound on
+// the table's non-empty cells after it: by fill quarter, else the default.
+uint32_t pick_group_width(const lpht_table *t, OpKind op, uint64_t used) {
   const uint64_t c = 1ull << t->log2c;
-  const uint64_t used = std::min<uint64_t>(c, t->known_used + t->pending);
+  used = std::min<uint64_t>(c, used);
   const uint32_t qi = (uint32_t)std::min<uint64_t>(3, (unsigned __int128)used * 4 / c);
   const uint8_t g = op == OP_FIND ? t->tuning.g_find[qi] : t->tuning.g_modify[qi];
   return g ? g : t->tuning.group_width;
 }
+
+// Inserting calls with fill-dependent widths are launched in pieces that end
+// at the fill-quarter boundaries the call may cross (pieces of at least this
+// many operations), each with its own quarter's width.  Consecutive pieces
+// are the call's operations in order, so the results are those of one launch.
+constexpr uint64_t kMinPiece = 1ull << 16;
 
 bool within_fill(const lpht_table *t, uint64_t x, uint64_t c) {
   return (unsigned __int128)x * t->cfg.max_fill_den <= (unsigned __int128)c * t->cfg.max_fill_num;
@@ -325,9 +331,37 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
                  t->known_used + t->pending <= (1ull << t->log2c))
                     ? 1u
                     : 0u;
-  LaunchCfg cfg = t->launch;
-  cfg.group_width = pick_group_width(t, op);
-  return from_hip(launch_bulk(op, a, cfg, s));
+  const bool inserting = op == OP_INSERT || op == OP_UPSERT;
+  const uint64_t c = 1ull << t->log2c;
+  // bound on used before this call (the growth rule already counted it)
+  const uint64_t used0 = t->known_used + t->pending - (inserting ? n : 0);
+  bool by_fill = false;
+  for (uint8_t g : t->tuning.g_modify) by_fill |= g != 0;
+  const uint32_t kb = t->cfg.layout == LPHT_PACKED32 ? 4 : 8;
+  uint64_t done = 0;
+  while (done < n) {
+    uint64_t len = n - done;
+    if (inserting && by_fill) {
+      for (uint64_t q = 1; q < 4; ++q) {
+        const uint64_t b = q * c / 4;
+        if (used0 + done < b && b < used0 + done + len && b - (used0 + done) >= kMinPiece &&
+            used0 + done + len - b >= kMinPiece)
+          len = b - (used0 + done);
+      }
+    }
+    BulkArgs p = a;
+    p.keys = (const unsigned char *)keys + done * kb;
+    p.vals = vals ? (const unsigned char *)vals + done * kb : nullptr;
+    p.vals_out = vals_out ? (unsigned char *)vals_out + done * kb : nullptr;
+    p.flags = flags ? flags + done : nullptr;
+    p.n = len;
+    LaunchCfg cfg = t->launch;
+    cfg.group_width = pick_group_width(t, op, inserting ? used0 + done + len : t->known_used + t->pending);
+    const hipError_t e = launch_bulk(op, p, cfg, s);
+    if (e != hipSuccess) return from_hip(e);
+    done += len;
+  }
+  return LPHT_OK;
 }
 
 }  // namespace host

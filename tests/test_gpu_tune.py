@@ -86,3 +86,50 @@ def test_invalid_fill_widths_rejected():
         t.set_tuning(g_find=(1, 3, 0, 0))
     with pytest.raises(lpht.LphtError):
         t.set_tuning(g_modify=(0, 0, 0, 32))
+
+
+@pytest.mark.parametrize("layout", [oracle.KV64, oracle.PACKED32])
+def test_insert_split_at_fill_quarters_matches_oracle(layout):
+    # one call from empty to 0.8 fill crosses the 1/4 and 1/2 boundaries with
+    # pieces of >= 2^16 operations, each launched with its quarter's width
+    log2c = 18
+    c = 1 << log2c
+    n = int(0.8 * c)
+    keys = _keys(layout, n, 31)
+    dup = np.concatenate([keys, keys[:: 7]])  # duplicates: exactly one insert wins
+    perm = inputs.permutation(dup.size, 32)
+    dup = dup[perm]
+    vals = (np.arange(dup.size) + 5).astype(keys_dtype(layout))
+    t = make_table(layout, log2c)
+    t.set_tuning(g_find=(2, 4, 8, 16), g_modify=(1, 4, 16, 8))
+    orc = oracle.OracleTable(layout, log2c)
+    gf = to_host(t.insert(to_dev(dup), to_dev(vals)))
+    of = orc.insert(dup, vals)
+    assert np.array_equal(H.canonical_flags(dup, gf), of)
+    assert t.count() == orc.counts()
+    g_cells = cells_host(t)
+    # the stored value of each key is the one whose insert won
+    won = {int(k): int(v) for k, v, f in zip(dup, vals, gf) if f == 1}
+    live = H.live_dict(g_cells, layout)
+    assert live == won
+    # which of two equal inserts wins is unspecified: compare everything but
+    # the values with the oracle
+    o_cells = orc.cells()
+    assert np.array_equal(H.occupancy(g_cells, layout), H.occupancy(o_cells, layout))
+    assert H.runs_key_sets(g_cells, layout) == H.runs_key_sets(o_cells, layout)
+
+
+def test_upsert_split_with_growth_matches_oracle():
+    # Zipf insert-or-increment into a growing table: the growth rule sees the
+    # whole call, the launch is split by fill quarter
+    layout = oracle.KV64
+    t = make_table(layout, 12, auto_grow=True)
+    t.set_tuning(g_modify=(2, 8, 1, 4))
+    orc = oracle.OracleTable(layout, 12, auto_grow=True)
+    for rep in range(3):
+        z = inputs.zipf_keys_u64(300_000, 400_000, 0.8, seed=50 + rep)
+        gf = to_host(t.insert_or_update(to_dev(z), None, op=oracle.ADD))
+        of = orc.insert_or_update(z, None, oracle.ADD)
+        assert np.array_equal(H.canonical_flags(z, gf), of)
+        assert t.count() == orc.counts() and t.capacity == orc.capacity
+    H.assert_same_table_modulo_run_order(cells_host(t), orc.cells(), layout)
