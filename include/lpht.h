@@ -314,8 +314,9 @@ int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void 
  *                       128-operation rounds phase by phase, copy values and
  *                       flags back into the request's host arrays, and
  *                       publish the completion in host memory.  No HIP call
- *                       is made per request.  The kernel exits when idle and
- *                       is relaunched on new work; for table growth it is
+ *                       is made per request.  The kernel's launch is captured
+ *                       once as a HIP graph and replayed: it exits when idle
+ *                       and is relaunched on new work; for table growth it is
  *                       stopped, the table migrates, and it is relaunched.
  *                       Request arrays must be pinned host memory (or device
  *                       memory); submit rejects others with

@@ -99,7 +99,8 @@ constexpr uint32_t kPersistRing = 256;
 struct alignas(64) PersistCtl {   // host memory, written by the host
   unsigned long long posted;      // requests posted so far
   unsigned long long stop;        // 1: every wave exits after its current round
-  unsigned long long pad[6];
+  unsigned long long base;        // the oldest request not complete, set before each launch
+  unsigned long long pad[5];
 };
 
 // A request's phases in the resident kernel: copy its keys and kinds from the
@@ -148,7 +149,8 @@ struct alignas(128) PersistState { // device memory
   unsigned long long alive;       // serving wavefronts still running
   unsigned long long published;   // ctl->posted as last copied by the poller
   unsigned long long completed;   // requests completed
-  unsigned long long pad[12];
+  unsigned long long base;        // this launch's first request (ctl->base, copied at arming)
+  unsigned long long pad[11];
   PersistGroupCtl group[kPersistGroups];
 };
 
@@ -157,14 +159,16 @@ hipError_t launch_gen_keys(void *out, uint64_t n, uint32_t layout, uint64_t seed
 
 // Arms the device ring for requests first_q .. first_q + kPersistRing - 1.
 hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first_q, hipStream_t s);
-// The resident kernel (after a one-wave kernel that arms st): wavefronts
-// serve requests from `base_q` on until ctl->stop is set, or until one of them
-// has found no work for `idle_ticks` ticks of the device's constant-rate clock
-// while every published request has completed.  `ring` is the
-// host ring, `dring` its device copy.  `grid` must be a positive multiple of
-// kPersistGroups.
+// The resident kernel, after a one-wave kernel that arms st (stop flags
+// cleared, serving wavefronts counted, ctl->base copied): wavefronts serve
+// requests from ctl->base on until ctl->stop is set, or until one of them has
+// found no work for `idle_ticks` ticks of the device's constant-rate clock
+// while every published request has completed.  `ring` is the host ring,
+// `dring` its device copy.  `grid` must be a positive multiple of
+// kPersistGroups.  The two launches take no per-launch argument, so the pair
+// can be captured once in a graph and replayed.
 hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
-                          PersistDone *done, PersistDev *dev, PersistState *st, uint64_t base_q,
-                          uint64_t idle_ticks, uint32_t grid, hipStream_t s);
+                          PersistDone *done, PersistDev *dev, PersistState *st, uint64_t idle_ticks,
+                          uint32_t grid, hipStream_t s);
 
 }  // namespace lpht

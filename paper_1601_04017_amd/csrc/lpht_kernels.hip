@@ -1238,11 +1238,14 @@ __global__ void k_persist_init(PersistDev *dev, PersistState *st, u64 first_q) {
   }
 }
 
-// Before each launch of the resident kernel: clear the stop mirrors and count
-// the serving wavefronts.
-__global__ void k_persist_arm(PersistState *st, u64 serving) {
+// Before each launch of the resident kernel: clear the stop mirrors, count
+// the serving wavefronts and take the first request to serve from the host.
+__global__ void k_persist_arm(PersistState *st, const PersistCtl *ctl, u64 serving) {
   if (threadIdx.x < kPersistGroups) st->group[threadIdx.x].stop = 0;
-  if (threadIdx.x == 0) st->alive = serving;
+  if (threadIdx.x == 0) {
+    st->alive = serving;
+    st->base = *(const volatile u64 *)&ctl->base;
+  }
 }
 
 __device__ void persist_poller(const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
@@ -1556,8 +1559,7 @@ __device__ bool persist_serve(const uint32_t (*T)[256], uint8_t *wflag, u64 *wou
 template <int LAYOUT>
 __global__ void __launch_bounds__(256, 4) k_persist(const PersistCtl *ctl, const PersistReq *ring,
                                                  PersistReq *dring, PersistDone *done_ring,
-                                                 PersistDev *dev, PersistState *st, u64 base_q,
-                                                 u64 idle_ticks) {
+                                                 PersistDev *dev, PersistState *st, u64 idle_ticks) {
   __shared__ uint32_t T[8][256];
   __shared__ u64 s_req[4][kPersistWords];  // per wave: the request it works on
   __shared__ u64 s_q[4];
@@ -1584,7 +1586,11 @@ __global__ void __launch_bounds__(256, 4) k_persist(const PersistCtl *ctl, const
   const uint32_t spread = (uint32_t)((gw * 0x9E3779B97F4A7C15ull) >> 58);
   if (lane == 0) s_q[wave] = ~0ull;
   wave_sync();
-  // the group's requests: q = g, g + G, g + 2G, ... (G = kPersistGroups)
+  // the group's requests: q = g, g + G, g + 2G, ... (G = kPersistGroups),
+  // from the launch's first request on
+  u64 base_q = 0;
+  if (lane == 0) base_q = dev_relaxed(&st->base);
+  base_q = uni(base_q);
   u64 lo = base_q + (g + kPersistGroups - (uint32_t)(base_q % kPersistGroups)) % kPersistGroups;
   u64 seen = 0;        // the largest posted count acquired so far
   bool rescan = true;  // something may be claimable
@@ -1836,19 +1842,19 @@ hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first
 }
 
 hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
-                          PersistDone *done, PersistDev *dev, PersistState *st, uint64_t base_q,
-                          uint64_t idle_ticks, uint32_t grid, hipStream_t s) {
+                          PersistDone *done, PersistDev *dev, PersistState *st, uint64_t idle_ticks,
+                          uint32_t grid, hipStream_t s) {
   if (grid < kPersistGroups || grid % kPersistGroups) return hipErrorInvalidValue;
   const size_t lds = 4 * (size_t)ROUND * 18;
-  hipLaunchKernelGGL(k_persist_arm, dim3(1), dim3(64), 0, s, st, (u64)grid * 4 - 1);
+  hipLaunchKernelGGL(k_persist_arm, dim3(1), dim3(64), 0, s, st, ctl, (u64)grid * 4 - 1);
   hipError_t rc = hipGetLastError();
   if (rc != hipSuccess) return rc;
   if (layout == 0)
     hipLaunchKernelGGL(k_persist<0>, dim3(grid), dim3(256), lds, s, ctl, ring, dring, done, dev, st,
-                       (u64)base_q, (u64)idle_ticks);
+                       (u64)idle_ticks);
   else
     hipLaunchKernelGGL(k_persist<1>, dim3(grid), dim3(256), lds, s, ctl, ring, dring, done, dev, st,
-                       (u64)base_q, (u64)idle_ticks);
+                       (u64)idle_ticks);
   return hipGetLastError();
 }
 

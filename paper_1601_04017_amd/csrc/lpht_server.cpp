@@ -113,6 +113,8 @@ struct lpht_server {
   uint64_t oldest_q = 0;           // oldest request not yet retired
   bool running = false;
   hipEvent_t persist_ev = nullptr;
+  hipGraph_t persist_graph = nullptr;     // {arm, resident kernel}, captured once
+  hipGraphExec_t persist_exec = nullptr;
   std::vector<Req *> grow_wait;    // admitted, waiting for their table to grow
   uint32_t persist_grid = 0;
   unsigned char *arena = nullptr;  // resident mode: device staging of requests in flight
@@ -355,11 +357,25 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
 // relaunches it).
 constexpr double kIdleExitMs = 20.0;
 
+// Captures the resident kernel's launch (arming kernel + resident kernel,
+// which read the first request to serve from ctl->base) into a graph.
+hipError_t persist_capture(lpht_server *S) {
+  hipStream_t s = S->streams[0];
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const hipError_t le = launch_persist(S->cfg.layout, S->pctl, S->pring, S->pdring, S->pdone, S->pdev,
+                                       S->pst, S->idle_ticks, S->persist_grid, s);
+  e = hipStreamEndCapture(s, &S->persist_graph);
+  if (le != hipSuccess) return le;
+  if (e != hipSuccess) return e;
+  return hipGraphInstantiate(&S->persist_exec, S->persist_graph, nullptr, nullptr, 0);
+}
+
 void persist_launch(lpht_server *S) {
   hipStream_t s = S->streams[0];
+  __atomic_store_n(&S->pctl->base, S->oldest_q, __ATOMIC_RELAXED);
   __atomic_store_n(&S->pctl->stop, 0ull, __ATOMIC_RELEASE);
-  if (launch_persist(S->cfg.layout, S->pctl, S->pring, S->pdring, S->pdone, S->pdev, S->pst,
-                     S->oldest_q, S->idle_ticks, S->persist_grid, s) == hipSuccess) {
+  if (hipGraphLaunch(S->persist_exec, s) == hipSuccess) {
     (void)hipEventRecord(S->persist_ev, s);
     S->running = true;
     S->persist_launches++;
@@ -603,6 +619,8 @@ void destroy_all(lpht_server *S) {
   if (S->pdev) (void)hipFree(S->pdev);
   if (S->pst) (void)hipFree(S->pst);
   if (S->persist_ev) (void)hipEventDestroy(S->persist_ev);
+  if (S->persist_exec) (void)hipGraphExecDestroy(S->persist_exec);
+  if (S->persist_graph) (void)hipGraphDestroy(S->persist_graph);
   for (auto &kv : S->reqs) delete kv.second;
   delete S;
 }
@@ -715,7 +733,7 @@ int lpht_server_create(const lpht_server_config *cfg, lpht_server **out) {
       khz = 100000;
     S->idle_ticks = (uint64_t)(kIdleExitMs * khz);
     if (launch_persist_init(S->pdev, S->pst, 0, S->streams[0]) != hipSuccess ||
-        hipStreamSynchronize(S->streams[0]) != hipSuccess) {
+        hipStreamSynchronize(S->streams[0]) != hipSuccess || persist_capture(S) != hipSuccess) {
       destroy_all(S);
       return LPHT_ERR_DEVICE;
     }
