@@ -73,10 +73,36 @@ def algorithmic_bytes_per_op(alpha):
 OP_CODE = {"insert": 1, "find_hit": 0, "find_miss": 0}
 
 
-def measured_traffic(phase, group_width):
-    """HBM bytes per launch of the phase's kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the
-    summary is missing or was taken with a different kernel source."""
+def phase_widths(tun, op, used0, n, c):
+    """The group width of each launch of a call, as the library picks them:
+    by the fill quarter (0, c/4], ..., (3c/4, c] of the bound on `used` after
+    the launch; inserting calls split where a quarter boundary changes it."""
+    key = "g_modify" if op == "insert" else "g_find"
+
+    def pick(used):
+        q = 0 if used == 0 else min(3, (min(used, c) - 1) * 4 // c)
+        return tun[key][q] or tun["group_width"]
+
+    if op != "insert":
+        return [pick(used0)]
+    widths, done = [], 0
+    while done < n:
+        ln = n - done
+        if any(tun[key]):
+            for q in (1, 2, 3):
+                b = q * c // 4
+                if (used0 + done < b < used0 + done + ln and b - (used0 + done) >= 1 << 16
+                        and used0 + done + ln - b >= 1 << 16 and pick(b) != pick(b + 1)):
+                    ln = b - (used0 + done)
+        widths.append(pick(used0 + done + ln))
+        done += ln
+    return widths
+
+
+def measured_traffic(phase, widths):
+    """HBM bytes of the phase's launches (one per width) from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated), or None
+    when the summary is missing or was taken with a different kernel source."""
     from paper_1601_04017_amd import profsum
 
     path = os.path.join(ROOT, "profiles", "k_bulk_kv64_headline_step.traffic.json")
@@ -85,11 +111,13 @@ def measured_traffic(phase, group_width):
     rec = json.load(open(path))
     if rec.get("kernel_source_sha") != profsum.kernel_source_sha():
         return None
-    name = f"k_bulk<1, {OP_CODE[phase]}, 0, {group_width}>"
-    k = rec.get("per_kernel", {}).get(name)
-    if k is None:
-        return None
-    return round(k["read_bytes"] + k["write_bytes"])
+    total = 0
+    for g in widths:
+        k = rec.get("per_kernel", {}).get(f"k_bulk<1, {OP_CODE[phase]}, 0, {g}>")
+        if k is None:
+            return None
+        total += k["read_bytes"] + k["write_bytes"]
+    return round(total)
 
 
 def cpu_baseline(keys, fkeys_hit, fkeys_miss, zipf, budget_s=25.0):
@@ -511,21 +539,23 @@ def main():
         "find_miss": bpo["find_miss"] * N_OPS / (ph_ms["find_miss"] / 1e3) / 1e9,
     }
     dominant = max(("insert", "find_hit", "find_miss"), key=lambda p: ph_ms[p])
-    # the group width each phase ran with (fill quarter of the table after it)
+    # the group widths each phase's launches ran with
     tun = t1.get_tuning()
-    q = min(3, int(4 * alpha))
-    width = {"insert": tun["g_modify"][q] or tun["group_width"],
-             "find_hit": tun["g_find"][q] or tun["group_width"],
-             "find_miss": tun["g_find"][q] or tun["group_width"]}
+    width = {"insert": phase_widths(tun, "insert", 0, N_OPS, 1 << LOG2C),
+             "find_hit": phase_widths(tun, "find", N_OPS, 0, 1 << LOG2C),
+             "find_miss": phase_widths(tun, "find", N_OPS, 0, 1 << LOG2C)}
     roofline = {
         "bound": "hbm",
-        "kernel": f"k_bulk<KV64,{dominant},G={width[dominant]}>",
+        "kernel": " + ".join(f"k_bulk<KV64,{dominant},G={g}>" for g in width[dominant]),
+        "launches": len(width[dominant]),
         "achieved": round(ach[dominant], 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(ach[dominant] / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic(dominant, width[dominant]),
-        "algorithmic_bytes_per_launch": round(bpo[dominant] * N_OPS),
+        # the phase's launches together (one per group width), timed with
+        # HIP events on the stream they run on
+        "algorithmic_bytes_per_phase": round(bpo[dominant] * N_OPS),
     }
 
     out = {

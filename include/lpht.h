@@ -109,10 +109,13 @@ typedef struct lpht_tuning {
   uint32_t blocks_per_cu; /* resident workgroups per compute unit the grid is sized for, 1..32 */
   uint32_t migrate_block; /* old cells per migration workgroup, power of two 256..8192 */
   uint32_t aggregate;     /* 1 (default): combine equal keys in LDS before LPHT_ADD upserts */
-  /* Group width by fill quarter, used / capacity in [0, 1/4), [1/4, 1/2),
-   * [1/2, 3/4), [3/4, 1] (the host's bound on `used` after the call): for
-   * finds, and for the operations that modify the table.  0 = group_width.
-   * Long probe runs at high fill are scanned faster by wider groups. */
+  /* Group width by fill quarter, used / capacity in [0, 1/4], (1/4, 1/2],
+   * (1/2, 3/4], (3/4, 1] (the host's bound on `used` after the operations):
+   * for finds, and for the operations that modify the table.  0 =
+   * group_width.  Long probe runs at high fill are scanned faster by wider
+   * groups.  An inserting call whose operations cross a quarter boundary
+   * where the width changes is launched in pieces split there (pieces of at
+   * least 2^16 operations). */
   uint8_t g_find[4];
   uint8_t g_modify[4];
   uint32_t reserved;      /* must be 0 */
@@ -216,8 +219,9 @@ int lpht_get_tuning(const lpht_table *t, lpht_tuning *tuning);
  *   - per fill quarter (fill 1/8, 3/8, 5/8, 7/8): the group width for finds
  *     (half present, half absent keys, a quarter of the capacity) and for
  *     inserts (the last capacity/16 keys before that fill), each over
- *     {1, 2, 4, 8, 16} -> g_find, g_modify; group_width = the fill-3/8 finds'
- *     choice;
+ *     {1, 2, 4, 8, 16} -> g_find, g_modify; a quarter keeps the fill-3/8
+ *     choice unless another width is more than 3 % faster; group_width = the
+ *     fill-3/8 finds' choice;
  *   - block_threads over {256, 512, 1024} at fill 3/8 with those widths;
  *   - migrate_block over {256, 512, 1024, 2048}: doubling a table at fill 7/16
  *     (lpht_grow);

@@ -122,18 +122,19 @@ bool tuning_ok(const lpht_tuning *u) {
 }
 
 // The group width for an operation on `t` when `used` is the host's bound on
-// the table's non-empty cells after it: by fill quarter, else the default.
+// the table's non-empty cells after it: by the fill quarter (0, c/4],
+// (c/4, c/2], (c/2, 3c/4], (3c/4, c] that holds `used`, else the default.
 uint32_t pick_group_width(const lpht_table *t, OpKind op, uint64_t used) {
   const uint64_t c = 1ull << t->log2c;
   used = std::min<uint64_t>(c, used);
-  const uint32_t qi = (uint32_t)std::min<uint64_t>(3, (unsigned __int128)used * 4 / c);
+  const uint32_t qi = used == 0 ? 0 : (uint32_t)std::min<uint64_t>(3, (unsigned __int128)(used - 1) * 4 / c);
   const uint8_t g = op == OP_FIND ? t->tuning.g_find[qi] : t->tuning.g_modify[qi];
   return g ? g : t->tuning.group_width;
 }
 
 // Inserting calls with fill-dependent widths are launched in pieces that end
-// at the fill-quarter boundaries the call may cross (pieces of at least this
-// many operations), each with its own quarter's width.  Consecutive pieces
+// at the fill-quarter boundaries the call may cross where the width changes
+// (pieces of at least this many operations), each with its quarter's width.  Consecutive pieces
 // are the call's operations in order, so the results are those of one launch.
 constexpr uint64_t kMinPiece = 1ull << 16;
 
@@ -345,7 +346,8 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
       for (uint64_t q = 1; q < 4; ++q) {
         const uint64_t b = q * c / 4;
         if (used0 + done < b && b < used0 + done + len && b - (used0 + done) >= kMinPiece &&
-            used0 + done + len - b >= kMinPiece)
+            used0 + done + len - b >= kMinPiece &&
+            pick_group_width(t, op, b) != pick_group_width(t, op, b + 1))
           len = b - (used0 + done);
       }
     }

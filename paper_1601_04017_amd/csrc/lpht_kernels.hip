@@ -33,6 +33,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <type_traits>
 #include <stdint.h>
@@ -977,164 +978,218 @@ __global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, u
   flush_counts(st, moved, moved, 0, s_acc, &s_err);
 }
 
-// LDS-staged block migration with owner writes (Sec. 5.3.1).  Workgroup w
-// owns old block [d, d+B) and writes new cells [g*d, g*(d+B)) exactly once,
-// empty cells included, so the new table needs no separate initialisation.
-// By Lemma 1 only clusters that overlap the block send elements into that
-// range: the one that may start before d (up to MIG_HALO cells back) and the
-// ones starting inside the block (the last may run up to MIG_HALO cells past
-// it).  The workgroup stages old cells [d - H, d + B + H) in LDS, re-inserts
-// every overlapping cluster in old-array order into an LDS image of the new
-// range [g*a0, g*(b_last + 1)), and streams the owned part of the image out.
+// LDS-staged block migration with owner writes (Sec. 5.3.1), one wavefront
+// per block.  Wavefront w owns old block [d, d+B) and writes new cells
+// [g*d, g*(d+B)) exactly once, empty cells included, so the new table needs no
+// separate initialisation.  By Lemma 1 only clusters that overlap the block
+// send elements into that range: the one that may start before d (up to
+// MIG_HALO cells back) and the ones starting inside the block (the last may
+// run up to MIG_HALO cells past it).  The wavefront
+//   - loads the window of old cells [d - H, d + B + H) (Q cells per lane,
+//     lane-consecutive, all loads in flight together) into its LDS region,
+//     hashing every live key on the way (all lanes at once) to its new home;
+//   - finds the empty cells with ballots, hence the window range [lo, hi) of
+//     the clusters that overlap the block and their starts;
+//   - re-inserts each such cluster in old-array order (one lane per cluster;
+//     Lemma 1 makes their target ranges disjoint) into an image of the new
+//     range that holds 16-bit indices into the window;
+//   - streams the owned part of the image out as whole cells.
 // Elements of the last cluster that land past the owned range are written by
-// the next workgroup, which sees that cluster as its incoming one; the first
-// block's incoming cluster is the one that wraps around the table end.
-// Positions are kept unwrapped (old cell x may be negative for block 0).
-// A cluster longer than the halo (or a table without empty cells) sets the
+// the next block's wavefront, which sees that cluster as its incoming one; the
+// first block's incoming cluster is the one that wraps around the table end.
+// Positions are kept unwrapped (old cell x may be negative for block 0).  A
+// cluster longer than the halo (or a table without empty cells) sets the
 // overflow flag; the guarded simple migration then redoes the whole move.
 constexpr int MIG_HALO = 128;
-constexpr int MIG_THREADS = 256;
+constexpr uint16_t kImgEmpty = 0xFFFF;
 
 __host__ __device__ constexpr uint32_t mig_window(uint32_t mb) { return mb + 2 * MIG_HALO; }
 
-__host__ __device__ constexpr size_t mig_lds_bytes(uint32_t mb, uint32_t layout, uint32_t gamma) {
-  return (size_t)mig_window(mb) * (layout == 0 ? 8u : 16u) * (1 + gamma);
+// LDS of one wavefront: window keys and values (u64 each; PACKED32 keeps the
+// word in the key array), each window cell's state (i32: the new home's image
+// slot, or one of the negative codes below), the image (u16 per new cell) and
+// the list of cluster starts (u16 per start, at most half the window).
+__host__ __device__ constexpr size_t mig_wave_lds(uint32_t mb, uint32_t layout, uint32_t gamma) {
+  return ((size_t)mig_window(mb) * ((layout == 0 ? 8u : 16u) + 4u + 1u) + (size_t)gamma * mig_window(mb) * 2u +
+          15) &
+         ~(size_t)15;
 }
+constexpr int32_t kCellEmpty = -1, kCellTomb = -2, kCellFar = -3;  // window cell states
 
-// Q = window cells per thread (window = mb + 2*MIG_HALO cells, a multiple of
-// MIG_THREADS).  The next block's window is loaded into registers while the
-// current block is processed, so the loads' latency overlaps the LDS work.
+// Q = window cells per lane; the block is B = 64 Q - 2 MIG_HALO old cells.
+// A workgroup is 1..4 wavefronts, each with its own LDS region.
 template <int LAYOUT, int Q>
-__global__ void __launch_bounds__(MIG_THREADS) k_migrate_lds(const void *old_cells, uint32_t log2_old,
-                                                             void *new_cells, uint32_t g,
-                                                             uint32_t crc_hi, uint32_t crc_lo,
-                                                             uint32_t mb, DevStatus *st) {
+__global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint32_t log2_old,
+                                                     void *new_cells, uint32_t g, uint32_t crc_hi,
+                                                     uint32_t crc_lo, DevStatus *st) {
   __shared__ uint32_t T[8][256];
   __shared__ long long s_acc[2];
   __shared__ uint32_t s_err;
-  __shared__ int s_last_empty, s_first_empty;
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
   crc_tables_build(T);
 
-  const int H = MIG_HALO;
-  const uint32_t W = mig_window(mb);  // == Q * MIG_THREADS
-  const uint32_t gamma = 1u << g;
-  const uint32_t IW = gamma * W;      // image cells
-  // old window and image: key and value arrays (KV64) or words (PACKED32)
-  u64 *okey = (u64 *)dyn_lds;
-  u64 *oval = okey + W;                              // KV64 only
-  u64 *ikey = (LAYOUT == 0) ? okey + W : okey + 2 * W;
-  u64 *ival = ikey + IW;                             // KV64 only
-  auto key_o = [&](int t) -> u64 { return LAYOUT == 0 ? (okey[t] & 0xFFFFFFFFull) : okey[t]; };
-  auto key_i = [&](uint32_t t) -> u64 { return LAYOUT == 0 ? (ikey[t] & 0xFFFFFFFFull) : ikey[t]; };
+  constexpr int H = MIG_HALO;
+  constexpr uint32_t W = 64 * Q;  // window cells
+  constexpr uint32_t mb = W - 2 * H;
+  static_assert(H % 64 == 0 && mb % 64 == 0, "window of whole lane rows");
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t gamma = 1u << g;  // 1 or 2
+  const uint32_t IW = gamma * W;   // image slots
+  unsigned char *base = dyn_lds + wave * mig_wave_lds(mb, LAYOUT, gamma);
+  u64 *wkey = (u64 *)base;
+  u64 *wval = wkey + W;                                   // KV64 only
+  int32_t *wnh = (int32_t *)(wkey + (LAYOUT == 0 ? W : 2 * W));
+  uint16_t *img = (uint16_t *)(wnh + W);
+  uint16_t *starts = img + IW;  // cluster starts of [lo, hi)
 
   const u64 cap = 1ull << log2_old, mask = cap - 1;
   const uint32_t log2_new = log2_old + g;
   const u64 nblocks = cap >> (31 - __builtin_clz(mb));  // cap / mb, both powers of two
-  const uint32_t tid = threadIdx.x;
+  const uint32_t nwb = blockDim.x >> 6;
+  const u64 nw = (u64)gridDim.x * nwb;
   long long moved = 0;
+  bool overflow = false;
 
-  u64x2 pre[Q];
-  auto issue = [&](u64 b) {
-    const long long d = (long long)(b * mb);
+  // window cells t = lane + 64 q of block b, loaded into registers; the next
+  // block's loads are issued before the current block is worked on, so their
+  // latency overlaps the work
+  u64 nk[Q], nv[Q];
+  auto load_window = [&](u64 b) {
+    const long long wb = (long long)(b * mb) - H;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const u64 x = (u64)(d - H + (long long)(tid + q * MIG_THREADS)) & mask;
+      const u64 x = (u64)(wb + (long long)(lane + 64 * q)) & mask;
       if (LAYOUT == 0) {
-        pre[q].x = ((const u64 *)old_cells)[x];
+        nk[q] = ((const u64 *)old_cells)[x];
+        nv[q] = 0;
       } else {
-        pre[q] = ((const u64x2 *)old_cells)[x];
+        const u64x2 c = ((const u64x2 *)old_cells)[x];
+        nk[q] = c.x;
+        nv[q] = c.y;
       }
     }
   };
-
-  u64 blk = blockIdx.x;
-  if (blk < nblocks) issue(blk);
-  for (; blk < nblocks; blk += gridDim.x) {
+  u64 blk = (u64)blockIdx.x * nwb + wave;
+  if (blk < nblocks) load_window(blk);
+  for (; blk < nblocks; blk += nw) {
     const long long d = (long long)(blk * mb);
+    const long long wbase = d - H;  // unwrapped old index of window cell 0
+    u64 k[Q], v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const uint32_t t = tid + q * MIG_THREADS;
-      okey[t] = pre[q].x;
-      if (LAYOUT == 1) oval[t] = pre[q].y;
+      k[q] = nk[q];
+      v[q] = nv[q];
     }
-    for (uint32_t t = tid; t < IW; t += MIG_THREADS) {
-      ikey[t] = 0;
-      if (LAYOUT == 1) ival[t] = 0;
+    if (blk + nw < nblocks) load_window(blk + nw);
+    u64 emp[Q];  // ballot of empty window cells, 64 per word
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const uint32_t t = lane + 64 * q;
+      const u64 key = LAYOUT == 0 ? (k[q] & 0xFFFFFFFFull) : k[q];
+      wkey[t] = k[q];
+      if (LAYOUT == 1) wval[t] = v[q];
+      int32_t rel = key == kEmpty ? kCellEmpty : kCellTomb;
+      if (key != kEmpty && key != kTomb) {
+        // new home, unwrapped consistently with this cell's old position
+        const u64 hn = home_of<LAYOUT>(T, key, crc_hi, crc_lo, log2_new);
+        const u64 oh = hn >> g;
+        const long long x = wbase + (long long)t;
+        const u64 delta = ((u64)x - oh) & mask;
+        const long long nh = (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
+        const long long r = nh - (long long)gamma * wbase;  // image slot of the home
+        rel = (r < 0 || r >= (long long)IW) ? kCellFar : (int32_t)r;
+      }
+      wnh[t] = rel;
+      emp[q] = __ballot(key == kEmpty);
     }
-    if (tid == 0) {
-      s_last_empty = -1;
-      s_first_empty = 0x7FFFFFFF;
-    }
-    __syncthreads();
-    if (blk + gridDim.x < nblocks) issue(blk + gridDim.x);
-    for (uint32_t t = tid; t < (uint32_t)H; t += MIG_THREADS)
-      if (key_o(t) == kEmpty) atomicMax(&s_last_empty, (int)t);
-    for (uint32_t t = H + mb + tid; t < W; t += MIG_THREADS)
-      if (key_o(t) == kEmpty) atomicMin(&s_first_empty, (int)t);
-    __syncthreads();
-    // window indices [lo, hi) of the clusters that overlap the block
-    bool skip = false;
+    for (uint32_t t = lane; t < IW / 2; t += 64) ((uint32_t *)img)[t] = 0xFFFFFFFFu;
+    // the window range [lo, hi) of the clusters overlapping the block
+    // (cell H - 1 and cell H both non-empty: a cluster comes in from before);
+    // every index into emp[] is a constant, so it stays in registers
     int lo = H, hi = H + (int)mb;
-    if (key_o(H - 1) != kEmpty && key_o(H) != kEmpty) {
-      if (s_last_empty < 0) skip = true;
-      lo = s_last_empty + 1;
+    bool skip = false;
+    if (!((emp[H / 64 - 1] >> 63) & 1ull) && !(emp[H / 64] & 1ull)) {
+      int last = -1;
+#pragma unroll
+      for (int q = 0; q < H / 64; ++q)
+        if (emp[q]) last = 64 * q + 63 - __builtin_clzll(emp[q]);
+      if (last < 0) skip = true;
+      lo = last + 1;
     }
-    if (key_o(H + mb - 1) != kEmpty) {
-      if (s_first_empty == 0x7FFFFFFF) skip = true;
-      hi = s_first_empty;
+    if (!((emp[(H + mb) / 64 - 1] >> 63) & 1ull)) {
+      int first = -1;
+#pragma unroll
+      for (int q = Q - 1; q >= 0; --q) {
+        if (64 * q < H + (int)mb) break;
+        if (emp[q]) first = 64 * q + __builtin_ctzll(emp[q]);
+      }
+      if (first < 0) skip = true;
+      hi = first;
     }
+    wave_sync();
     if (skip) {
-      if (tid == 0) atomicOr(&st->overflow, 1ull);
+      overflow = true;
     } else {
-      const long long ib = (long long)gamma * (d - H + lo);  // image base (unwrapped new index)
+      // the cluster starts in [lo, hi) (non-empty cells after an empty one),
+      // listed in LDS; lanes then take them round-robin, each walking its
+      // clusters in old-array order
+      uint32_t nstarts = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int t = (int)lane + 64 * q;
+        const bool here_empty = (emp[q] >> lane) & 1ull;
+        const bool prev_empty =
+            lane ? (bool)((emp[q] >> (lane - 1)) & 1ull) : (q == 0 ? true : (bool)(emp[q > 0 ? q - 1 : 0] >> 63));
+        const bool st0 = t >= lo && t < hi && !here_empty && prev_empty;
+        const u64 m = __ballot(st0);
+        if (st0) starts[nstarts + __builtin_popcountll(m & ((1ull << lane) - 1))] = (uint16_t)t;
+        nstarts += (uint32_t)__builtin_popcountll(m);
+      }
+      wave_sync();
       bool bad = false;
-      for (int t = lo + (int)tid; t < hi; t += MIG_THREADS) {
-        if (key_o(t) == kEmpty || key_o(t - 1) != kEmpty) continue;  // not a cluster start
-        for (int u = t; u < hi; ++u) {
-          const u64 k = key_o(u);
-          if (k == kEmpty) break;
-          if (k == kTomb) continue;
-          const long long x = d - H + u;  // unwrapped old position
-          const u64 hn = home_of<LAYOUT>(T, k, crc_hi, crc_lo, log2_new);
-          const u64 oh = hn >> g;  // home in the old table
-          const u64 delta = ((u64)x - oh) & mask;
-          const long long nh =
-              (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
-          long long p = nh - ib;
-          while (p >= 0 && p < (long long)IW && key_i((uint32_t)p) != kEmpty) ++p;
-          if (p < 0 || p >= (long long)IW) {
+      for (uint32_t i = lane; i < nstarts && !bad; i += 64) {
+        for (int u = starts[i]; u < hi; ++u) {
+          int p = wnh[u];
+          if (p == kCellEmpty) break;
+          if (p == kCellTomb) continue;
+          if (p < 0) {
             bad = true;
             break;
           }
-          if (LAYOUT == 0) {
-            ikey[p] = okey[u];
-          } else {
-            ikey[p] = k;
-            ival[p] = oval[u];
+          while (p < (int)IW && img[p] != kImgEmpty) ++p;
+          if (p >= (int)IW) {
+            bad = true;
+            break;
           }
+          img[p] = (uint16_t)u;
         }
       }
-      if (bad) atomicOr(&st->overflow, 1ull);
-    }
-    __syncthreads();
-    if (!skip) {
-      const uint32_t off = gamma * (uint32_t)(H - lo);
+      if (bad) overflow = true;
+      wave_sync();
+      // the owned new cells [g*d, g*(d+B)) = image slots [g*H, g*(H+B))
       const u64 dst0 = (u64)d * gamma;
-      for (uint32_t t = tid; t < gamma * mb; t += MIG_THREADS) {
+      const uint32_t n_out = gamma * mb;
+      for (uint32_t t = lane; t < n_out; t += 64) {
+        const uint16_t ix = img[gamma * H + t];
         if (LAYOUT == 0) {
-          const u64 w = ikey[off + t];
+          const u64 w = ix == kImgEmpty ? 0ull : wkey[ix];
           ((u64 *)new_cells)[dst0 + t] = w;
-          moved += (w != 0);
+          moved += (ix != kImgEmpty);
         } else {
-          const u64x2 c = {ikey[off + t], ival[off + t]};
+          u64x2 c = {0ull, 0ull};
+          if (ix != kImgEmpty) {
+            c.x = wkey[ix];
+            c.y = wval[ix];
+          }
           ((u64x2 *)new_cells)[dst0 + t] = c;
-          moved += (c.x != kEmpty);
+          moved += (ix != kImgEmpty);
         }
       }
     }
-    __syncthreads();
+    wave_sync();
   }
+  if (__any(overflow) && lane == 0) atomicOr(&st->overflow, 1ull);
   flush_counts(st, moved, moved, 0, s_acc, &s_err);
 }
 
@@ -1876,32 +1931,36 @@ hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_ce
   const u64 new_bytes = (1ull << log2_new) * (layout == 0 ? 8ull : 16ull);
   const uint32_t g = log2_new - log2_old;
   const uint32_t mb = cfg.migrate_block;
-  // static LDS of the kernel (CRC tables and counters) plus the staged window
-  // and image must fit the 64 KiB a workgroup may allocate
-  const size_t lds_total = (g <= 1) ? mig_lds_bytes(mb, layout, 1u << g) + 8192 + 64 : ~(size_t)0;
-  const bool lds_path = !old_is_full && g <= 1 && mb >= 256 && cap >= mb && lds_total <= 65536;
+  // static LDS of the kernel (CRC tables and counters) plus one region per
+  // wavefront; as many wavefronts (up to 4) as fit the 64 KiB a workgroup may
+  // allocate
+  const size_t per_wave = g <= 1 ? mig_wave_lds(mb, layout, 1u << g) : ~(size_t)0 / 8;
+  const size_t fixed = 8192 + 64;
+  const uint32_t wpb = per_wave > 65536 - fixed ? 0u : (uint32_t)std::min<size_t>(4, (65536 - fixed) / per_wave);
+  const bool lds_path = !old_is_full && g <= 1 && (mb == 256 || mb == 512 || mb == 1024) && cap >= mb &&
+                        wpb >= 1;
   const uint32_t sgrid = grid_for(cap, LaunchCfg{256, 1, cfg.blocks_per_cu, cfg.num_cus, mb, 0});
   if (lds_path) {
-    const size_t lds = mig_lds_bytes(mb, layout, 1u << g);
-    u64 nblocks = cap / mb;
-    u64 per_cu = (160 * 1024) / lds_total;
+    const size_t lds = wpb * per_wave;
+    const u64 nwaves = cap / mb;
+    u64 per_cu = (160 * 1024) / (lds + fixed);
     if (per_cu < 1) per_cu = 1;
     u64 grid = (u64)cfg.num_cus * per_cu;
-    if (grid > nblocks) grid = nblocks;
+    const u64 need = (nwaves + wpb - 1) / wpb;
+    if (grid > need) grid = need;
 #define LPHT_MIG_LAUNCH(L, Q)                                                                    \
-  hipLaunchKernelGGL((k_migrate_lds<L, Q>), dim3((uint32_t)grid), dim3(MIG_THREADS), lds, s, old_cells, \
-                     log2_old, new_cells, g, crc_hi, crc_lo, mb, st)
-    switch (mig_window(mb) / MIG_THREADS) {
-      case 2: if (layout == 0) LPHT_MIG_LAUNCH(0, 2); else LPHT_MIG_LAUNCH(1, 2); break;
-      case 3: if (layout == 0) LPHT_MIG_LAUNCH(0, 3); else LPHT_MIG_LAUNCH(1, 3); break;
-      case 5: if (layout == 0) LPHT_MIG_LAUNCH(0, 5); else LPHT_MIG_LAUNCH(1, 5); break;
-      case 9: if (layout == 0) LPHT_MIG_LAUNCH(0, 9); else LPHT_MIG_LAUNCH(1, 9); break;
+  hipLaunchKernelGGL((k_migrate_lds<L, Q>), dim3((uint32_t)grid), dim3(64 * wpb), lds, s, old_cells, \
+                     log2_old, new_cells, g, crc_hi, crc_lo, st)
+    switch (mig_window(mb) / 64) {
+      case 8: if (layout == 0) LPHT_MIG_LAUNCH(0, 8); else LPHT_MIG_LAUNCH(1, 8); break;
+      case 12: if (layout == 0) LPHT_MIG_LAUNCH(0, 12); else LPHT_MIG_LAUNCH(1, 12); break;
+      case 20: if (layout == 0) LPHT_MIG_LAUNCH(0, 20); else LPHT_MIG_LAUNCH(1, 20); break;
       default: return hipErrorInvalidValue;
     }
 #undef LPHT_MIG_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // fallback, a no-op unless a workgroup reported overflow
+    // fallback, a no-op unless a wavefront reported overflow
     const u64 n16 = new_bytes / 16;
     hipLaunchKernelGGL(k_fill_zero_if, dim3(grid_for(n16, cfg)), dim3(cfg.block_threads), 0, s,
                        (u64x2 *)new_cells, n16, st);

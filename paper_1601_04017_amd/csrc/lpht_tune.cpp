@@ -20,6 +20,7 @@ namespace {
 constexpr uint32_t kWidths[5] = {1, 2, 4, 8, 16};
 constexpr uint32_t kBlocks[3] = {256, 512, 1024};
 constexpr uint32_t kMigrateBlocks[4] = {256, 512, 1024, 2048};
+constexpr double kTie = 0.03;  // relative time difference treated as noise
 
 lpht_tuning default_tuning() {
   lpht_tuning u;
@@ -124,18 +125,32 @@ extern "C" int lpht_autotune(uint32_t layout, uint32_t log2c, uint32_t reps, voi
   lpht_tuning best = base;
   for (int qi = 0; qi < 4; ++qi) {
     const uint64_t end = (2 * (uint64_t)qi + 1) * c / 8;
-    uint32_t bf = 0, bi = 0;
     for (int gi = 0; gi < 5; ++gi) {
       lpht_tuning u = base;
       u.group_width = kWidths[gi];
       rc = measure(end, u, rep.insert_ms[qi][gi], rep.find_ms[qi][gi]);
       if (rc) return rc;
-      if (rep.find_ms[qi][gi] < rep.find_ms[qi][bf]) bf = gi;
-      if (rep.insert_ms[qi][gi] < rep.insert_ms[qi][bi]) bi = gi;
     }
-    best.g_find[qi] = (uint8_t)kWidths[bf];
-    best.g_modify[qi] = (uint8_t)kWidths[bi];
   }
+  // Per quarter the fastest width; but a quarter keeps the width chosen for
+  // fill 3/8 unless another is more than kTie faster, so that timing noise
+  // does not split calls into launches of different widths.
+  auto choose = [&](const double (*ms)[5], uint8_t *g) {
+    auto argmin = [&](int q) {
+      int b = 0;
+      for (int gi = 1; gi < 5; ++gi)
+        if (ms[q][gi] < ms[q][b]) b = gi;
+      return b;
+    };
+    const int ref = argmin(1);
+    g[1] = (uint8_t)kWidths[ref];
+    for (int q : {0, 2, 3}) {
+      const int b = argmin(q);
+      g[q] = (uint8_t)kWidths[ms[q][ref] <= ms[q][b] * (1.0 + kTie) ? ref : b];
+    }
+  };
+  choose(rep.find_ms, best.g_find);
+  choose(rep.insert_ms, best.g_modify);
   best.group_width = best.g_find[1];
 
   // workgroup size at fill 3/8 with the chosen widths

@@ -69,10 +69,12 @@ def calibration(path, counter, true_bytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--cal-fetch", required=True)
-    ap.add_argument("--cal-write", required=True)
+    ap.add_argument("--fetch", help="FETCH_SIZE pass (omit, with the other counter files, for a "
+                                    "durations-only summary)")
+    ap.add_argument("--write")
+    ap.add_argument("--cal-fetch")
+    ap.add_argument("--cal-write")
+    ap.add_argument("--rows", type=int, default=14, help="kernels listed in the durations table")
     ap.add_argument("--copy-bytes", type=float, default=float(1 << 31),
                     help="bytes read (= bytes written) by one calibration copy")
     ap.add_argument("--cmd", required=True, help="the commands that produced the CSV files")
@@ -84,19 +86,24 @@ def main():
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
 
-    ff = calibration(a.cal_fetch, "FETCH_SIZE", a.copy_bytes)
-    fw = calibration(a.cal_write, "WRITE_SIZE", a.copy_bytes)
     stats = read_stats(a.trace)
-    fetch = read_counters(a.fetch, "FETCH_SIZE")
-    write = read_counters(a.write, "WRITE_SIZE")
-
     lines = [f"# rocprofv3 summary: {os.path.basename(a.out)}", "", "Commands:", "", "```"]
     lines += a.cmd.split(";;")
     lines += ["```", "", f"Kernel source sha256[:16]: `{kernel_source_sha()}`", "",
               "## Kernel durations (--kernel-trace --stats)", "",
               "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
-    for s in stats[:14]:
+    for s in stats[:a.rows]:
         lines.append(f"| `{s['name']}` | {s['calls']} | {s['avg_us']:.1f} | {s['total_ms']:.2f} | {s['pct']:.1f} |")
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    if not a.fetch:
+        with open(a.out + ".md", "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print(open(a.out + ".md").read())
+        return
+    ff = calibration(a.cal_fetch, "FETCH_SIZE", a.copy_bytes)
+    fw = calibration(a.cal_write, "WRITE_SIZE", a.copy_bytes)
+    fetch = read_counters(a.fetch, "FETCH_SIZE")
+    write = read_counters(a.write, "WRITE_SIZE")
     lines += ["", f"## HBM bytes per dispatch (FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {fw:.3f})", "",
               "Calibration: a streaming copy of libroofline.so moving a known byte count.", "",
               "| kernel | dispatches | read MB/dispatch | write MB/dispatch |", "|---|---|---|---|"]
@@ -112,7 +119,6 @@ def main():
         traffic[name] = {"read_bytes": rd, "write_bytes": wr, "dispatches": len(big)}
         lines.append(f"| `{name}` | {len(big)} | {rd / 1e6:.1f} | {wr / 1e6:.1f} |")
     lines.append("")
-    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out + ".md", "w") as f:
         f.write("\n".join(lines) + "\n")
     dom = traffic.get(a.dominant)
