@@ -23,11 +23,15 @@ import os
 from collections import OrderedDict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRC = os.path.join(PKG, "csrc", "lpht_kernels.hip")
+KERNEL_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_kernels.hip", "lpht_device.h", "lpht_internal.h")]
 
 
 def kernel_source_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the table kernels are built from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _short(name: str) -> str:
