@@ -92,6 +92,7 @@ uint64_t orc_home(uint64_t h, uint32_t log2c) {
 typedef struct orc_table {
   int layout;
   uint32_t log2c;
+  uint32_t log2_min; /* the capacity it was created with: no automatic shrink below */
   uint64_t cap;
   uint64_t *cells;
   uint32_t seed_hi, seed_lo;
@@ -147,6 +148,7 @@ orc_table *orc_create(int layout, uint32_t log2c, uint32_t seed_hi, uint32_t see
   if (!t) return NULL;
   t->layout = layout;
   t->log2c = log2c;
+  t->log2_min = log2c;
   t->cap = 1ull << log2c;
   t->seed_hi = seed_hi;
   t->seed_lo = seed_lo;
@@ -337,8 +339,8 @@ uint64_t orc_probe_count(const orc_table *t, uint64_t k) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Migration (Sec. 5.3.1, growing with factor gamma = new/old >= 1) and      */
-/* cleanup of tombstones by migration (Sec. 5.4).                             */
+/* Migration (Sec. 5.3.1: growing with factor gamma = new/old >= 1, and      */
+/* shrinking, gamma < 1) and cleanup of tombstones by migration (Sec. 5.4).  */
 /* ------------------------------------------------------------------------- */
 
 /* The sequential migration: scan the old table once, starting just after an
@@ -349,8 +351,10 @@ uint64_t orc_probe_count(const orc_table *t, uint64_t k) {
  * from cell 0.  This is the sequential order whose placement the
  * block-parallel migration reproduces (Lemma 1). */
 int orc_migrate(orc_table *t, uint32_t log2_new) {
-  if (log2_new < t->log2c || log2_new > 40) return -1;
+  if (log2_new < 1 || log2_new > 40) return -1;
   uint64_t newcap = 1ull << log2_new;
+  /* the target must keep an empty cell (a smaller table may not) */
+  if (t->live >= newcap) return -3;
   uint64_t *nc = (uint64_t *)calloc(newcap * words_per_cell(t), sizeof(uint64_t));
   if (!nc) return -2;
   uint64_t e = t->cap - 1;
@@ -388,17 +392,31 @@ static int within_fill(const orc_table *t, uint64_t x, uint64_t c) {
 
 /* Growth rule applied before a batch of b operations that may insert
  * (bulk insertion by pre-growing, Sec. 5.5; trigger at fill factor alpha,
- * doubling, Sec. 5.3.2 and Sec. 7; cleanup decided on non-empty cells and on
- * live elements, Sec. 5.4):
+ * doubling, Sec. 5.3.2 and Sec. 7; the migration is triggered by the
+ * non-empty cells I and its size chosen from the live elements I - D,
+ * Sec. 5.4):
  *   used + b <= alpha*c            -> nothing;
- *   live + b <= alpha*c/2          -> migrate with gamma = 1 (drop tombstones);
+ *   live + b <= alpha*c/2          -> migrate once to c' = c / 2^s, the
+ *                                     smallest s >= 0 with c' >= the created
+ *                                     capacity such that halving once more
+ *                                     would give live + b > alpha*c'/2
+ *                                     (s = 0: gamma = 1, tombstones dropped;
+ *                                     s > 0: a shrink);
  *   otherwise                      -> migrate with gamma = 2, repeated while
  *                                     live + b > alpha*c. */
+static int fits_quarter(const orc_table *t, uint64_t x, uint64_t c) {
+  /* x <= alpha * c / 4 */
+  return (unsigned __int128)x * 4 * t->alpha_den <= (unsigned __int128)c * t->alpha_num;
+}
+
 static int grow_before_batch(orc_table *t, uint64_t b) {
   if (!t->auto_grow || b == 0) return 0;
   if (within_fill(t, t->used + b, t->cap)) return 0;
-  if ((unsigned __int128)(t->live + b) * 2 * t->alpha_den <= (unsigned __int128)t->cap * t->alpha_num)
-    return orc_migrate(t, t->log2c);
+  if ((unsigned __int128)(t->live + b) * 2 * t->alpha_den <= (unsigned __int128)t->cap * t->alpha_num) {
+    uint32_t target = t->log2c;
+    while (target > t->log2_min && fits_quarter(t, t->live + b, 1ull << target)) --target;
+    return orc_migrate(t, target);
+  }
   do {
     if (t->log2c >= 40) return -1;
     int rc = orc_migrate(t, t->log2c + 1);
@@ -475,12 +493,10 @@ int orc_erase(orc_table *t, const void *keys, uint64_t n, uint8_t *flags) {
   return 0;
 }
 
-/* Explicit resize entry (gamma = 2^(log2_new - log2c) >= 1; equal size is
- * the tombstone cleanup with gamma = 1). */
-int orc_grow(orc_table *t, uint32_t log2_new) {
-  if (log2_new < t->log2c) return -1;
-  return orc_migrate(t, log2_new);
-}
+/* Explicit resize entry: gamma = 2^(log2_new - log2c); equal size is the
+ * tombstone cleanup with gamma = 1, a smaller size a shrink (-3 when the live
+ * elements would not leave an empty cell). */
+int orc_grow(orc_table *t, uint32_t log2_new) { return orc_migrate(t, log2_new); }
 
 /* Hash of many keys at once (for test comparisons). */
 void orc_hash_bulk(const void *keys, uint64_t n, int key_bytes, uint32_t seed_hi, uint32_t seed_lo,

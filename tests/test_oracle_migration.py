@@ -239,3 +239,78 @@ def test_zipf_upsert_with_growth_matches_histogram():
     assert H.live_dict(t.cells(), oracle.KV64) == dict(zip(uk.tolist(), cnt.tolist()))
     used, live = t.counts()
     assert used == live == uk.size
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_cleanup_shrinks_to_hand_computed_capacity(layout):
+    # Created at 2^6 cells, auto-grow, alpha = 1/2.  30000 inserts grow it to
+    # 2^16 (30000 <= 32768 = alpha * 2^16, > alpha * 2^15).  Erasing all but 10
+    # leaves used = 30000, live = 10.  A batch of b = 3000 inserts triggers a
+    # migration (used + b = 33000 > 32768), and live + b = 3010 <= alpha*c/2 =
+    # 16384 makes it a cleanup that may shrink: halving 2^16 -> 2^15 needs
+    # 3010 <= alpha * 2^16 / 4 = 8192 (yes), 2^15 -> 2^14 needs 3010 <= 4096
+    # (yes), 2^14 -> 2^13 needs 3010 <= 2048 (no): one migration to 2^14.
+    keys = (inputs.distinct_keys_u32(33000, 6) if layout == oracle.PACKED32
+            else inputs.distinct_keys_u64(33000, 6))
+    t = oracle.OracleTable(layout, 6, auto_grow=True)
+    t.insert(keys[:30000])
+    assert t.capacity == 1 << 16
+    t.erase(keys[10:30000])
+    assert t.counts() == (30000, 10)
+    m0 = t.migrations
+    t.insert(keys[30000:33000])
+    assert t.capacity == 1 << 14
+    assert t.migrations == m0 + 1
+    assert t.counts() == (3010, 3010)
+    H.check_invariants(t.cells(), layout, 14, 3010, 3010)
+    live = H.live_dict(t.cells(), layout)
+    assert sorted(live) == sorted(np.concatenate([keys[:10], keys[30000:33000]]).tolist())
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_cleanup_never_shrinks_below_created_capacity(layout):
+    # created at 2^12: however few keys stay live, cleanups keep >= 2^12 cells
+    keys = (inputs.distinct_keys_u32(12000, 8) if layout == oracle.PACKED32
+            else inputs.distinct_keys_u64(12000, 8))
+    t = oracle.OracleTable(layout, 12, auto_grow=True)
+    t.insert(keys[:6000])
+    t.erase(keys[:5990])
+    for lo in range(6000, 12000, 300):
+        t.insert(keys[lo:lo + 300])
+        t.erase(keys[lo:lo + 290])
+        assert t.capacity >= 1 << 12
+    assert t.migrations >= 1
+    H.check_invariants(t.cells(), layout, t.log2c, *t.counts())
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("shrink", [1, 2, 3])
+def test_explicit_shrink_keeps_contents_and_order_free_occupancy(layout, shrink):
+    log2c = 12
+    t = _filled(layout, log2c, 0.2, 0.5, 60 + shrink)  # about 410 live keys
+    live_before = H.live_dict(t.cells(), layout)
+    t.grow(log2c - shrink)
+    cells = t.cells()
+    assert t.capacity == 1 << (log2c - shrink)
+    assert H.live_dict(cells, layout) == live_before
+    H.check_invariants(cells, layout, log2c - shrink, len(live_before), len(live_before))
+    # the occupancy of a linear-probing table does not depend on the order of
+    # insertion: the same keys inserted in a random order give the same cells
+    ks = np.array(list(live_before.keys()), dtype=np.uint64)
+    vs = np.array([live_before[k] for k in ks.tolist()], dtype=np.uint64)
+    perm = np.random.default_rng(shrink).permutation(ks.size)
+    dt = np.uint32 if layout == oracle.PACKED32 else np.uint64
+    ref = oracle.OracleTable(layout, log2c - shrink)
+    ref.insert(ks[perm].astype(dt), vs[perm].astype(dt))
+    assert np.array_equal(H.occupancy(cells, layout), H.occupancy(ref.cells(), layout))
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_shrink_without_room_is_refused(layout):
+    t = oracle.OracleTable(layout, 10)
+    keys = (inputs.distinct_keys_u32(300, 2) if layout == oracle.PACKED32
+            else inputs.distinct_keys_u64(300, 2))
+    t.insert(keys)
+    with pytest.raises(RuntimeError):
+        t.grow(8)  # 256 cells cannot hold 300 keys and an empty cell
+    assert t.capacity == 1 << 10 and t.counts() == (300, 300)

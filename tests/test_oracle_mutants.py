@@ -33,8 +33,13 @@ MUTANTS = [
      "if (k == ORC_EMPTY) continue;"),
     ("growth_single_doubling", "grow_before_batch", "} while (!within_fill(t, t->live + b, t->cap));",
      "} while (0);"),
-    ("growth_never_cleans", "grow_before_batch", "return orc_migrate(t, t->log2c);",
+    ("growth_never_cleans", "grow_before_batch", "return orc_migrate(t, target);",
      "return orc_migrate(t, t->log2c + 1);"),
+    ("growth_never_shrinks", "grow_before_batch",
+     "while (target > t->log2_min && fits_quarter(t, t->live + b, 1ull << target)) --target;", ";"),
+    ("shrink_below_created_capacity", "grow_before_batch", "target > t->log2_min && ", ""),
+    ("shrink_one_step_too_far", "grow_before_batch", "fits_quarter(t, t->live + b, 1ull << target)",
+     "within_fill(t, t->live + b, 1ull << target)"),
 ]
 
 
@@ -64,6 +69,9 @@ def _pins():
         yield lambda layout=layout: TM.test_migration_equals_insert_in_scan_order(layout, 1, 0.5, 0.2)
         yield lambda layout=layout: TM.test_growth_insert_only_final_capacity_closed_form(layout)
         yield lambda layout=layout: TM.test_tombstone_cleanup_same_size(layout)
+        yield lambda layout=layout: TM.test_cleanup_shrinks_to_hand_computed_capacity(layout)
+        yield lambda layout=layout: TM.test_cleanup_never_shrinks_below_created_capacity(layout)
+        yield lambda layout=layout: TM.test_explicit_shrink_keeps_contents_and_order_free_occupancy(layout, 2)
 
 
 @pytest.mark.parametrize("name,func,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
