@@ -157,13 +157,14 @@ def _timed(fn, stream):
     return a.elapsed_time(b)
 
 
-SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "zipf", "serving")
+SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "deletion", "zipf", "serving")
 
 
 def run_suite(dev, reps=3, parts=SUITE_PARTS):
     """The other workloads, each timed on the GPU (mean of `reps` after one
     warm-up): packed 2^21 table; the fill sweep of the 2^28 table; growing
-    from 4096 cells in batches of 2^20; Zipf insert-or-increment presized and
+    from 4096 cells in batches of 2^20; the deletion test (sliding window of
+    10^7 keys) and shrinking migrations; Zipf insert-or-increment presized and
     growing for s in {0.5, 1, 1.25, 1.5}; and the measured memory ceilings."""
     import torch
 
@@ -180,7 +181,7 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
         out["ceilings"] = roofline.measure()
     if "packed32" in parts:
         out["packed32_2e21"] = _suite_packed32(dev, up, stream, reps)
-    need_keys = "fill_sweep" in parts or "growing" in parts
+    need_keys = "fill_sweep" in parts or "growing" in parts or "deletion" in parts
     if need_keys:
         nmax = 201_326_592
         keys = inputs.distinct_keys_u64(nmax, 201)
@@ -191,6 +192,9 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
         out["fill_sweep_2e28"] = _suite_fill_sweep(dev, up, stream, reps, dkeys, dvals)
     if "growing" in parts:
         out["growing_from_4096"] = _suite_growing(stream, reps, dkeys, dvals)
+    if "deletion" in parts:
+        out["deletion_window_1e7"] = _suite_deletion(stream, dkeys, dvals)
+        out["shrink_2e26"] = _suite_shrink(stream, dkeys, dvals)
     if need_keys:
         del dkeys, dvals
     if "zipf" in parts:
@@ -363,6 +367,79 @@ def _suite_growing(stream, reps, dkeys, dvals):
             "insert_ms_excl_migration": round(el - mig, 3),
             "mops": round(N_OPS / el / 1e3, 1), "data_migrations": int(nmig),
             "resizes": int(nres), "final_log2_capacity": int(lg), "host_syncs": int(syncs)}
+
+
+WINDOW = 10 ** 7
+ALTERNATIONS = 10 ** 8
+
+
+def _suite_deletion(stream, dkeys, dvals):
+    import torch
+
+    from paper_1601_04017_amd import lpht
+
+    # Deletion test: a table created for 1.5e7 elements (2^24 cells, auto
+    # growth) prefilled with 10^7 keys, then 10^8 alternations of inserting
+    # the next key and erasing the key 10^7 before it, in batches of b
+    # inserts followed by the b matching erases; one alternation counts as
+    # one operation.  Tombstones are reclaimed by the cleanup migrations.
+    out = {}
+    for b in (1 << 16, 1 << 20):
+        log(f"suite: deletion window, batches of {b}")
+        t = new_table(layout=lpht.KV64, log2_capacity=24, auto_grow=True)
+        t.set_timing(True)
+        for lo in range(0, WINDOW, 1 << 20):
+            hi = min(WINDOW, lo + (1 << 20))
+            t.insert(dkeys[lo:hi], dvals[lo:hi], flags=False)
+        st0 = t.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lo in range(0, ALTERNATIONS, b):
+            hi = min(ALTERNATIONS, lo + b)
+            t.insert(dkeys[WINDOW + lo:WINDOW + hi], dvals[WINDOW + lo:WINDOW + hi], flags=False)
+            t.erase(dkeys[lo:hi], flags=False)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) * 1e3
+        st = t.stats()
+        assert t.count()[1] == WINDOW, t.count()
+        assert t.status() == 0
+        out[str(b)] = {"total_ms": round(el, 3), "mops": round(ALTERNATIONS / el / 1e3, 1),
+                       "cleanup_migrations": int(st["resizes"] - st0["resizes"]),
+                       "cleanup_ms": round(st["migrate_ms"] - st0["migrate_ms"], 3),
+                       "shrinks": int(st["shrinks"]), "final_log2_capacity": int(t.log2_capacity),
+                       "host_syncs": int(st["host_syncs"] - st0["host_syncs"])}
+        t.close()
+    return out
+
+
+def _suite_shrink(stream, dkeys, dvals):
+    import torch
+
+    from paper_1601_04017_amd import lpht
+
+    # Shrinking migrations of a 2^26-cell KV64 table holding 2^22 live keys
+    # (and 2^22 tombstones) into 2^25 and 2^23 cells; algorithmic bytes = the
+    # old cells read once plus the new cells written once.
+    out = {}
+    n = 1 << 23
+    for log2_new in (25, 23):
+        res = []
+        for r in range(3):
+            t = new_table(layout=lpht.KV64, log2_capacity=26)
+            t.insert(dkeys[:n], dvals[:n], flags=False)
+            t.erase(dkeys[:n:2].contiguous(), flags=False)
+            t.set_timing(True)
+            t.grow(log2_new)
+            torch.cuda.synchronize()
+            st = t.stats()
+            assert t.count() == (n // 2, n // 2) and st["shrinks"] == 1
+            if r:
+                res.append(st["migrate_ms"])
+            t.close()
+        ms = float(np.mean(res))
+        nbytes = (1 << 26) * 16 + (1 << log2_new) * 16
+        out[f"to_2e{log2_new}"] = {"ms": round(ms, 4), "algorithmic_gbs": round(nbytes / ms / 1e6, 1)}
+    return out
 
 
 def _suite_zipf(up, stream, reps):

@@ -7,8 +7,9 @@
  * Dementiev, "Concurrent Hash Tables: Fast and General(?)!" (arXiv 1601.04017),
  * Sec. 4 and Algorithm 1, with tombstone deletion (Sec. 5.4), growth by
  * block-parallel cluster migration into a table of double size (Sec. 5.3.1,
- * Lemma 1), bulk insertion by pre-growing (Sec. 5.5) and the paper's hash
- * function (two CRC-32C with different seeds, Sec. 8.3).
+ * Lemma 1), shrinking by two-phase migration (Sec. 5.3.1, "Shrinking"), bulk
+ * insertion by pre-growing (Sec. 5.5) and the paper's hash function (two
+ * CRC-32C with different seeds, Sec. 8.3).
  *
  * Conventions shared by all calls
  * -------------------------------
@@ -95,7 +96,15 @@ typedef struct lpht_config {
   uint32_t seed_lo;       /* CRC-32C seed of the lower 32 hash bits */
   uint32_t max_fill_num;  /* growth trigger alpha = num/den, 0 < alpha <= 1 (Sec. 5.3.2) */
   uint32_t max_fill_den;
-  uint32_t auto_grow;     /* 0: bounded folklore table; 1: grow before batches (Sec. 5.5) */
+  uint32_t auto_grow;     /* 0: bounded folklore table; 1: migrate before batches (Sec. 5.5):
+                           * with b the operations of a call that may insert,
+                           * used + b > alpha*c triggers a migration (Sec. 5.4:
+                           * triggered by non-empty cells, sized by live ones);
+                           * if live + b <= alpha*c/2 it is a cleanup into the
+                           * smallest c' >= the created capacity with
+                           * live + b <= alpha*c'/2 (c' = c drops tombstones,
+                           * c' < c shrinks), else the table doubles until
+                           * live + b <= alpha*c */
   uint32_t reserved0;     /* must be 0 */
   lpht_alloc_fn alloc;
   lpht_free_fn free;
@@ -127,6 +136,7 @@ typedef struct lpht_stats {
   uint64_t cells_migrated; /* sum of old capacities over data migrations */
   uint64_t host_syncs;     /* count synchronisations the growth rule needed */
   double migrate_ms;       /* device time of data migrations (when timing is on) */
+  uint64_t shrinks;        /* data migrations to a smaller capacity */
 } lpht_stats;
 
 typedef struct lpht_table lpht_table; /* opaque; owned by the library */
@@ -179,11 +189,17 @@ int lpht_update(lpht_table *t, const void *keys, const void *vals, uint64_t n, u
  * it.  Tombstones are removed only by migration. */
 int lpht_erase(lpht_table *t, const void *keys, uint64_t n, uint8_t *flags, void *stream);
 
-/* Migrates the table into a new table of 2^log2_new_capacity cells
- * (gamma = 2^(log2_new - log2_old) >= 1; equal sizes drop tombstones,
- * Sec. 5.4) by block-parallel cluster migration (Sec. 5.3.1).  The placement
- * equals the sequential migration's exactly (Lemma 1).  Errors: INVALID
- * (shrinking), OOM. */
+/* Migrates the table into a new table of 2^log2_new_capacity cells, 6..34.
+ * Growing or equal sizes (gamma = 2^(log2_new - log2_old) >= 1; equal sizes
+ * drop tombstones, Sec. 5.4): block-parallel cluster migration (Sec. 5.3.1);
+ * the placement equals the sequential migration's exactly (Lemma 1).
+ * Smaller sizes: two-phase shrinking migration (Sec. 5.3.1, "Shrinking"):
+ * source blocks are placed into disjoint target blocks, then the elements
+ * that did not fit are inserted concurrently; the occupied cells and each
+ * cluster's key set equal the sequential migration's, the order of keys
+ * inside a cluster may differ.  Errors: INVALID (range), FULL (the live
+ * elements would not leave an empty cell in the smaller table; the table is
+ * unchanged), OOM. */
 int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream);
 
 /* Exact counts: `used` non-empty cells (live keys and tombstones), `live`

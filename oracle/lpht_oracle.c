@@ -353,8 +353,9 @@ uint64_t orc_probe_count(const orc_table *t, uint64_t k) {
 int orc_migrate(orc_table *t, uint32_t log2_new) {
   if (log2_new < 1 || log2_new > 40) return -1;
   uint64_t newcap = 1ull << log2_new;
-  /* the target must keep an empty cell (a smaller table may not) */
-  if (t->live >= newcap) return -3;
+  /* a smaller target must keep an empty cell; a table of the same or a
+   * larger size holds its live elements as they are */
+  if (log2_new < t->log2c && t->live >= newcap) return -3;
   uint64_t *nc = (uint64_t *)calloc(newcap * words_per_cell(t), sizeof(uint64_t));
   if (!nc) return -2;
   uint64_t e = t->cap - 1;

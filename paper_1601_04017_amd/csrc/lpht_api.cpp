@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lpht_host.h"
+#include "lpht_shrink.h"
 
 using namespace lpht;
 
@@ -191,9 +192,12 @@ int resize_empty(lpht_table *t, uint32_t log2_new, hipStream_t s, uint32_t steps
   return LPHT_OK;
 }
 
-// One migration into 2^log2_new cells (>= current).  The host must know the
-// exact live count (`known_live`); afterwards used = live = that count.
+// One migration into 2^log2_new cells.  The host must know the exact live
+// count (`known_live`); afterwards used = live = that count.  A smaller
+// target must have more cells than live elements (else LPHT_ERR_FULL, the
+// table unchanged).
 int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
+  if (log2_new < t->log2c && t->known_live >= (1ull << log2_new)) return LPHT_ERR_FULL;
   if (t->known_live == 0) return resize_empty(t, log2_new, s);
   const size_t ob = (size_t)cell_bytes(t->cfg.layout) << t->log2c;
   const size_t nb = (size_t)cell_bytes(t->cfg.layout) << log2_new;
@@ -206,10 +210,21 @@ int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
     (void)hipEventRecord(tm.start, s);
   }
   const int old_full = (t->known_used == (1ull << t->log2c)) ? 1 : 0;
+  const bool shrink = log2_new < t->log2c;
+  const size_t sb = shrink ? shrink_scratch_bytes(t->log2c, log2_new) : 0;
+  uint32_t *scratch = nullptr;
+  if (sb && !(scratch = (uint32_t *)dev_alloc(t, sb, s))) {
+    dev_free(t, nc, nb, s);
+    return LPHT_ERR_OOM;
+  }
   hipError_t e = launch_set_status(t->status, 0, 0, 0, s);
-  if (e == hipSuccess)
+  if (e == hipSuccess && shrink)
+    e = launch_shrink(t->cells, t->log2c, nc, log2_new, t->cfg.layout, t->crc_hi, t->crc_lo, scratch,
+                      t->status, t->launch, s);
+  else if (e == hipSuccess)
     e = launch_migrate(t->cells, t->log2c, nc, log2_new, t->cfg.layout, t->crc_hi, t->crc_lo,
                        old_full, t->status, t->launch, s);
+  if (scratch) dev_free(t, scratch, sb, s);
   if (e != hipSuccess) {
     dev_free(t, nc, nb, s);
     return from_hip(e);
@@ -221,6 +236,7 @@ int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
   dev_free(t, t->cells, ob, s);
   t->stats.migrations++;
   t->stats.resizes++;
+  if (shrink) t->stats.shrinks++;
   t->stats.cells_migrated += 1ull << t->log2c;
   t->cells = nc;
   t->log2c = log2_new;
@@ -232,10 +248,13 @@ int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
 
 // The growth rule before a batch of b operations that may insert (bulk
 // insertion by pre-growing, Sec. 5.5; trigger at fill factor alpha and
-// doubling, Sec. 5.3.2 and Sec. 7; cleanup decided on non-empty cells and
-// live elements, Sec. 5.4):
+// doubling, Sec. 5.3.2 and Sec. 7; the migration triggered by non-empty
+// cells and sized by live elements, Sec. 5.4):
 //   used + b <= alpha*c     -> nothing
-//   live + b <= alpha*c/2   -> migrate with gamma = 1 (drops tombstones)
+//   live + b <= alpha*c/2   -> one migration into c' = c / 2^k, the largest
+//                              k >= 0 with c' >= the created capacity and
+//                              live + b <= alpha*c'/2 (k = 0 drops
+//                              tombstones, k > 0 shrinks)
 //   otherwise               -> migrate with gamma = 2, repeated while
 //                              live + b > alpha*c.
 // Decisions use exact counts.  The host keeps an upper bound of `used` and
@@ -264,7 +283,12 @@ int grow_before_batch(lpht_table *t, uint64_t b, hipStream_t s) {
   }
   if ((unsigned __int128)(t->known_live + b) * 2 * t->cfg.max_fill_den <=
       (unsigned __int128)c * t->cfg.max_fill_num) {
-    rc = migrate_once(t, t->log2c, s);
+    // halve while live + b <= alpha * c_target / 4
+    uint32_t target = t->log2c;
+    while (target > t->log2_min && (unsigned __int128)(t->known_live + b) * 4 * t->cfg.max_fill_den <=
+                                       ((unsigned __int128)1 << target) * t->cfg.max_fill_num)
+      --target;
+    rc = migrate_once(t, target, s);
   } else {
     uint32_t target = t->log2c;
     do {
@@ -588,6 +612,7 @@ int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out) {
     return LPHT_ERR_OOM;
   }
   t->log2c = cfg->log2_capacity;
+  t->log2_min = cfg->log2_capacity;
   e = launch_fill_zero(t->cells, nb, t->launch, s);
   if (e != hipSuccess) {
     dev_free(t, t->cells, nb, s);
@@ -652,7 +677,7 @@ int lpht_erase(lpht_table *t, const void *keys, uint64_t n, uint8_t *flags, void
 
 int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream) {
   if (!t) return LPHT_ERR_INVALID;
-  if (log2_new_capacity < t->log2c || log2_new_capacity > 34) return LPHT_ERR_INVALID;
+  if (log2_new_capacity < 6 || log2_new_capacity > 34) return LPHT_ERR_INVALID;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
   int rc = sync_counts(t, s);

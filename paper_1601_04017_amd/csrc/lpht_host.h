@@ -17,6 +17,7 @@ struct lpht_table {
   lpht_config cfg;
   int device;
   uint32_t log2c;
+  uint32_t log2_min;  // the created capacity: the growth rule never shrinks below it
   void *cells;
   lpht::DevStatus *status;
   uint32_t crc_hi, crc_lo;

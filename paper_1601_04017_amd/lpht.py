@@ -85,6 +85,7 @@ class lpht_stats(ctypes.Structure):
         ("cells_migrated", ctypes.c_uint64),
         ("host_syncs", ctypes.c_uint64),
         ("migrate_ms", ctypes.c_double),
+        ("shrinks", ctypes.c_uint64),
     ]
 
 

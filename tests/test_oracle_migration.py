@@ -314,3 +314,19 @@ def test_shrink_without_room_is_refused(layout):
     with pytest.raises(RuntimeError):
         t.grow(8)  # 256 cells cannot hold 300 keys and an empty cell
     assert t.capacity == 1 << 10 and t.counts() == (300, 300)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_full_table_migrates_at_same_size(layout):
+    # a bounded table with every cell live: a gamma = 1 migration keeps it
+    # full (the scan starts at cell 0), only a smaller size is refused
+    keys = (inputs.distinct_keys_u32(64, 12) if layout == oracle.PACKED32
+            else inputs.distinct_keys_u64(64, 12))
+    t = oracle.OracleTable(layout, 6)
+    t.insert(keys)
+    assert t.counts() == (64, 64)
+    before = H.live_dict(t.cells(), layout)
+    t.grow(6)
+    assert t.counts() == (64, 64) and H.live_dict(t.cells(), layout) == before
+    with pytest.raises(RuntimeError):
+        t.grow(5)
