@@ -24,12 +24,14 @@ from collections import OrderedDict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_kernels.hip", "lpht_device.h", "lpht_internal.h")]
+SHRINK_SRCS = [os.path.join(PKG, "csrc", f)
+               for f in ("lpht_shrink.hip", "lpht_shrink.h", "lpht_device.h", "lpht_internal.h")]
 
 
-def kernel_source_sha() -> str:
-    """Hash of the sources the table kernels are built from."""
+def kernel_source_sha(srcs=None) -> str:
+    """Hash of the sources the table kernels (or the given files) are built from."""
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
+    for f in srcs or KERNEL_SRCS:
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
@@ -93,7 +95,8 @@ def main():
     stats = read_stats(a.trace)
     lines = [f"# rocprofv3 summary: {os.path.basename(a.out)}", "", "Commands:", "", "```"]
     lines += a.cmd.split(";;")
-    lines += ["```", "", f"Kernel source sha256[:16]: `{kernel_source_sha()}`", "",
+    lines += ["```", "", f"Kernel source sha256[:16]: `{kernel_source_sha()}` "
+              f"(shrink kernels: `{kernel_source_sha(SHRINK_SRCS)}`)", "",
               "## Kernel durations (--kernel-trace --stats)", "",
               "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
     for s in stats[:a.rows]:
