@@ -88,6 +88,8 @@ def load(path):
     L.orc_grow.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
     L.orc_migrate.restype = ctypes.c_int
     L.orc_migrate.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    L.orc_bulk_merge.restype = ctypes.c_int
+    L.orc_bulk_merge.argtypes = [ctypes.c_void_p, u8p, u8p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
     return L
 
 
@@ -225,3 +227,18 @@ class OracleTable:
         rc = lib().orc_grow(self._t, log2_new)
         if rc:
             raise RuntimeError(f"orc_grow failed: {rc}")
+
+    def build(self, keys, vals=None, op=ASSIGN):
+        """Replaces the contents by the batch (sort-based bulk build, Sec. 5.5)."""
+        self._bulk(keys, vals, op, 0)
+
+    def merge(self, keys, vals=None, op=ASSIGN):
+        """Merges the batch into the table (sort-based batched merge, Sec. 5.5)."""
+        self._bulk(keys, vals, op, 1)
+
+    def _bulk(self, keys, vals, op, keep_old):
+        keys = self._keys(keys)
+        vals = None if vals is None else np.ascontiguousarray(vals, dtype=self.kdt)
+        rc = lib().orc_bulk_merge(self._t, _ptr(keys), _ptr(vals), keys.size, op, keep_old)
+        if rc:
+            raise RuntimeError(f"orc_bulk_merge failed: {rc}")

@@ -499,6 +499,113 @@ int orc_erase(orc_table *t, const void *keys, uint64_t n, uint8_t *flags) {
  * elements would not leave an empty cell). */
 int orc_grow(orc_table *t, uint32_t log2_new) { return orc_migrate(t, log2_new); }
 
+/* ------------------------------------------------------------------------- */
+/* Bulk build and batched merge by sorting (Sec. 5.5).                        */
+/* ------------------------------------------------------------------------- */
+
+/* An element of a sorted batch: its 64-bit hash, key, value and sequence
+ * number (0 for an element already in the table, i + 1 for batch entry i). */
+typedef struct orc_item {
+  uint64_t h, k, v, seq;
+} orc_item;
+
+static int item_cmp(const void *a, const void *b) {
+  const orc_item *x = (const orc_item *)a, *y = (const orc_item *)b;
+  if (x->h != y->h) return x->h < y->h ? -1 : 1;
+  if (x->k != y->k) return x->k < y->k ? -1 : 1;
+  if (x->seq != y->seq) return x->seq < y->seq ? -1 : 1;
+  return 0;
+}
+
+/* Builds the table from a batch (keep_old = 0: the old contents are dropped)
+ * or merges the batch into it (keep_old = 1), following the sort-based bulk
+ * operation of Sec. 5.5:
+ *   1. the elements (the table's live elements first, then the batch in index
+ *      order) are sorted by their hash value; equal hashes by key, equal keys
+ *      by sequence number;
+ *   2. among equal keys all but the last are removed; with ORC_ADD the kept
+ *      element carries the wrapping sum of all their values, with ORC_ASSIGN
+ *      its own value (the batch's last occurrence overrides the table);
+ *   3. the result is inserted into an empty table in that sorted order by
+ *      ordinary linear probing, so each element starts its search for a free
+ *      cell at the larger of its home and the previous element's position.
+ * vals NULL means every value is 1.  Reserved keys are skipped (sticky
+ * RESERVED).  The capacity: unchanged for a bounded table; with auto growth
+ * doubled while (kept live elements + n) exceeds alpha * capacity (a + b is
+ * an upper bound of the new size, Sec. 5.5), never shrunk.  Returns -3
+ * (sticky FULL, table unchanged) when the distinct keys exceed the capacity,
+ * -2 when out of memory. */
+int orc_bulk_merge(orc_table *t, const void *keys, const void *vals, uint64_t n, int op, int keep_old) {
+  uint64_t old_n = keep_old ? t->live : 0;
+  orc_item *it = (orc_item *)malloc((old_n + n + 1) * sizeof(orc_item));
+  if (!it) return -2;
+  uint64_t m = 0;
+  if (keep_old)
+    for (uint64_t i = 0; i < t->cap; ++i) {
+      uint64_t k = key_at(t, t->cells, i);
+      if (k == ORC_EMPTY || k == ORC_TOMB) continue;
+      it[m].h = orc_hash(k, key_bytes(t), t->seed_hi, t->seed_lo);
+      it[m].k = k;
+      it[m].v = val_at(t, t->cells, i);
+      it[m].seq = 0;
+      ++m;
+    }
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t k = load_word(t, keys, i);
+    if (k == ORC_EMPTY || k == ORC_TOMB) {
+      t->sticky |= ORC_STICKY_RESERVED;
+      continue;
+    }
+    it[m].h = orc_hash(k, key_bytes(t), t->seed_hi, t->seed_lo);
+    it[m].k = k;
+    it[m].v = vals ? load_word(t, vals, i) : 1;
+    it[m].seq = i + 1;
+    ++m;
+  }
+  qsort(it, m, sizeof(orc_item), item_cmp);
+  uint64_t d = 0;
+  for (uint64_t i = 0; i < m; ++i) {
+    if (d > 0 && it[d - 1].k == it[i].k) {
+      it[d - 1].v = (op == ORC_ADD) ? apply_up(t, it[d - 1].v, it[i].v, ORC_ADD) : it[i].v;
+      it[d - 1].seq = it[i].seq;
+    } else {
+      it[d++] = it[i];
+    }
+  }
+  uint32_t log2c = t->log2c;
+  if (t->auto_grow)
+    while (!within_fill(t, old_n + n, 1ull << log2c)) {
+      if (log2c >= 40) {
+        free(it);
+        return -1;
+      }
+      ++log2c;
+    }
+  uint64_t cap = 1ull << log2c;
+  if (d > cap) {
+    free(it);
+    t->sticky |= ORC_STICKY_FULL;
+    return -3;
+  }
+  uint64_t *cells = (uint64_t *)calloc(cap * words_per_cell(t), sizeof(uint64_t));
+  if (!cells) {
+    free(it);
+    return -2;
+  }
+  for (uint64_t j = 0; j < d; ++j) {
+    uint64_t i = orc_home(it[j].h, log2c);
+    while (key_at(t, cells, i) != ORC_EMPTY) i = (i + 1) & (cap - 1);
+    set_cell(t, cells, i, it[j].k, it[j].v);
+  }
+  free(it);
+  free(t->cells);
+  t->cells = cells;
+  t->log2c = log2c;
+  t->cap = cap;
+  t->used = t->live = d;
+  return 0;
+}
+
 /* Hash of many keys at once (for test comparisons). */
 void orc_hash_bulk(const void *keys, uint64_t n, int key_bytes, uint32_t seed_hi, uint32_t seed_lo,
                    uint64_t *out) {

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import test_oracle_bulk as TB
 from tests import test_oracle_hash as TH
 from tests import test_oracle_migration as TM
 from tests import test_oracle_table as TT
@@ -40,6 +41,15 @@ MUTANTS = [
     ("shrink_below_created_capacity", "grow_before_batch", "target > t->log2_min && ", ""),
     ("shrink_one_step_too_far", "grow_before_batch", "fits_quarter(t, t->live + b, 1ull << target)",
      "within_fill(t, t->live + b, 1ull << target)"),
+    ("bulk_keeps_first", "orc_bulk_merge", ": it[i].v;", ": it[d - 1].v;"),
+    ("bulk_sorted_by_key", "item_cmp", "if (x->h != y->h) return x->h < y->h ? -1 : 1;",
+     "if (x->k != y->k) return x->k < y->k ? -1 : 1;"),
+    ("bulk_add_drops_table_value", "orc_bulk_merge", "it[m].v = val_at(t, t->cells, i);", "it[m].v = 0;"),
+    ("bulk_no_dedup", "orc_bulk_merge", "if (d > 0 && it[d - 1].k == it[i].k) {", "if (0) {"),
+    ("bulk_never_grows", "orc_bulk_merge", "while (!within_fill(t, old_n + n, 1ull << log2c)) {",
+     "while (0) {"),
+    ("bulk_probe_skips_home", "orc_bulk_merge", "uint64_t i = orc_home(it[j].h, log2c);",
+     "uint64_t i = (orc_home(it[j].h, log2c) + 1) & (cap - 1);"),
 ]
 
 
@@ -72,6 +82,15 @@ def _pins():
         yield lambda layout=layout: TM.test_cleanup_shrinks_to_hand_computed_capacity(layout)
         yield lambda layout=layout: TM.test_cleanup_never_shrinks_below_created_capacity(layout)
         yield lambda layout=layout: TM.test_explicit_shrink_keeps_contents_and_order_free_occupancy(layout, 2)
+        for op in (oracle.ASSIGN, oracle.ADD):
+            for seed in range(3):
+                yield lambda layout=layout, op=op, seed=seed: TB.test_build_matches_dict_model_and_invariants(
+                    layout, op, seed)
+                yield lambda layout=layout, op=op, seed=seed: TB.test_merge_matches_dict_model_with_tombstones(
+                    layout, op, seed)
+        yield lambda layout=layout: TB.test_occupancy_equals_insertion_in_random_order(layout)
+        yield lambda layout=layout: TB.test_hand_worked_wrapping_example(layout)
+        yield lambda layout=layout: TB.test_capacity_rule_and_full_tables(layout)
 
 
 @pytest.mark.parametrize("name,func,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
