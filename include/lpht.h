@@ -137,6 +137,7 @@ typedef struct lpht_stats {
   uint64_t host_syncs;     /* count synchronisations the growth rule needed */
   double migrate_ms;       /* device time of data migrations (when timing is on) */
   uint64_t shrinks;        /* data migrations to a smaller capacity */
+  uint64_t bulk_merges;    /* completed lpht_build / lpht_merge calls */
 } lpht_stats;
 
 typedef struct lpht_table lpht_table; /* opaque; owned by the library */
@@ -201,6 +202,31 @@ int lpht_erase(lpht_table *t, const void *keys, uint64_t n, uint8_t *flags, void
  * elements would not leave an empty cell in the smaller table; the table is
  * unchanged), OOM. */
 int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream);
+
+/* Sort-based bulk build (Sec. 5.5): replaces the table's contents by the n
+ * elements of the batch (keys, and vals or NULL meaning every value is 1).
+ * The elements are ordered by hash value (ties by key, then by index); among
+ * equal keys only the last is kept, with LPHT_ASSIGN carrying its own value
+ * and with LPHT_ADD the wrapping sum of all their values; the result is laid
+ * out as if inserted one by one in that order into an empty table, so the
+ * cells are a function of the set of (key, value) pairs alone.  Capacity:
+ * unchanged for a bounded table; with auto_grow doubled while
+ * n > alpha * capacity (never shrunk).  Reserved keys are skipped and set the
+ * sticky RESERVED_KEY error.  Errors: INVALID (arguments, op), FULL (more
+ * distinct keys than cells; the table and its counts are unchanged, sticky
+ * FULL set), UNSUPPORTED (n + live >= 2^32 or a target above 2^29 cells),
+ * OOM.  Synchronises the stream (the distinct count is read back).  Scratch:
+ * about 2 x (live + n) x (2 x key width + 4) bytes for the call. */
+int lpht_build(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, void *stream);
+
+/* Sort-based batched merge (Sec. 5.5): as lpht_build over the table's live
+ * elements followed by the batch, i.e. the batch applied to the table with
+ * insertOrUpdate semantics in index order (LPHT_ASSIGN: the last occurrence
+ * of a key wins, over the table too; LPHT_ADD: the table's value plus all the
+ * batch's values of that key), tombstones dropped, cells in the canonical
+ * hash order.  Capacity: with auto_grow doubled while live + n > alpha *
+ * capacity.  Errors and synchronisation as lpht_build. */
+int lpht_merge(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, void *stream);
 
 /* Exact counts: `used` non-empty cells (live keys and tombstones), `live`
  * keys.  Synchronises `stream`.  Either pointer may be NULL. */

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lpht_host.h"
+#include "lpht_bulk.h"
 #include "lpht_shrink.h"
 
 using namespace lpht;
@@ -673,6 +674,90 @@ int lpht_update(lpht_table *t, const void *keys, const void *vals, uint64_t n, u
 
 int lpht_erase(lpht_table *t, const void *keys, uint64_t n, uint8_t *flags, void *stream) {
   return run_bulk(t, OP_ERASE, keys, nullptr, n, 0, nullptr, flags, stream);
+}
+
+namespace {
+
+// The sort-based bulk build (keep_old = false) and batched merge (Sec. 5.5):
+// the result replaces the table's cells; the host learns the distinct count
+// from the device (one synchronisation after the launches, one before to
+// know the live elements exactly).
+int bulk_merge(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, bool keep_old,
+               void *stream) {
+  int rc = check_arrays(t, keys, vals, n);
+  if (rc) return rc;
+  if (op > LPHT_ADD) return LPHT_ERR_INVALID;
+  if (n >= (1ull << 32) - 1) return LPHT_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  rc = sync_counts(t, s);
+  if (rc) return rc;
+  const uint64_t old_live = keep_old ? t->known_live : 0;
+  uint32_t log2_new = t->log2c;
+  if (t->cfg.auto_grow)
+    while (!within_fill(t, old_live + n, 1ull << log2_new)) {
+      if (log2_new >= 34) return LPHT_ERR_OOM;
+      ++log2_new;
+    }
+  if (log2_new > kBulkMaxLog2) return LPHT_ERR_UNSUPPORTED;
+  const uint64_t max_items = old_live + n;
+  if (max_items >= (1ull << 32)) return LPHT_ERR_UNSUPPORTED;
+  const uint64_t old_ncells = keep_old ? (1ull << t->log2c) : 0;
+  const size_t nb = (size_t)cell_bytes(t->cfg.layout) << log2_new;
+  const size_t sb = bulk_merge_scratch_bytes(old_ncells + n, max_items, log2_new, t->cfg.layout);
+  void *nc = dev_alloc(t, nb, s);
+  if (!nc) return LPHT_ERR_OOM;
+  void *scratch = dev_alloc(t, sb, s);
+  if (!scratch) {
+    dev_free(t, nc, nb, s);
+    return LPHT_ERR_OOM;
+  }
+  BulkMergeArgs a{};
+  a.layout = t->cfg.layout;
+  a.op = op;
+  a.old_cells = keep_old ? t->cells : nullptr;
+  a.old_ncells = old_ncells;
+  a.keys = keys;
+  a.vals = vals;
+  a.n = n;
+  a.max_items = max_items;
+  a.new_cells = nc;
+  a.log2_new = log2_new;
+  a.crc_hi = t->crc_hi;
+  a.crc_lo = t->crc_lo;
+  a.status = t->status;
+  a.scratch = scratch;
+  a.num_cus = t->launch.num_cus;
+  BulkMergeCtl ctl{};
+  hipError_t e = launch_set_status(t->status, 0, 0, 0, s);
+  if (e == hipSuccess) e = launch_bulk_merge(a, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&ctl, scratch, sizeof(ctl), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(t, scratch, sb, s);
+  if (e != hipSuccess || ctl.full) {
+    dev_free(t, nc, nb, s);
+    // the table is unchanged: restore its counts
+    (void)launch_set_status(t->status, t->known_used, t->known_live, 0, s);
+    return e != hipSuccess ? from_hip(e) : ctl.full == 1 ? LPHT_ERR_FULL : LPHT_ERR_DEVICE;
+  }
+  dev_free(t, t->cells, (size_t)cell_bytes(t->cfg.layout) << t->log2c, s);
+  t->cells = nc;
+  t->log2c = log2_new;
+  t->known_used = t->known_live = ctl.distinct;
+  t->pending = 0;
+  t->mods_since_exact = 0;
+  t->stats.bulk_merges++;
+  return LPHT_OK;
+}
+
+}  // namespace
+
+int lpht_build(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, void *stream) {
+  return bulk_merge(t, keys, vals, n, op, false, stream);
+}
+
+int lpht_merge(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, void *stream) {
+  return bulk_merge(t, keys, vals, n, op, true, stream);
 }
 
 int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream) {

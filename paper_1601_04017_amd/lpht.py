@@ -86,6 +86,7 @@ class lpht_stats(ctypes.Structure):
         ("host_syncs", ctypes.c_uint64),
         ("migrate_ms", ctypes.c_double),
         ("shrinks", ctypes.c_uint64),
+        ("bulk_merges", ctypes.c_uint64),
     ]
 
 
@@ -122,6 +123,8 @@ _SIGS = {
     "lpht_update": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP, _VP]),
     "lpht_erase": (ctypes.c_int, [_VP, _VP, _U64, _VP, _VP]),
     "lpht_grow": (ctypes.c_int, [_VP, _U32, _VP]),
+    "lpht_build": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP]),
+    "lpht_merge": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP]),
     "lpht_count": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
     "lpht_capacity": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U32)]),
     "lpht_cell_bytes": (_U32, [_U32]),
@@ -279,6 +282,16 @@ class Table:
 
     def grow(self, log2_new: int, stream=None):
         _check(load().lpht_grow(self._h, log2_new, _stream_handle(stream)), "lpht_grow")
+
+    def build(self, keys, vals=None, op=ASSIGN, stream=None):
+        """Sort-based bulk build: the table's contents become the batch."""
+        n = self._n(keys)
+        _check(load().lpht_build(self._h, _ptr(keys), _ptr(vals), n, op, _stream_handle(stream)), "lpht_build")
+
+    def merge(self, keys, vals=None, op=ASSIGN, stream=None):
+        """Sort-based batched merge of the batch into the table."""
+        n = self._n(keys)
+        _check(load().lpht_merge(self._h, _ptr(keys), _ptr(vals), n, op, _stream_handle(stream)), "lpht_merge")
 
     def count(self, stream=None):
         u, l = ctypes.c_uint64(), ctypes.c_uint64()
