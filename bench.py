@@ -157,7 +157,7 @@ def _timed(fn, stream):
     return a.elapsed_time(b)
 
 
-SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "deletion", "zipf", "serving")
+SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "deletion", "bulk", "zipf", "serving")
 
 
 def run_suite(dev, reps=3, parts=SUITE_PARTS):
@@ -181,7 +181,7 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
         out["ceilings"] = roofline.measure()
     if "packed32" in parts:
         out["packed32_2e21"] = _suite_packed32(dev, up, stream, reps)
-    need_keys = "fill_sweep" in parts or "growing" in parts or "deletion" in parts
+    need_keys = "fill_sweep" in parts or "growing" in parts or "deletion" in parts or "bulk" in parts
     if need_keys:
         nmax = 201_326_592
         keys = inputs.distinct_keys_u64(nmax, 201)
@@ -195,6 +195,8 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
     if "deletion" in parts:
         out["deletion_window_1e7"] = _suite_deletion(stream, dkeys, dvals)
         out["shrink_2e26"] = _suite_shrink(stream, dkeys, dvals)
+    if "bulk" in parts:
+        out["bulk_build_merge_2e28"] = _suite_bulk(up, stream, reps, dkeys, dvals)
     if need_keys:
         del dkeys, dvals
     if "zipf" in parts:
@@ -439,6 +441,40 @@ def _suite_shrink(stream, dkeys, dvals):
         ms = float(np.mean(res))
         nbytes = (1 << 26) * 16 + (1 << log2_new) * 16
         out[f"to_2e{log2_new}"] = {"ms": round(ms, 4), "algorithmic_gbs": round(nbytes / ms / 1e6, 1)}
+    return out
+
+
+def _suite_bulk(up, stream, reps, dkeys, dvals):
+    import torch
+
+    from paper_1601_04017_amd import inputs, lpht
+
+    # Sort-based bulk build / merge into a 2^28-cell KV64 table: 10^8
+    # distinct keys (the headline insert's workload), 10^8 Zipf(1.0) keys
+    # aggregated with add, and a merge of 10^7 new keys into the 10^8.
+    log("suite: bulk build and merge")
+    out = {}
+    t = new_table(layout=lpht.KV64, log2_capacity=28)
+    res = [_timed(lambda: t.build(dkeys[:N_OPS], dvals[:N_OPS]), stream) for _ in range(reps + 1)][1:]
+    assert t.count() == (N_OPS, N_OPS)
+    out["build_1e8_distinct_ms"] = round(float(np.mean(res)), 3)
+    out["build_1e8_distinct_mops"] = round(N_OPS / np.mean(res) / 1e3, 1)
+    m = 10 ** 7
+    res = []
+    for r in range(reps + 1):
+        t.build(dkeys[:N_OPS], dvals[:N_OPS])
+        torch.cuda.synchronize()
+        tm = _timed(lambda: t.merge(dkeys[N_OPS:N_OPS + m], dvals[N_OPS:N_OPS + m]), stream)
+        if r:
+            res.append(tm)
+    assert t.count() == (N_OPS + m, N_OPS + m)
+    out["merge_1e7_into_1e8_ms"] = round(float(np.mean(res)), 3)
+    z = up(inputs.zipf_keys_u64(N_OPS, ZIPF_N, ZIPF_S, seed=404))
+    res = [_timed(lambda: t.build(z, None, op=lpht.ADD), stream) for _ in range(reps + 1)][1:]
+    out["build_zipf1_add_1e8_ms"] = round(float(np.mean(res)), 3)
+    out["build_zipf1_add_distinct"] = int(t.count()[1])
+    t.close()
+    del z
     return out
 
 

@@ -39,7 +39,9 @@ struct BulkMergeCtl {
   unsigned int full;            // 1: more distinct keys than cells; 2: more elements than the
                                 // staging holds (inconsistent counts); nothing was written
   unsigned int big_blocks;      // target blocks sorted by the global-memory path
-  unsigned long long pad[5];
+  unsigned int mid_blocks;      // target blocks sorted by a whole workgroup
+  unsigned int pad0;
+  unsigned long long pad[4];
 };
 
 // Scratch for `inputs` = old_ncells + n input positions of which at most

@@ -16,15 +16,17 @@
 // The target table is cut into blocks of B = 256 cells.  Steps:
 //   A. partition by the top l1 bits of the block index (<= 1024 bins): each
 //      workgroup counts its contiguous share of the input per bin
-//      (k_bm_count), one scan gives every (bin, workgroup) pair its own output
-//      range (k_bm_scan_matrix), and each workgroup writes its share in tiles
-//      of 1024 elements, equal keys of a tile combined in an LDS hash table
-//      (k_bm_scatter) -- no global atomics;
+//      (k_bm_count), scans give every (bin, workgroup) pair its own output
+//      range (k_bm_scan_rows, k_bm_scan_bins), and each workgroup writes its
+//      share in tiles of 1024 elements, equal keys of a tile combined in an
+//      LDS hash table (k_bm_scatter), the entries freed by combining marked
+//      with the empty key -- no global atomics;
 //   B. one workgroup per first-level bin partitions its elements by the
 //      remaining l2 bits into blocks (k_bm_partition), combining equal keys
 //      again per chunk of 1024 elements, so a hot key reaches its block at
 //      most once per chunk;
-//   C. one workgroup per block sorts the block's elements in LDS (bitonic,
+//   C. one wavefront per block sorts the block's elements in LDS (bitonic,
+//      k_bm_block_wave; a workgroup for blocks of more than 256 elements,
 //      k_bm_block), removes equal keys and computes the block's carry
 //      function: the number of elements that run past the block's end is
 //      f(c) = max(a, c + m - B) when c elements run in from the left, with m
@@ -62,7 +64,8 @@ constexpr uint32_t kSlots = 2048;   // LDS combining table slots (>= 2 x element
 constexpr uint32_t kL1Max = 1024;
 constexpr uint32_t kL2Max = 2048;
 constexpr uint32_t kGAMax = 1024;
-constexpr uint32_t kEMax = 1024;    // elements a block keeps in LDS in stage C
+constexpr uint32_t kEW = 256;       // elements a wavefront sorts in LDS in stage C
+constexpr uint32_t kEMax = 1024;    // elements a workgroup sorts in LDS in stage C
 constexpr uint32_t kScanPer = 16;   // blocks per thread in stage D
 constexpr uint32_t kScanTile = 256 * kScanPer;
 
@@ -86,7 +89,7 @@ struct BmK {
   uint32_t *seqA;
   void *keyB, *valB;
   uint32_t *seqB;
-  uint32_t *mcnt, *moff, *l1_off, *blk_off, *blk_cnt, *big_list;
+  uint32_t *mcnt, *moff, *l1_off, *blk_off, *blk_cnt, *big_list, *mid_list;
   long long *car_a, *car_d, *cin, *tile_a, *tile_d;
 };
 
@@ -268,21 +271,38 @@ __global__ void __launch_bounds__(256) k_bm_count(BmK k) {
   if (threadIdx.x == 0 && s_err) atomicOr(&k.st->err, s_err);
 }
 
-// One workgroup of 1024 threads: exclusive scan of the (bin, workgroup)
-// counts in bin-major order.
-__global__ void __launch_bounds__(1024) k_bm_scan_matrix(BmK k) {
+// One workgroup per bin: exclusive scan of the bin's per-workgroup counts
+// (offsets inside the bin) and the bin's total.
+__global__ void __launch_bounds__(256) k_bm_scan_rows(BmK k) {
   __shared__ uint32_t sw[17];
-  const u64 E = (u64)k.L1 * k.GA;
-  const u64 ch = (E + blockDim.x - 1) / blockDim.x;
-  const u64 lo = std::min<u64>(E, threadIdx.x * ch), hi = std::min<u64>(E, lo + ch);
+  const uint32_t b = blockIdx.x;
+  const uint32_t per = (k.GA + blockDim.x - 1) / blockDim.x;
+  const uint32_t w0 = std::min(k.GA, threadIdx.x * per), w1 = std::min(k.GA, w0 + per);
+  const u64 row = (u64)b * k.GA;
   uint32_t sum = 0;
-  for (u64 i = lo; i < hi; ++i) sum += k.mcnt[i];
+  for (uint32_t w = w0; w < w1; ++w) sum += k.mcnt[row + w];
   uint32_t total;
   uint32_t acc = block_excl_scan(sum, &total, sw);
-  for (u64 i = lo; i < hi; ++i) {
-    k.moff[i] = acc;
-    if (i % k.GA == 0) k.l1_off[i / k.GA] = acc;
-    acc += k.mcnt[i];
+  for (uint32_t w = w0; w < w1; ++w) {
+    k.moff[row + w] = acc;
+    acc += k.mcnt[row + w];
+  }
+  if (threadIdx.x == 0) k.l1_off[b] = total;  // the bin's size; turned into its offset next
+}
+
+// One workgroup of 1024 threads: exclusive scan of the bin sizes.
+__global__ void __launch_bounds__(1024) k_bm_scan_bins(BmK k) {
+  __shared__ uint32_t sw[17];
+  const uint32_t per = (k.L1 + blockDim.x - 1) / blockDim.x;
+  const uint32_t b0 = std::min(k.L1, threadIdx.x * per), b1 = std::min(k.L1, b0 + per);
+  uint32_t sum = 0;
+  for (uint32_t b = b0; b < b1; ++b) sum += k.l1_off[b];
+  uint32_t total;
+  uint32_t acc = block_excl_scan(sum, &total, sw);
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint32_t t = k.l1_off[b];
+    k.l1_off[b] = acc;
+    acc += t;
   }
   if (threadIdx.x == 0) {
     k.l1_off[k.L1] = total;
@@ -304,7 +324,7 @@ __global__ void __launch_bounds__(256) k_bm_scatter(BmK k) {
   if (k.ctl->full) return;
   crc_tables_build(T);
   const uint32_t w = blockIdx.x;
-  for (uint32_t i = threadIdx.x; i < k.L1; i += blockDim.x) cur[i] = k.moff[(u64)i * k.GA + w];
+  for (uint32_t i = threadIdx.x; i < k.L1; i += blockDim.x) cur[i] = k.l1_off[i] + k.moff[(u64)i * k.GA + w];
   const u64 lo = (u64)w * k.per;
   const u64 hi = std::min<u64>(lo + k.per, k.ntot);
   KT<L> *keyA = (KT<L> *)k.keyA;
@@ -385,10 +405,12 @@ __global__ void __launch_bounds__(256) k_bm_scatter(BmK k) {
     for (uint32_t b = threadIdx.x; b < k.L1; b += blockDim.x) cur[b] += toff[b + 1] - toff[b];
     __syncthreads();
   }
-  // valid elements of each (bin, workgroup) range
+  // the entries of each (bin, workgroup) range left free by combined
+  // duplicates get the empty key, which stage B skips
   for (uint32_t i = threadIdx.x; i < k.L1; i += blockDim.x) {
     const u64 m = (u64)i * k.GA + w;
-    k.mcnt[m] = cur[i] - k.moff[m];
+    const u64 end = (u64)k.l1_off[i] + k.moff[m] + k.mcnt[m];
+    for (u64 p = cur[i]; p < end; ++p) keyA[p] = 0;
   }
   if (err) atomicOr(&k.st->err, err);
 }
@@ -399,7 +421,6 @@ __global__ void __launch_bounds__(256) k_bm_scatter(BmK k) {
 template <int L>
 __global__ void __launch_bounds__(1024) k_bm_partition(BmK k) {
   __shared__ uint32_t T[8][256];
-  __shared__ uint32_t pre[kGAMax + 1];
   __shared__ uint32_t hist[kL2Max];
   __shared__ Combine<L> cb;
   __shared__ uint32_t sw[17];
@@ -408,40 +429,19 @@ __global__ void __launch_bounds__(1024) k_bm_partition(BmK k) {
   const uint32_t s = blockIdx.x;
   const uint32_t nl2 = 1u << k.l2_bits;
   const uint32_t mask2 = nl2 - 1;
-  // prefix over the workgroups' valid counts of this bin
-  {
-    const uint32_t per = (k.GA + blockDim.x - 1) / blockDim.x;
-    const uint32_t w0 = std::min(k.GA, threadIdx.x * per), w1 = std::min(k.GA, w0 + per);
-    uint32_t sum = 0;
-    for (uint32_t w = w0; w < w1; ++w) sum += k.mcnt[(u64)s * k.GA + w];
-    uint32_t tot;
-    uint32_t acc = block_excl_scan(sum, &tot, sw);
-    for (uint32_t w = w0; w < w1; ++w) {
-      pre[w] = acc;
-      acc += k.mcnt[(u64)s * k.GA + w];
-    }
-    if (threadIdx.x == 0) pre[k.GA] = tot;
-  }
   for (uint32_t i = threadIdx.x; i < nl2; i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  const uint32_t total = pre[k.GA];
+  // the bin's stage-A range; entries with the empty key are holes
   const u64 out0 = k.l1_off[s];
+  const uint32_t total = k.l1_off[s + 1] - k.l1_off[s];
   const KT<L> *keyA = (const KT<L> *)k.keyA;
   const KT<L> *valA = (const KT<L> *)k.valA;
   KT<L> *keyB = (KT<L> *)k.keyB;
   KT<L> *valB = (KT<L> *)k.valB;
-  // index of the j-th element of this bin in the stage-A output
-  auto at = [&](uint32_t j) -> u64 {
-    uint32_t lo = 0, hi = k.GA;  // largest w with pre[w] <= j
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (pre[mid] <= j) lo = mid; else hi = mid;
-    }
-    return (u64)k.moff[(u64)s * k.GA + lo] + (j - pre[lo]);
-  };
   for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) {
-    const uint32_t u = sort_hash<L>(T, keyA[at(j)], k.crc_hi);
-    atomicAdd(&hist[top_bits(u, k.nb_bits) & mask2], 1u);
+    const KT<L> key = keyA[out0 + j];
+    if (key == 0) continue;
+    atomicAdd(&hist[top_bits(sort_hash<L>(T, key, k.crc_hi), k.nb_bits) & mask2], 1u);
   }
   __syncthreads();
   // block regions inside the bin's output range, sized by the raw counts
@@ -466,14 +466,13 @@ __global__ void __launch_bounds__(1024) k_bm_partition(BmK k) {
     combine_clear<L>(cb);
     __syncthreads();
     const uint32_t j = chunk + threadIdx.x;
-    const bool ok = j < total;
-    KT<L> key = 0, val = 0;
+    KT<L> key = j < total ? keyA[out0 + j] : (KT<L>)0;
+    const bool ok = key != 0;
+    KT<L> val = 0;
     uint32_t seq = 0, p = 0;
     if (ok) {
-      const u64 e = at(j);
-      key = keyA[e];
-      val = valA[e];
-      seq = k.seqA[e];
+      val = valA[out0 + j];
+      seq = k.seqA[out0 + j];
       p = combine_claim<L>(cb, key, sort_hash<L>(T, key, k.crc_hi));
     }
     __syncthreads();
@@ -546,6 +545,134 @@ __device__ void lds_bitonic(BlockLds<L> &b, uint32_t cnt) {
   }
 }
 
+// Per-wavefront LDS of the common case: a block of at most kEW elements.
+template <int L>
+struct WaveLds {
+  KT<L> key[kEW];
+  KT<L> val[kEW];
+  uint32_t seq[kEW];
+  uint32_t u[kEW];
+  uint16_t ix[kEW];
+};
+
+template <int L>
+__device__ __forceinline__ bool witem_less(const WaveLds<L> &b, uint32_t x, uint32_t y) {
+  if (b.u[x] != b.u[y]) return b.u[x] < b.u[y];
+  if (b.key[x] != b.key[y]) return b.key[x] < b.key[y];
+  return b.seq[x] < b.seq[y];
+}
+
+__device__ __forceinline__ long long wave_max(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const long long t = __shfl_xor(v, o, 64);
+    v = v > t ? v : t;
+  }
+  return v;
+}
+
+// One wavefront per block (4 per workgroup, no workgroup barrier after the
+// CRC tables): the block's elements are sorted by a bitonic network in the
+// wavefront's LDS, equal keys reduced to their run end, and the carry map
+// computed.  Larger blocks are listed for the workgroup and global paths.
+template <int L>
+__global__ void __launch_bounds__(256) k_bm_block_wave(BmK k) {
+  __shared__ uint32_t T[8][256];
+  __shared__ WaveLds<L> wl[4];
+  if (k.ctl->full) return;
+  crc_tables_build(T);
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  WaveLds<L> &b = wl[wv];
+  KT<L> *keyB = (KT<L> *)k.keyB;
+  KT<L> *valB = (KT<L> *)k.valB;
+  const uint32_t B = 1u << k.log2b;
+  for (u64 blk = (u64)blockIdx.x * 4 + wv; blk < k.nblocks; blk += (u64)gridDim.x * 4) {
+    const uint32_t off = k.blk_off[blk], cnt = k.blk_cnt[blk];
+    if (cnt > kEW) {
+      if (lane == 0) {
+        if (cnt > kEMax)
+          k.big_list[atomicAdd(&k.ctl->big_blocks, 1u)] = (uint32_t)blk;
+        else
+          k.mid_list[atomicAdd(&k.ctl->mid_blocks, 1u)] = (uint32_t)blk;
+      }
+      continue;
+    }
+    for (uint32_t i = lane; i < cnt; i += 64) {
+      b.key[i] = keyB[(u64)off + i];
+      b.val[i] = valB[(u64)off + i];
+      b.seq[i] = k.seqB[(u64)off + i];
+      b.u[i] = sort_hash<L>(T, b.key[i], k.crc_hi);
+      b.ix[i] = (uint16_t)i;
+    }
+    wave_sync();
+    uint32_t P = 1;
+    while (P < cnt) P <<= 1;
+    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+      for (uint32_t t = lane; t < P / 2; t += 64) {
+        const uint32_t half = kk >> 1, bl = t / half, r = t % half;
+        const uint32_t i = bl * kk + r, j = bl * kk + kk - 1 - r;
+        if (j < cnt && witem_less<L>(b, b.ix[j], b.ix[i])) {
+          const uint16_t x = b.ix[i];
+          b.ix[i] = b.ix[j];
+          b.ix[j] = x;
+        }
+      }
+      wave_sync();
+      for (uint32_t jj = kk >> 2; jj >= 1; jj >>= 1) {
+        for (uint32_t t = lane; t < P / 2; t += 64) {
+          const uint32_t i = 2 * jj * (t / jj) + (t % jj), j = i + jj;
+          if (j < cnt && witem_less<L>(b, b.ix[j], b.ix[i])) {
+            const uint16_t x = b.ix[i];
+            b.ix[i] = b.ix[j];
+            b.ix[j] = x;
+          }
+        }
+        wave_sync();
+      }
+    }
+    // run ends of equal keys are kept; 4 consecutive sorted positions per lane
+    uint32_t keep = 0;
+    KT<L> kv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t r = lane * 4 + q;
+      if (r < cnt && (r + 1 == cnt || b.key[b.ix[r + 1]] != b.key[b.ix[r]])) {
+        keep |= 1u << q;
+        KT<L> v = b.val[b.ix[r]];
+        if (k.op == 1)
+          for (uint32_t r2 = r; r2 > 0 && b.key[b.ix[r2 - 1]] == b.key[b.ix[r]]; --r2) v += b.val[b.ix[r2 - 1]];
+        kv[q] = v;
+      }
+    }
+    const uint32_t mine = (uint32_t)__popc(keep);
+    const uint32_t incl = wave_incl_scan(mine);
+    const uint32_t m = __shfl(incl, 63, 64);
+    uint32_t rank = incl - mine;
+    long long qmax = LLONG_MIN;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!(keep >> q & 1u)) continue;
+      const uint32_t x = b.ix[lane * 4 + q];
+      const long long qq = (long long)top_bits(b.u[x], k.log2c) - (long long)rank;
+      qmax = qmax > qq ? qmax : qq;
+      keyB[(u64)off + rank] = b.key[x];
+      valB[(u64)off + rank] = kv[q];
+      k.seqB[(u64)off + rank] = b.u[x];  // the hash, for the placement
+      ++rank;
+    }
+    const long long mx = wave_max(qmax);
+    if (lane == 0) {
+      k.blk_cnt[blk] = m;
+      const long long s0 = (long long)(blk << k.log2b);
+      const long long a = m ? (long long)m + mx - s0 - (long long)B : 0;
+      k.car_a[blk] = a > 0 ? a : 0;
+      k.car_d[blk] = (long long)m - (long long)B;
+    }
+    wave_sync();
+  }
+}
+
+// Blocks of kEW < elements <= kEMax: one workgroup each, from the list.
 template <int L>
 __global__ void __launch_bounds__(256) k_bm_block(BmK k) {
   __shared__ uint32_t T[8][256];
@@ -557,12 +684,10 @@ __global__ void __launch_bounds__(256) k_bm_block(BmK k) {
   KT<L> *keyB = (KT<L> *)k.keyB;
   KT<L> *valB = (KT<L> *)k.valB;
   const uint32_t B = 1u << k.log2b;
-  for (u64 blk = blockIdx.x; blk < k.nblocks; blk += gridDim.x) {
+  const uint32_t nmid = k.ctl->mid_blocks;
+  for (uint32_t mi = blockIdx.x; mi < nmid; mi += gridDim.x) {
+    const u64 blk = k.mid_list[mi];
     const uint32_t off = k.blk_off[blk], cnt = k.blk_cnt[blk];
-    if (cnt > kEMax) {
-      if (threadIdx.x == 0) k.big_list[atomicAdd(&k.ctl->big_blocks, 1u)] = (uint32_t)blk;
-      continue;
-    }
     for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
       b.key[i] = keyB[(u64)off + i];
       b.val[i] = valB[(u64)off + i];
@@ -844,71 +969,70 @@ __global__ void __launch_bounds__(256) k_bm_scan_down(BmK k) {
 // ------------------------------------------------------------- stage E
 
 template <int L>
+__device__ __forceinline__ void put_cell(void *cells, u64 p, KT<L> key, KT<L> val) {
+  if (L == 0) {
+    ((u64 *)cells)[p] = (u64)key | ((u64)val << 32);
+  } else {
+    u64x2 w;
+    w.x = (u64)key;
+    w.y = (u64)val;
+    ((u64x2 *)cells)[p] = w;
+  }
+}
+
+// One wavefront per block: element r of the block (in order) goes to
+// p = r + max(s + c_in, max_{l<=r}(pos_l - l)); cells of the block itself
+// go through an LDS image written once from cell s + min(c_in, B) on.
+template <int L>
 __global__ void __launch_bounds__(256) k_bm_place(BmK k) {
-  __shared__ KT<L> ik[256];
-  __shared__ KT<L> iv[256];
-  __shared__ long long sm[17];
-  __shared__ long long carry_mx;
+  __shared__ KT<L> ik[4][256];
+  __shared__ KT<L> iv[4][256];
   if (k.ctl->full) return;
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const KT<L> *keyB = (const KT<L> *)k.keyB;
   const KT<L> *valB = (const KT<L> *)k.valB;
   KT<L> *wk = (KT<L> *)k.keyA;
-  KT<L> *wv = (KT<L> *)k.valA;
+  KT<L> *wvv = (KT<L> *)k.valA;
   const uint32_t B = 1u << k.log2b;
-  for (u64 blk = blockIdx.x; blk < k.nblocks; blk += gridDim.x) {
+  for (u64 blk = (u64)blockIdx.x * 4 + wv; blk < k.nblocks; blk += (u64)gridDim.x * 4) {
     const u64 s0 = blk << k.log2b;
     const long long cin = k.cin[blk];
     const uint32_t off = k.blk_off[blk], m = k.blk_cnt[blk];
-    for (uint32_t i = threadIdx.x; i < B; i += blockDim.x) {
-      ik[i] = 0;
-      iv[i] = 0;
+    for (uint32_t i = lane; i < B; i += 64) {
+      ik[wv][i] = 0;
+      iv[wv][i] = 0;
     }
-    if (threadIdx.x == 0) carry_mx = LLONG_MIN;
-    __syncthreads();
-    for (uint32_t c0 = 0; c0 < m; c0 += blockDim.x) {
-      const uint32_t r = c0 + threadIdx.x;
-      long long q = LLONG_MIN;
-      if (r < m) q = (long long)top_bits(k.seqB[(u64)off + r], k.log2c) - (long long)r;
-      long long tot;
-      long long mx = block_incl_max(q, &tot, sm);
+    wave_sync();
+    const long long start = (long long)s0 + cin;
+    long long carry_mx = LLONG_MIN;
+    for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+      const uint32_t r = c0 + lane;
+      long long mx = r < m ? (long long)top_bits(k.seqB[(u64)off + r], k.log2c) - (long long)r : LLONG_MIN;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const long long t = __shfl_up(mx, o, 64);
+        if (lane >= (uint32_t)o) mx = mx > t ? mx : t;
+      }
       mx = mx > carry_mx ? mx : carry_mx;
       if (r < m) {
-        const long long start = (long long)s0 + cin;
         const long long p = (long long)r + (mx > start ? mx : start);
         const KT<L> key = keyB[(u64)off + r], val = valB[(u64)off + r];
         if (p < (long long)(s0 + B)) {
-          ik[p - (long long)s0] = key;
-          iv[p - (long long)s0] = val;
+          ik[wv][p - (long long)s0] = key;
+          iv[wv][p - (long long)s0] = val;
         } else if (p < (long long)k.c) {  // an element that runs into a later block
-          if (L == 0) {
-            ((u64 *)k.cells)[p] = (u64)key | ((u64)val << 32);
-          } else {
-            u64x2 w;
-            w.x = (u64)key;
-            w.y = (u64)val;
-            ((u64x2 *)k.cells)[p] = w;
-          }
+          put_cell<L>(k.cells, (u64)p, key, val);
         } else if (p - (long long)k.c < (long long)k.cap_items) {  // wrapped: listed in order
           wk[p - (long long)k.c] = key;
-          wv[p - (long long)k.c] = val;
+          wvv[p - (long long)k.c] = val;
         }
       }
-      __syncthreads();
-      if (threadIdx.x == 0) carry_mx = tot > carry_mx ? tot : carry_mx;
-      __syncthreads();
+      carry_mx = __shfl(mx, 63, 64);
     }
+    wave_sync();
     const uint32_t first = cin < (long long)B ? (uint32_t)cin : B;
-    for (uint32_t i = first + threadIdx.x; i < B; i += blockDim.x) {
-      if (L == 0) {
-        ((u64 *)k.cells)[s0 + i] = (u64)ik[i] | ((u64)iv[i] << 32);
-      } else {
-        u64x2 w;
-        w.x = (u64)ik[i];
-        w.y = (u64)iv[i];
-        ((u64x2 *)k.cells)[s0 + i] = w;
-      }
-    }
-    __syncthreads();
+    for (uint32_t i = first + lane; i < B; i += 64) put_cell<L>(k.cells, s0 + i, ik[wv][i], iv[wv][i]);
+    wave_sync();
   }
 }
 
@@ -993,6 +1117,7 @@ void carve_all(Carve &cv, uint64_t N, const Geometry &g, uint32_t layout, BmK &k
   cv.take(k.blk_off, g.nblocks * 4);
   cv.take(k.blk_cnt, g.nblocks * 4);
   cv.take(k.big_list, g.nblocks * 4);
+  cv.take(k.mid_list, g.nblocks * 4);
   cv.take(k.car_a, g.nblocks * 8);
   cv.take(k.car_d, g.nblocks * 8);
   cv.take(k.cin, g.nblocks * 8);
@@ -1050,8 +1175,9 @@ hipError_t launch_bulk_merge(const BulkMergeArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_bm_init, dim3(1), dim3(64), 0, s, k.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const uint32_t wide = std::max<uint32_t>(1, a.num_cus) * 8;
-  const uint32_t gblk = (uint32_t)std::min<uint64_t>(g.nblocks, wide);
+  // one wavefront per block, grid-stride over the blocks
+  const uint32_t gwave =
+      (uint32_t)std::min<uint64_t>((g.nblocks + 3) / 4, (uint64_t)std::max<uint32_t>(1, a.num_cus) * 16);
 #define LPHT_BM(KERN, GRID, THREADS)                                                   \
   do {                                                                                 \
     if (a.layout == 0)                                                                 \
@@ -1061,11 +1187,14 @@ hipError_t launch_bulk_merge(const BulkMergeArgs &a, hipStream_t s) {
     if ((e = hipGetLastError()) != hipSuccess) return e;                               \
   } while (0)
   LPHT_BM(k_bm_count, g.GA, 256);
-  hipLaunchKernelGGL(k_bm_scan_matrix, dim3(1), dim3(1024), 0, s, k);
+  hipLaunchKernelGGL(k_bm_scan_rows, dim3(g.L1), dim3(256), 0, s, k);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bm_scan_bins, dim3(1), dim3(1024), 0, s, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   LPHT_BM(k_bm_scatter, g.GA, 256);
   LPHT_BM(k_bm_partition, g.L1, 1024);
-  LPHT_BM(k_bm_block, gblk, 256);
+  LPHT_BM(k_bm_block_wave, gwave, 256);
+  LPHT_BM(k_bm_block, 256, 256);
   LPHT_BM(k_bm_big_block, 64, 256);
   hipLaunchKernelGGL(k_bm_scan_reduce, dim3((uint32_t)g.ntiles), dim3(256), 0, s, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1073,7 +1202,7 @@ hipError_t launch_bulk_merge(const BulkMergeArgs &a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bm_scan_down, dim3((uint32_t)g.ntiles), dim3(256), 0, s, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  LPHT_BM(k_bm_place, gblk, 256);
+  LPHT_BM(k_bm_place, gwave, 256);
   LPHT_BM(k_bm_wrap, 1, 256);
 #undef LPHT_BM
   return hipSuccess;

@@ -147,11 +147,13 @@ def test_wrapping_and_full_tables(layout):
 
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("op", OPS)
-def test_oversized_blocks_sorted_in_global_memory(layout, op):
-    # 3000 distinct keys homed in one 256-cell block (more than a block sorts
-    # in LDS), each three times in scattered order, plus background keys
+@pytest.mark.parametrize("nhot", [600, 3000])
+def test_large_blocks_sorted_by_workgroup_or_global_memory(layout, op, nhot):
+    # nhot distinct keys homed in one 256-cell block (600: more than a
+    # wavefront sorts, 3000: more than a workgroup sorts in LDS), each three
+    # times in scattered order, plus background keys
     log2c = 16
-    hot = _homed(layout, log2c, 256 * 7, 256 * 8, 3000)
+    hot = _homed(layout, log2c, 256 * 7, 256 * 8, nhot)
     keys = np.concatenate([hot, hot, hot, _keys(layout, 5000, 31)])
     keys = keys[inputs.permutation(keys.size, 32)]
     vals = _vals(layout, keys.size, 33)
