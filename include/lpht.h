@@ -138,6 +138,7 @@ typedef struct lpht_stats {
   double migrate_ms;       /* device time of data migrations (when timing is on) */
   uint64_t shrinks;        /* data migrations to a smaller capacity */
   uint64_t bulk_merges;    /* completed lpht_build / lpht_merge calls */
+  uint64_t async_growths;  /* migrations made inside lpht_insert_async kernels */
 } lpht_stats;
 
 typedef struct lpht_table lpht_table; /* opaque; owned by the library */
@@ -202,6 +203,29 @@ int lpht_erase(lpht_table *t, const void *keys, uint64_t n, uint8_t *flags, void
  * elements would not leave an empty cell in the smaller table; the table is
  * unchanged), OOM. */
 int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream);
+
+/* Insertion that grows the table while the kernel runs (Sec. 5.3.2, the
+ * (semi-)synchronized protocol, with the approximate size of Sec. 5.2): one
+ * cooperative launch inserts the n keys (add = 0: insert, the first of equal
+ * keys wins, flag 1 for the operation that inserted the key, 0 when present;
+ * add = 1: insert-or-add, the value gets the sum of all values (vals NULL: 1
+ * each), exact).  Wavefronts keep local counts of successful insertions and
+ * add them to a global counter after a random number (1..64) of them; when
+ * that counter reaches alpha * capacity all wavefronts stop taking work,
+ * migrate the table together into one of twice the size, and go on.  The
+ * capacity therefore follows the number of distinct keys actually inserted,
+ * not the batch length (insert-or-add over repeated keys needs far fewer
+ * cells than pre-growth by n would reserve).  The host first grows the table,
+ * if needed, to a minimum that leaves room for the work in flight
+ * (device-dependent, about 2^21 cells) and below alpha * capacity, and
+ * reserves tables of 2, 4, ... times the capacity up to the one that holds
+ * used + n (unused ones are released afterwards).  Counts are exact after
+ * the call.  Reserved keys get flag LPHT_FLAG_RESERVED.  Synchronises the
+ * stream.  Errors: INVALID, UNSUPPORTED (no cooperative launch, alpha = 1, or
+ * more than 16 doublings), OOM, DEVICE (a wait inside the kernel exceeded its
+ * two-second bound). */
+int lpht_insert_async(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t add,
+                      uint8_t *flags, void *stream);
 
 /* Sort-based bulk build (Sec. 5.5): replaces the table's contents by the n
  * elements of the batch (keys, and vals or NULL meaning every value is 1).

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lpht_host.h"
+#include "lpht_async.h"
 #include "lpht_bulk.h"
 #include "lpht_shrink.h"
 
@@ -758,6 +759,98 @@ int lpht_build(lpht_table *t, const void *keys, const void *vals, uint64_t n, ui
 
 int lpht_merge(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, void *stream) {
   return bulk_merge(t, keys, vals, n, op, true, stream);
+}
+
+int lpht_insert_async(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t add,
+                      uint8_t *flags, void *stream) {
+  int rc = check_arrays(t, keys, vals, n);
+  if (rc) return rc;
+  if (add > 1) return LPHT_ERR_INVALID;
+  if (n == 0) return LPHT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  const uint32_t grid = async_grid(t->device);
+  if (!grid || t->cfg.max_fill_den - t->cfg.max_fill_num < 1) return LPHT_ERR_UNSUPPORTED;
+  rc = sync_counts(t, s);
+  if (rc) return rc;
+  // the kernel needs room for the work in flight, and starts below the trigger
+  uint32_t lg = std::max(t->log2c, async_min_log2(grid, t->cfg.max_fill_num, t->cfg.max_fill_den));
+  while (!within_fill(t, t->known_used, 1ull << lg)) ++lg;
+  if (lg > 34) return LPHT_ERR_OOM;
+  if (lg != t->log2c) {
+    rc = migrate_once(t, lg, s);
+    if (rc) return rc;
+  }
+  // the ladder of doubled tables, up to the capacity that holds used + n
+  uint32_t K = 0;
+  while (!within_fill(t, t->known_used + n, 1ull << (t->log2c + K))) ++K;
+  if (K > kAsyncLadder || t->log2c + K > 34) return LPHT_ERR_UNSUPPORTED;
+  AsyncArgs a{};
+  a.layout = t->cfg.layout;
+  a.add = add;
+  a.keys = keys;
+  a.vals = vals;
+  a.n = n;
+  a.flags = flags;
+  a.ladder[0] = t->cells;
+  a.nladder = K + 1;
+  a.log2c = t->log2c;
+  a.used0 = t->known_used;
+  a.alpha_num = t->cfg.max_fill_num;
+  a.alpha_den = t->cfg.max_fill_den;
+  a.crc_hi = t->crc_hi;
+  a.crc_lo = t->crc_lo;
+  a.status = t->status;
+  a.grid = grid;
+  const size_t cb = cell_bytes(t->cfg.layout);
+  auto release = [&](uint32_t keep) {
+    for (uint32_t i = 1; i <= K; ++i)
+      if (i != keep && a.ladder[i]) dev_free(t, a.ladder[i], cb << (t->log2c + i), s);
+  };
+  for (uint32_t i = 1; i <= K; ++i) {
+    a.ladder[i] = dev_alloc(t, cb << (t->log2c + i), s);
+    if (!a.ladder[i]) {
+      release(0);
+      return LPHT_ERR_OOM;
+    }
+  }
+  AsyncCtl *ctl = (AsyncCtl *)dev_alloc(t, sizeof(AsyncCtl), s);
+  if (!ctl) {
+    release(0);
+    return LPHT_ERR_OOM;
+  }
+  a.ctl = ctl;
+  AsyncCtl h{};
+  hipError_t e = launch_async_insert(a, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(t, ctl, sizeof(AsyncCtl), s);
+  if (e != hipSuccess) {
+    release(0);
+    return from_hip(e);
+  }
+  const uint32_t fin = h.epoch;
+  if (fin > K) {
+    release(0);
+    return LPHT_ERR_DEVICE;
+  }
+  release(fin);
+  if (fin > 0) {
+    dev_free(t, t->cells, cb << t->log2c, s);
+    t->stats.migrations += fin;
+    t->stats.resizes += fin;
+    for (uint32_t i = 0; i < fin; ++i) t->stats.cells_migrated += 1ull << (t->log2c + i);
+    t->cells = a.ladder[fin];
+    t->log2c += fin;
+  }
+  t->stats.async_growths += fin;
+  // exact counts of the result
+  e = launch_set_status(t->status, 0, 0, 0, s);
+  if (e == hipSuccess) e = launch_recount(t->cells, t->log2c, t->cfg.layout, t->status, t->launch, s);
+  if (e != hipSuccess) return from_hip(e);
+  rc = sync_counts(t, s);
+  if (rc) return rc;
+  return (h.err & 3) ? LPHT_ERR_DEVICE : LPHT_OK;
 }
 
 int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream) {

@@ -1,0 +1,391 @@
+// Inserting kernel that grows the table while it runs (Sec. 5.3.2, "Hiding
+// the Migration from the Underlying Application", with the (semi-)synchronized
+// protocol and the approximate size of Sec. 5.2).
+//
+// One cooperative launch (every workgroup resident) processes a batch of
+// insertions (or insert-or-add operations).  Wavefronts take chunks of 64
+// operations from a shared counter, one operation per lane (linear probing
+// with compare-and-swap, Alg. 1).  Each wavefront counts its successful
+// insertions locally and adds the count to the global counter I after a
+// randomised number (1..64) of them; when the addition makes I reach
+// alpha * c, it raises the growing flag.
+//
+// The protocol of the synchronized variant: a wavefront looks at the flag
+// before taking each chunk (its "busy" period is one chunk); when it is
+// raised the wavefront drops its local count and arrives at the growth.  Once
+// every wavefront has arrived nobody touches the old table, and all of them
+// migrate it together (the dedicated helpers are the kernel's own
+// wavefronts): they clear the target table of twice the size, then walk the
+// old table's clusters in parallel, each cluster in order by one lane, into
+// disjoint target ranges (Lemma 1).  The last to finish publishes the new
+// table version, with I = the number of moved elements, and clears the flag.
+//
+// The growing flag and the version share one word, gen = 2 * epoch + flag,
+// so a wavefront can never confuse a finished growth with a pending one.
+// Every wait is bounded by the device's constant-rate clock; passing the
+// bound sets an error and ends the wavefront (the others then time out too).
+//
+// Table cells are read with device-coherent loads and written with
+// device-coherent stores or atomics, since different wavefronts write the
+// target table and read it afterwards within the same launch.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "lpht_async.h"
+#include "lpht_device.h"
+
+namespace lpht {
+
+namespace {
+
+constexpr uint32_t kZeroBlock = 1u << 16;  // target cells per zero-fill work item
+constexpr uint8_t kFlagReserved = 0xFE;
+constexpr uint8_t kFlagFull = 0xFF;
+
+__device__ __forceinline__ uint32_t ld32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 ld64(const u64 *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st64(u64 *p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The key word of cell i (PACKED32: the whole cell word, key in the low half).
+template <int L>
+__device__ __forceinline__ u64 key_at(const void *cells, u64 i) {
+  const u64 w = ld64((const u64 *)cells + (L == 0 ? i : 2 * i));
+  return L == 0 ? (w & 0xFFFFFFFFull) : w;
+}
+
+struct View {
+  void *cells;
+  uint32_t log2c;
+  u64 mask, thr;
+};
+
+__device__ __forceinline__ View view_of(const AsyncArgs &a, uint32_t e) {
+  View v;
+  v.cells = a.ladder[e];
+  v.log2c = a.log2c + e;
+  v.mask = (1ull << v.log2c) - 1;
+  v.thr = (u64)(((unsigned __int128)(1ull << v.log2c) * a.alpha_num) / a.alpha_den);
+  return v;
+}
+
+// Waits (lane 0 polls) until *p >= target; false if the bound passed.
+__device__ bool wait_ge(const uint32_t *p, uint32_t target, u64 ticks) {
+  uint32_t ok = 1;
+  if ((threadIdx.x & 63) == 0) {
+    const u64 t0 = wall_clock64();
+    while (ld32(p) < target) {
+      if (wall_clock64() - t0 > ticks) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  return uni(ok) != 0;
+}
+
+// Waits until gen moved past `g`; returns the new gen, or ~0u on timeout.
+__device__ uint32_t wait_gen_past(const uint32_t *gen, uint32_t g, u64 ticks) {
+  uint32_t r = 0;
+  if ((threadIdx.x & 63) == 0) {
+    const u64 t0 = wall_clock64();
+    for (;;) {
+      r = ld32(gen);
+      if (r != g) break;
+      if (wall_clock64() - t0 > ticks) {
+        r = ~0u;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  return uni(r);
+}
+
+__device__ __forceinline__ uint32_t lane0_add(uint32_t *p, uint32_t d) {
+  uint32_t r = 0;
+  if ((threadIdx.x & 63) == 0) r = __hip_atomic_fetch_add(p, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return uni(r);
+}
+
+template <int L>
+__device__ __forceinline__ void put(void *cells, u64 p, u64 key, u64 val) {
+  if (L == 0) {
+    st64((u64 *)cells + p, (key & 0xFFFFFFFFull) | (val << 32));
+  } else {
+    st64((u64 *)cells + 2 * p + 1, val);
+    st64((u64 *)cells + 2 * p, key);
+  }
+}
+
+// The migration of epoch e into e + 1 by all W wavefronts.  Returns false
+// on timeout.  gen is 2e + 1 on entry; the last wavefront through sets it
+// to 2(e + 1).
+template <int L>
+__device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e, uint32_t W, u64 ticks) {
+  AsyncCtl *ctl = a.ctl;
+  const uint32_t lane = threadIdx.x & 63;
+  const View o = view_of(a, e), nv = view_of(a, e + 1);
+  // 1. every wavefront has left the old table
+  __threadfence();
+  lane0_add(&ctl->arrived, 1);
+  if (!wait_ge(&ctl->arrived, W, ticks)) return false;
+  __threadfence();
+  // 2. clear the target
+  const u64 nc = 1ull << nv.log2c;
+  for (;;) {
+    const u64 item = lane0_add(&ctl->zero_next, 1);
+    const u64 z0 = item * kZeroBlock;
+    if (z0 >= nc) break;
+    const u64 z1 = std::min<u64>(nc, z0 + kZeroBlock);
+    for (u64 i = z0 + lane; i < z1; i += 64) put<L>(nv.cells, i, 0, 0);
+  }
+  __threadfence();
+  lane0_add(&ctl->arrived, 1);
+  if (!wait_ge(&ctl->arrived, 2 * W, ticks)) return false;
+  __threadfence();
+  // 3. clusters of the old table, each walked in order by the lane that owns
+  //    its first cell; their target ranges are disjoint (Lemma 1)
+  const u64 oc = 1ull << o.log2c;
+  u64 moved = 0;
+  for (;;) {
+    const u64 item = lane0_add(&ctl->mig_next, 1);
+    const u64 b0 = item * kAsyncMigBlock;
+    if (b0 >= oc) break;
+    const u64 b1 = std::min<u64>(oc, b0 + kAsyncMigBlock);
+    for (u64 i = b0 + lane; i < b1; i += 64) {
+      if (key_at<L>(o.cells, i) == kEmpty || key_at<L>(o.cells, (i - 1) & o.mask) != kEmpty) continue;
+      for (u64 j = i;; j = (j + 1) & o.mask) {
+        const u64 k = key_at<L>(o.cells, j);
+        if (k == kEmpty) break;
+        if (k == kTomb) continue;
+        const u64 v = L == 0 ? (ld64((const u64 *)o.cells + j) >> 32) : ld64((const u64 *)o.cells + 2 * j + 1);
+        u64 p = home_of<L>(T, k, a.crc_hi, a.crc_lo, nv.log2c);
+        while (key_at<L>(nv.cells, p) != kEmpty) p = (p + 1) & nv.mask;
+        put<L>(nv.cells, p, k, v);
+        ++moved;
+      }
+    }
+  }
+  const long long ms = wave_sum((long long)moved);
+  if (lane == 0 && ms) __hip_atomic_fetch_add(&ctl->moved, (unsigned long long)ms, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+  // 4. the last to arrive publishes the new version
+  __threadfence();
+  const uint32_t before = lane0_add(&ctl->arrived, 1);
+  if (before == 3 * W - 1) {
+    if (lane == 0) {
+      __threadfence();
+      const unsigned long long mv = __hip_atomic_load(&ctl->moved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->I, mv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->moved, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->zero_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->mig_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->epoch, e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      __hip_atomic_store(&ctl->gen, 2 * (e + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  return true;
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, uint32_t W) {
+  __shared__ uint32_t T[8][256];
+  crc_tables_build(T);
+  AsyncCtl *ctl = a.ctl;
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t *gen = &ctl->gen;
+  uint32_t my = 0;
+  View v = view_of(a, 0);
+  uint32_t rng = 0x9E3779B9u ^ (blockIdx.x * 4 + (threadIdx.x >> 6)) * 0x85EBCA6Bu;
+  auto next_flush = [&]() {
+    rng ^= rng << 13;
+    rng ^= rng >> 17;
+    rng ^= rng << 5;
+    return 1u + rng % kAsyncFlushMax;
+  };
+  uint32_t flush_at = next_flush();
+  uint32_t local = 0;
+  uint32_t err = 0;
+  bool finished = false;
+  u64 idle_since = 0;
+  for (;;) {
+    const uint32_t g = uni(ld32(gen));
+    if (g / 2 > my) {  // a growth finished (this wavefront took part in it)
+      my = g / 2;
+      v = view_of(a, my);
+      __threadfence();
+    }
+    if (g & 1u) {  // a growth of version `my` is pending: arrive and help
+      local = 0;  // the migration recounts what was inserted
+      if (!migrate<L>(a, T, my, W, ticks)) {
+        err = 1;
+        break;
+      }
+      const uint32_t g2 = wait_gen_past(gen, g, ticks);
+      if (g2 == ~0u) {
+        err = 1;
+        break;
+      }
+      idle_since = wall_clock64();
+      continue;
+    }
+    if (finished) {
+      // the others end their last chunks (and any growth) within the bound
+      if (uni(ld32(&ctl->finished)) >= W) break;
+      if (wall_clock64() - idle_since > ticks) {
+        err = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+      continue;
+    }
+    u64 base = 0;
+    if (lane == 0) base = __hip_atomic_fetch_add(&ctl->next, (unsigned long long)kAsyncChunk, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    base = ((u64)uni((uint32_t)(base >> 32)) << 32) | uni((uint32_t)base);
+    if (base >= a.n) {
+      finished = true;
+      idle_since = wall_clock64();
+      lane0_add(&ctl->finished, 1);
+      continue;
+    }
+    // one operation per lane
+    const u64 i = base + lane;
+    uint32_t inserted = 0;
+    if (i < a.n) {
+      const u64 key = L == 0 ? (u64)((const uint32_t *)a.keys)[i] : ((const u64 *)a.keys)[i];
+      const u64 d = a.vals ? (L == 0 ? (u64)((const uint32_t *)a.vals)[i] : ((const u64 *)a.vals)[i]) : 1;
+      uint8_t flag;
+      if (key <= kTomb) {
+        flag = kFlagReserved;
+        err |= 4;
+      } else {
+        flag = kFlagFull;
+        u64 p = home_of<L>(T, key, a.crc_hi, a.crc_lo, v.log2c);
+        for (u64 step = 0; step <= v.mask; ++step, p = (p + 1) & v.mask) {
+          u64 cur = key_at<L>(v.cells, p);
+          if (cur == kEmpty) {
+            if (L == 0) {
+              const u64 want = key | ((d & 0xFFFFFFFFull) << 32);
+              const u64 w = cas64((u64 *)v.cells + p, kEmpty, want);
+              if (w == kEmpty) {
+                flag = 1;
+                inserted = 1;
+                break;
+              }
+              cur = w & 0xFFFFFFFFull;
+            } else {
+              const u64 w = cas64((u64 *)v.cells + 2 * p, kEmpty, key);
+              if (w == kEmpty) {
+                if (a.add)
+                  add64((u64 *)v.cells + 2 * p + 1, d);
+                else
+                  st64((u64 *)v.cells + 2 * p + 1, d);
+                flag = 1;
+                inserted = 1;
+                break;
+              }
+              cur = w;
+            }
+          }
+          if (cur == key) {
+            if (a.add) {
+              if (L == 0)
+                __hip_atomic_fetch_add((uint32_t *)((u64 *)v.cells + p) + 1, (uint32_t)d, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+              else
+                add64((u64 *)v.cells + 2 * p + 1, d);
+            }
+            flag = 0;
+            break;
+          }
+        }
+      }
+      if (a.flags) a.flags[i] = flag;
+    }
+    local += (uint32_t)__popcll(__ballot(inserted));
+    if (local >= flush_at) {
+      uint32_t trig = 0;
+      if (lane == 0) {
+        const unsigned long long before =
+            __hip_atomic_fetch_add(&ctl->I, (unsigned long long)local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        trig = before + local >= v.thr && my + 1 < a.nladder;
+      }
+      local = 0;
+      flush_at = next_flush();
+      if (uni(trig) && lane == 0) {
+        uint32_t expect = 2 * my;
+        __hip_atomic_compare_exchange_strong(gen, &expect, 2 * my + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  // timeouts are set by the whole wavefront, reserved keys by single lanes
+  const uint32_t werr = uni(err & 3u) | (__ballot((err & 4u) != 0) ? 4u : 0u);
+  if (werr && lane == 0) {
+    atomicOr(&ctl->err, werr);
+    if (werr & 4u) atomicOr(&a.status->err, kErrReserved);
+  }
+}
+
+__global__ void k_async_init(AsyncCtl *ctl, u64 used0) {
+  if (threadIdx.x < sizeof(AsyncCtl) / 8) ((unsigned long long *)ctl)[threadIdx.x] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) ctl->I = used0;
+}
+
+}  // namespace
+
+uint32_t async_grid(int device) {
+  int coop = 0, ncu = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0)
+    return 0;
+  int b0 = 0, b1 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_async_insert<0>, 256, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_async_insert<1>, 256, 0) != hipSuccess)
+    return 0;
+  const int per = std::min(2, std::min(b0, b1));
+  return per > 0 ? (uint32_t)(per * ncu) : 0u;
+}
+
+uint32_t async_min_log2(uint32_t grid, uint32_t alpha_num, uint32_t alpha_den) {
+  // In flight beyond the flushed count: per wavefront one chunk plus one
+  // unflushed batch of insertions, twice (before and while the growth is
+  // noticed); they must fit half the free cells (1 - alpha) c.
+  const unsigned __int128 slack = (unsigned __int128)grid * 4 * (kAsyncChunk + kAsyncFlushMax) * 2;
+  uint32_t lg = 6;
+  while (lg < 40 && ((unsigned __int128)(1ull << lg) * (alpha_den - alpha_num)) < slack * 2 * alpha_den) ++lg;
+  return lg;
+}
+
+hipError_t launch_async_insert(const AsyncArgs &a, hipStream_t s) {
+  if (a.layout > 1 || !a.ctl || !a.grid || a.nladder < 1 || a.nladder > kAsyncLadder + 1) return hipErrorInvalidValue;
+  int dev = 0, khz = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_async_init, dim3(1), dim3(64), 0, s, a.ctl, (u64)a.used0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  AsyncArgs args = a;
+  u64 ticks = (u64)khz * 1000ull * 2;  // two seconds
+  uint32_t W = a.grid * 4;
+  void *kargs[] = {&args, &ticks, &W};
+  e = hipLaunchCooperativeKernel(a.layout == 0 ? (const void *)k_async_insert<0> : (const void *)k_async_insert<1>,
+                                 dim3(a.grid), dim3(256), kargs, 0, s);
+  return e;
+}
+
+}  // namespace lpht

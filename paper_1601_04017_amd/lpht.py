@@ -87,6 +87,7 @@ class lpht_stats(ctypes.Structure):
         ("migrate_ms", ctypes.c_double),
         ("shrinks", ctypes.c_uint64),
         ("bulk_merges", ctypes.c_uint64),
+        ("async_growths", ctypes.c_uint64),
     ]
 
 
@@ -124,6 +125,7 @@ _SIGS = {
     "lpht_erase": (ctypes.c_int, [_VP, _VP, _U64, _VP, _VP]),
     "lpht_grow": (ctypes.c_int, [_VP, _U32, _VP]),
     "lpht_build": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP]),
+    "lpht_insert_async": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP, _VP]),
     "lpht_merge": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP]),
     "lpht_count": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
     "lpht_capacity": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U32)]),
@@ -282,6 +284,14 @@ class Table:
 
     def grow(self, log2_new: int, stream=None):
         _check(load().lpht_grow(self._h, log2_new, _stream_handle(stream)), "lpht_grow")
+
+    def insert_async(self, keys, vals=None, add=False, flags=True, stream=None):
+        """Insertion (or insert-or-add) that grows the table inside the kernel."""
+        n = self._n(keys)
+        f = self._flags(n, flags)
+        _check(load().lpht_insert_async(self._h, _ptr(keys), _ptr(vals), n, 1 if add else 0, _ptr(f),
+                                        _stream_handle(stream)), "lpht_insert_async")
+        return f
 
     def build(self, keys, vals=None, op=ASSIGN, stream=None):
         """Sort-based bulk build: the table's contents become the batch."""
