@@ -157,7 +157,7 @@ def _timed(fn, stream):
     return a.elapsed_time(b)
 
 
-SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "deletion", "bulk", "zipf", "serving")
+SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "deletion", "bulk", "async", "zipf", "serving")
 
 
 def run_suite(dev, reps=3, parts=SUITE_PARTS):
@@ -181,7 +181,7 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
         out["ceilings"] = roofline.measure()
     if "packed32" in parts:
         out["packed32_2e21"] = _suite_packed32(dev, up, stream, reps)
-    need_keys = "fill_sweep" in parts or "growing" in parts or "deletion" in parts or "bulk" in parts
+    need_keys = any(p in parts for p in ("fill_sweep", "growing", "deletion", "bulk", "async"))
     if need_keys:
         nmax = 201_326_592
         keys = inputs.distinct_keys_u64(nmax, 201)
@@ -197,6 +197,8 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
         out["shrink_2e26"] = _suite_shrink(stream, dkeys, dvals)
     if "bulk" in parts:
         out["bulk_build_merge_2e28"] = _suite_bulk(up, stream, reps, dkeys, dvals)
+    if "async" in parts:
+        out["async_growth_one_call"] = _suite_async(up, reps, dkeys, dvals)
     if need_keys:
         del dkeys, dvals
     if "zipf" in parts:
@@ -474,6 +476,45 @@ def _suite_bulk(up, stream, reps, dkeys, dvals):
     out["build_zipf1_add_1e8_ms"] = round(float(np.mean(res)), 3)
     out["build_zipf1_add_distinct"] = int(t.count()[1])
     t.close()
+    del z
+    return out
+
+
+def _suite_async(up, reps, dkeys, dvals):
+    import torch
+
+    from paper_1601_04017_amd import inputs, lpht
+
+    # One call of 10^8 operations into a table created with 4096 cells:
+    # growth inside the kernel (lpht_insert_async) against growth by the
+    # host before the call (pre-growth by the call's length), for distinct
+    # keys and for Zipf(1.0) insert-or-increment.
+    log("suite: async growth")
+    z = up(inputs.zipf_keys_u64(N_OPS, ZIPF_N, ZIPF_S, seed=404))
+    out = {}
+    for name, keys, vals, add in (("distinct", dkeys[:N_OPS], dvals[:N_OPS], False), ("zipf1_add", z, None, True)):
+        row = {}
+        for mode in ("async", "host"):
+            res = []
+            for r in range(reps + 1):
+                t = new_table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+                t.set_timing(True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if mode == "async":
+                    t.insert_async(keys, vals, add=add, flags=False)
+                elif add:
+                    t.insert_or_update(keys, None, op=lpht.ADD, flags=False)
+                else:
+                    t.insert(keys, vals, flags=False)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t0) * 1e3
+                if r:
+                    res.append((el, t.log2_capacity, t.stats()["async_growths"]))
+                t.close()
+            el, lg, ng = np.mean(res, axis=0)
+            row[mode] = {"ms": round(el, 3), "final_log2_capacity": int(lg), "in_kernel_growths": int(ng)}
+        out[name] = row
     del z
     return out
 

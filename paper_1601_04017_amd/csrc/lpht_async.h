@@ -11,8 +11,9 @@
 namespace lpht {
 
 constexpr uint32_t kAsyncLadder = 16;     // most doublings one call can make
-constexpr uint32_t kAsyncChunk = 64;      // operations a wavefront takes at a time
-constexpr uint32_t kAsyncFlushMax = 64;   // a wavefront's local count is flushed after 1..64 insertions
+constexpr uint32_t kAsyncChunk = 64;      // operations of one round (one per lane)
+constexpr uint32_t kAsyncMaxRounds = 16;  // rounds per chunk a wavefront takes at a time (at most)
+constexpr uint32_t kAsyncFlushMax = 64;   // on the smallest tables a local count is flushed after 1..64 insertions
 constexpr uint32_t kAsyncMigBlock = 4096; // old cells per migration work item
 
 // Device control block (zeroed by the launcher).

@@ -65,15 +65,23 @@ __device__ __forceinline__ u64 key_at(const void *cells, u64 i) {
 struct View {
   void *cells;
   uint32_t log2c;
+  uint32_t rounds;  // 64-operation rounds per chunk (and the flush bound / 64)
   u64 mask, thr;
 };
 
-__device__ __forceinline__ View view_of(const AsyncArgs &a, uint32_t e) {
+// A chunk is `rounds` rounds of 64 operations; rounds grows with the table
+// so that every wavefront's chunk plus unflushed count, twice, fit half the
+// free cells: 256 * W * rounds <= (1 - alpha) c / 2.
+__device__ __forceinline__ View view_of(const AsyncArgs &a, uint32_t e, uint32_t W) {
   View v;
   v.cells = a.ladder[e];
   v.log2c = a.log2c + e;
   v.mask = (1ull << v.log2c) - 1;
   v.thr = (u64)(((unsigned __int128)(1ull << v.log2c) * a.alpha_num) / a.alpha_den);
+  const u64 free_half = (u64)(((unsigned __int128)(1ull << v.log2c) * (a.alpha_den - a.alpha_num)) /
+                              ((u64)a.alpha_den * 2));
+  const u64 r = free_half / (256ull * W);
+  v.rounds = (uint32_t)std::max<u64>(1, std::min<u64>(kAsyncMaxRounds, r));
   return v;
 }
 
@@ -134,7 +142,7 @@ template <int L>
 __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e, uint32_t W, u64 ticks) {
   AsyncCtl *ctl = a.ctl;
   const uint32_t lane = threadIdx.x & 63;
-  const View o = view_of(a, e), nv = view_of(a, e + 1);
+  const View o = view_of(a, e, W), nv = view_of(a, e + 1, W);
   // 1. every wavefront has left the old table
   __threadfence();
   lane0_add(&ctl->arrived, 1);
@@ -147,7 +155,12 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
     const u64 z0 = item * kZeroBlock;
     if (z0 >= nc) break;
     const u64 z1 = std::min<u64>(nc, z0 + kZeroBlock);
-    for (u64 i = z0 + lane; i < z1; i += 64) put<L>(nv.cells, i, 0, 0);
+    if (L == 0) {
+      for (u64 i = z0 + lane; i < z1; i += 64) ((u64 *)nv.cells)[i] = 0;
+    } else {
+      const u64x2 zero = {0, 0};
+      for (u64 i = z0 + lane; i < z1; i += 64) ((u64x2 *)nv.cells)[i] = zero;
+    }
   }
   __threadfence();
   lane0_add(&ctl->arrived, 1);
@@ -207,13 +220,13 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
   const uint32_t lane = threadIdx.x & 63;
   uint32_t *gen = &ctl->gen;
   uint32_t my = 0;
-  View v = view_of(a, 0);
+  View v = view_of(a, 0, W);
   uint32_t rng = 0x9E3779B9u ^ (blockIdx.x * 4 + (threadIdx.x >> 6)) * 0x85EBCA6Bu;
   auto next_flush = [&]() {
     rng ^= rng << 13;
     rng ^= rng >> 17;
     rng ^= rng << 5;
-    return 1u + rng % kAsyncFlushMax;
+    return 1u + rng % (64u * v.rounds);
   };
   uint32_t flush_at = next_flush();
   uint32_t local = 0;
@@ -224,7 +237,7 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
     const uint32_t g = uni(ld32(gen));
     if (g / 2 > my) {  // a growth finished (this wavefront took part in it)
       my = g / 2;
-      v = view_of(a, my);
+      v = view_of(a, my, W);
       __threadfence();
     }
     if (g & 1u) {  // a growth of version `my` is pending: arrive and help
@@ -251,8 +264,9 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
       __builtin_amdgcn_s_sleep(4);
       continue;
     }
+    const u64 span = 64ull * v.rounds;
     u64 base = 0;
-    if (lane == 0) base = __hip_atomic_fetch_add(&ctl->next, (unsigned long long)kAsyncChunk, __ATOMIC_RELAXED,
+    if (lane == 0) base = __hip_atomic_fetch_add(&ctl->next, (unsigned long long)span, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     base = ((u64)uni((uint32_t)(base >> 32)) << 32) | uni((uint32_t)base);
     if (base >= a.n) {
@@ -261,74 +275,76 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
       lane0_add(&ctl->finished, 1);
       continue;
     }
-    // one operation per lane
-    const u64 i = base + lane;
-    uint32_t inserted = 0;
-    if (i < a.n) {
-      const u64 key = L == 0 ? (u64)((const uint32_t *)a.keys)[i] : ((const u64 *)a.keys)[i];
-      const u64 d = a.vals ? (L == 0 ? (u64)((const uint32_t *)a.vals)[i] : ((const u64 *)a.vals)[i]) : 1;
-      uint8_t flag;
-      if (key <= kTomb) {
-        flag = kFlagReserved;
-        err |= 4;
-      } else {
-        flag = kFlagFull;
-        u64 p = home_of<L>(T, key, a.crc_hi, a.crc_lo, v.log2c);
-        for (u64 step = 0; step <= v.mask; ++step, p = (p + 1) & v.mask) {
-          u64 cur = key_at<L>(v.cells, p);
-          if (cur == kEmpty) {
-            if (L == 0) {
-              const u64 want = key | ((d & 0xFFFFFFFFull) << 32);
-              const u64 w = cas64((u64 *)v.cells + p, kEmpty, want);
-              if (w == kEmpty) {
-                flag = 1;
-                inserted = 1;
-                break;
+    for (uint32_t rd = 0; rd < v.rounds; ++rd) {
+      // one operation per lane
+      const u64 i = base + 64ull * rd + lane;
+      uint32_t inserted = 0;
+      if (i < a.n) {
+        const u64 key = L == 0 ? (u64)((const uint32_t *)a.keys)[i] : ((const u64 *)a.keys)[i];
+        const u64 d = a.vals ? (L == 0 ? (u64)((const uint32_t *)a.vals)[i] : ((const u64 *)a.vals)[i]) : 1;
+        uint8_t flag;
+        if (key <= kTomb) {
+          flag = kFlagReserved;
+          err |= 4;
+        } else {
+          flag = kFlagFull;
+          u64 p = home_of<L>(T, key, a.crc_hi, a.crc_lo, v.log2c);
+          for (u64 step = 0; step <= v.mask; ++step, p = (p + 1) & v.mask) {
+            u64 cur = key_at<L>(v.cells, p);
+            if (cur == kEmpty) {
+              if (L == 0) {
+                const u64 want = key | ((d & 0xFFFFFFFFull) << 32);
+                const u64 w = cas64((u64 *)v.cells + p, kEmpty, want);
+                if (w == kEmpty) {
+                  flag = 1;
+                  inserted = 1;
+                  break;
+                }
+                cur = w & 0xFFFFFFFFull;
+              } else {
+                const u64 w = cas64((u64 *)v.cells + 2 * p, kEmpty, key);
+                if (w == kEmpty) {
+                  if (a.add)
+                    add64((u64 *)v.cells + 2 * p + 1, d);
+                  else
+                    st64((u64 *)v.cells + 2 * p + 1, d);
+                  flag = 1;
+                  inserted = 1;
+                  break;
+                }
+                cur = w;
               }
-              cur = w & 0xFFFFFFFFull;
-            } else {
-              const u64 w = cas64((u64 *)v.cells + 2 * p, kEmpty, key);
-              if (w == kEmpty) {
-                if (a.add)
-                  add64((u64 *)v.cells + 2 * p + 1, d);
+            }
+            if (cur == key) {
+              if (a.add) {
+                if (L == 0)
+                  __hip_atomic_fetch_add((uint32_t *)((u64 *)v.cells + p) + 1, (uint32_t)d, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
                 else
-                  st64((u64 *)v.cells + 2 * p + 1, d);
-                flag = 1;
-                inserted = 1;
-                break;
+                  add64((u64 *)v.cells + 2 * p + 1, d);
               }
-              cur = w;
+              flag = 0;
+              break;
             }
-          }
-          if (cur == key) {
-            if (a.add) {
-              if (L == 0)
-                __hip_atomic_fetch_add((uint32_t *)((u64 *)v.cells + p) + 1, (uint32_t)d, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-              else
-                add64((u64 *)v.cells + 2 * p + 1, d);
-            }
-            flag = 0;
-            break;
           }
         }
+        if (a.flags) a.flags[i] = flag;
       }
-      if (a.flags) a.flags[i] = flag;
-    }
-    local += (uint32_t)__popcll(__ballot(inserted));
-    if (local >= flush_at) {
-      uint32_t trig = 0;
-      if (lane == 0) {
-        const unsigned long long before =
-            __hip_atomic_fetch_add(&ctl->I, (unsigned long long)local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        trig = before + local >= v.thr && my + 1 < a.nladder;
-      }
-      local = 0;
-      flush_at = next_flush();
-      if (uni(trig) && lane == 0) {
-        uint32_t expect = 2 * my;
-        __hip_atomic_compare_exchange_strong(gen, &expect, 2 * my + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
+      local += (uint32_t)__popcll(__ballot(inserted));
+      if (local >= flush_at) {
+        uint32_t trig = 0;
+        if (lane == 0) {
+          const unsigned long long before =
+              __hip_atomic_fetch_add(&ctl->I, (unsigned long long)local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          trig = before + local >= v.thr && my + 1 < a.nladder;
+        }
+        local = 0;
+        flush_at = next_flush();
+        if (uni(trig) && lane == 0) {
+          uint32_t expect = 2 * my;
+          __hip_atomic_compare_exchange_strong(gen, &expect, 2 * my + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
     }
   }
