@@ -88,6 +88,8 @@ def load(path):
     L.orc_grow.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
     L.orc_migrate.restype = ctypes.c_int
     L.orc_migrate.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    L.orc_set_full_keys.restype = ctypes.c_int
+    L.orc_set_full_keys.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.orc_bulk_merge.restype = ctypes.c_int
     L.orc_bulk_merge.argtypes = [ctypes.c_void_p, u8p, u8p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
     return L
@@ -128,13 +130,15 @@ class OracleTable:
     """Sequential linear-probing table with the device table's cell layout."""
 
     def __init__(self, layout: int, log2c: int, seed_hi: int = SEED_HI, seed_lo: int = SEED_LO,
-                 alpha=(1, 2), auto_grow: bool = False):
+                 alpha=(1, 2), auto_grow: bool = False, full_keys: bool = False):
         self.layout = layout
         self.kdt = np.uint32 if layout == PACKED32 else np.uint64
         self._t = lib().orc_create(layout, log2c, seed_hi, seed_lo, alpha[0], alpha[1],
                                    1 if auto_grow else 0)
         if not self._t:
             raise ValueError("oracle table creation failed")
+        if full_keys:
+            lib().orc_set_full_keys(self._t, 1)
 
     def __del__(self):
         t = getattr(self, "_t", None)

@@ -102,6 +102,11 @@ typedef struct orc_table {
   uint64_t live; /* live keys */
   int sticky;
   uint64_t migrations;
+  /* Full key space (Sec. 5.6): keys empty_key and del_key live in two
+   * special slots outside the cell array instead of being reserved. */
+  int full_keys;
+  int sp_present[2];
+  uint64_t sp_val[2];
 } orc_table;
 
 static int key_bytes(const orc_table *t) { return t->layout == ORC_PACKED32 ? 4 : 8; }
@@ -174,9 +179,30 @@ uint64_t orc_capacity(const orc_table *t) { return t->cap; }
 uint32_t orc_log2_capacity(const orc_table *t) { return t->log2c; }
 uint64_t orc_migrations(const orc_table *t) { return t->migrations; }
 
+/* Counts include the special slots that hold a key. */
 void orc_counts(const orc_table *t, uint64_t *used, uint64_t *live) {
-  *used = t->used;
-  *live = t->live;
+  uint64_t sp = (uint64_t)t->sp_present[0] + (uint64_t)t->sp_present[1];
+  *used = t->used + sp;
+  *live = t->live + sp;
+}
+
+/* Switches the full key space on or off (a table with no special key). */
+int orc_set_full_keys(orc_table *t, int on) {
+  if (t->sp_present[0] || t->sp_present[1]) return -1;
+  t->full_keys = on ? 1 : 0;
+  return 0;
+}
+
+/* Operations on a special slot (k is 0 or 1), with the same results as the
+ * cell operations: a slot is one cell that only key k can use. */
+static uint8_t sp_insert(orc_table *t, uint64_t k, uint64_t v, int is_upsert, int op) {
+  if (!t->sp_present[k]) {
+    t->sp_present[k] = 1;
+    t->sp_val[k] = apply_up(t, 0, v, ORC_ASSIGN);
+    return 1;
+  }
+  if (is_upsert) t->sp_val[k] = apply_up(t, t->sp_val[k], v, op);
+  return 0;
 }
 
 /* Returns the sticky error bits and clears them. */
@@ -220,6 +246,7 @@ int orc_import(orc_table *t, const uint64_t *src, uint32_t log2c) {
  * an equal key means the key is present (false).  Tombstones and other keys
  * are skipped, so tombstones are never reused. */
 static uint8_t op_insert(orc_table *t, uint64_t k, uint64_t v) {
+  if (t->full_keys && k <= ORC_TOMB) return sp_insert(t, k, v, 0, ORC_ASSIGN);
   if (k == ORC_EMPTY || k == ORC_TOMB) {
     t->sticky |= ORC_STICKY_RESERVED;
     return ORC_FLAG_RESERVED;
@@ -243,6 +270,7 @@ static uint8_t op_insert(orc_table *t, uint64_t k, uint64_t v) {
 /* insertOrUpdate(k,d,up): as insert, but an equal key gets
  * value := up(value, d); returns true iff a new key was inserted. */
 static uint8_t op_insert_or_update(orc_table *t, uint64_t k, uint64_t d, int op) {
+  if (t->full_keys && k <= ORC_TOMB) return sp_insert(t, k, d, 1, op);
   if (k == ORC_EMPTY || k == ORC_TOMB) {
     t->sticky |= ORC_STICKY_RESERVED;
     return ORC_FLAG_RESERVED;
@@ -268,6 +296,11 @@ static uint8_t op_insert_or_update(orc_table *t, uint64_t k, uint64_t d, int op)
 
 /* update(k,d,up): false if the key is absent, else value := up(value, d). */
 static uint8_t op_update(orc_table *t, uint64_t k, uint64_t d, int op) {
+  if (t->full_keys && k <= ORC_TOMB) {
+    if (!t->sp_present[k]) return 0;
+    t->sp_val[k] = apply_up(t, t->sp_val[k], d, op);
+    return 1;
+  }
   if (k == ORC_EMPTY || k == ORC_TOMB) {
     t->sticky |= ORC_STICKY_RESERVED;
     return ORC_FLAG_RESERVED;
@@ -288,6 +321,11 @@ static uint8_t op_update(orc_table *t, uint64_t k, uint64_t d, int op) {
 /* find(k): a copy of the stored value if the key is present. */
 static uint8_t op_find(orc_table *t, uint64_t k, uint64_t *val) {
   *val = 0;
+  if (t->full_keys && k <= ORC_TOMB) {
+    if (!t->sp_present[k]) return 0;
+    *val = t->sp_val[k];
+    return 1;
+  }
   if (k == ORC_EMPTY || k == ORC_TOMB) {
     t->sticky |= ORC_STICKY_RESERVED;
     return ORC_FLAG_RESERVED;
@@ -307,6 +345,12 @@ static uint8_t op_find(orc_table *t, uint64_t k, uint64_t *val) {
 
 /* Tombstone delete: the key becomes del_key, the value stays. */
 static uint8_t op_erase(orc_table *t, uint64_t k) {
+  if (t->full_keys && k <= ORC_TOMB) {
+    if (!t->sp_present[k]) return 0;
+    t->sp_present[k] = 0;
+    t->sp_val[k] = 0;
+    return 1;
+  }
   if (k == ORC_EMPTY || k == ORC_TOMB) {
     t->sticky |= ORC_STICKY_RESERVED;
     return ORC_FLAG_RESERVED;
@@ -550,9 +594,20 @@ int orc_bulk_merge(orc_table *t, const void *keys, const void *vals, uint64_t n,
       it[m].seq = 0;
       ++m;
     }
+  /* full key space: the special slots take the batch's keys 0 and 1 in
+   * index order (a build starts them empty); decided after the capacity
+   * check below, so a refused call changes nothing */
+  int spp[2] = {keep_old ? t->sp_present[0] : 0, keep_old ? t->sp_present[1] : 0};
+  uint64_t spv[2] = {keep_old ? t->sp_val[0] : 0, keep_old ? t->sp_val[1] : 0};
   for (uint64_t i = 0; i < n; ++i) {
     uint64_t k = load_word(t, keys, i);
     if (k == ORC_EMPTY || k == ORC_TOMB) {
+      if (t->full_keys) {
+        uint64_t v = vals ? load_word(t, vals, i) : 1;
+        spv[k] = (op == ORC_ADD) ? apply_up(t, spp[k] ? spv[k] : 0, v, ORC_ADD) : apply_up(t, 0, v, ORC_ASSIGN);
+        spp[k] = 1;
+        continue;
+      }
       t->sticky |= ORC_STICKY_RESERVED;
       continue;
     }
@@ -603,6 +658,10 @@ int orc_bulk_merge(orc_table *t, const void *keys, const void *vals, uint64_t n,
   t->log2c = log2c;
   t->cap = cap;
   t->used = t->live = d;
+  for (int q = 0; q < 2; ++q) {
+    t->sp_present[q] = spp[q];
+    t->sp_val[q] = spv[q];
+  }
   return 0;
 }
 

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_bulk as TB
+from tests import test_oracle_fullkeys as TF
 from tests import test_oracle_hash as TH
 from tests import test_oracle_migration as TM
 from tests import test_oracle_table as TT
@@ -41,6 +42,9 @@ MUTANTS = [
     ("shrink_below_created_capacity", "grow_before_batch", "target > t->log2_min && ", ""),
     ("shrink_one_step_too_far", "grow_before_batch", "fits_quarter(t, t->live + b, 1ull << target)",
      "within_fill(t, t->live + b, 1ull << target)"),
+    ("special_erase_keeps_key", "op_erase", "t->sp_present[k] = 0;", ";"),
+    ("special_upsert_assigns", "sp_insert", "if (is_upsert) t->sp_val[k] = apply_up(t, t->sp_val[k], v, op);",
+     "if (is_upsert) t->sp_val[k] = v;"),
     ("bulk_keeps_first", "orc_bulk_merge", ": it[i].v;", ": it[d - 1].v;"),
     ("bulk_sorted_by_key", "item_cmp", "if (x->h != y->h) return x->h < y->h ? -1 : 1;",
      "if (x->k != y->k) return x->k < y->k ? -1 : 1;"),
@@ -91,6 +95,9 @@ def _pins():
         yield lambda layout=layout: TB.test_occupancy_equals_insertion_in_random_order(layout)
         yield lambda layout=layout: TB.test_hand_worked_wrapping_example(layout)
         yield lambda layout=layout: TB.test_capacity_rule_and_full_tables(layout)
+        for seed in range(3):
+            yield lambda layout=layout, seed=seed: TF.test_sequences_with_keys_0_and_1_match_dict_model(layout, seed)
+        yield lambda layout=layout: TF.test_special_keys_survive_migration_and_follow_bulk_rules(layout)
 
 
 @pytest.mark.parametrize("name,func,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
