@@ -105,7 +105,9 @@ typedef struct lpht_config {
                            * live + b <= alpha*c'/2 (c' = c drops tombstones,
                            * c' < c shrinks), else the table doubles until
                            * live + b <= alpha*c */
-  uint32_t reserved0;     /* must be 0 */
+  uint32_t full_keys;     /* 0: keys 0 and 1 are reserved; 1: full key space (Sec. 5.6): keys 0
+                           * and 1 are stored in two special slots of the table object; the
+                           * batch and serving APIs do not take such tables */
   lpht_alloc_fn alloc;
   lpht_free_fn free;
   void *alloc_ctx;

@@ -15,6 +15,7 @@
 #include "lpht_async.h"
 #include "lpht_bulk.h"
 #include "lpht_shrink.h"
+#include "lpht_special.h"
 
 using namespace lpht;
 
@@ -389,6 +390,9 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
     if (e != hipSuccess) return from_hip(e);
     done += len;
   }
+  if (t->special)
+    return from_hip(launch_special(t->cfg.layout, op, up, keys, vals, n, vals_out, flags, t->special,
+                                   t->special_scratch, false, s));
   return LPHT_OK;
 }
 
@@ -482,6 +486,7 @@ int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void 
   for (uint32_t j = 0; j < nops; ++j) {
     const lpht_batch_op &o = ops[j];
     if (!o.table || o.op > LPHT_OP_ERASE || o.up > LPHT_ADD) return LPHT_ERR_INVALID;
+    if (o.table->special) return LPHT_ERR_UNSUPPORTED;
     if (o.count_sel > o.n) return LPHT_ERR_INVALID;
     if (o.table->device != b->device) return LPHT_ERR_INVALID;
     int rc = check_arrays(o.table, o.keys, o.vals, o.n);
@@ -569,7 +574,7 @@ int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out) {
   if (cfg->log2_capacity < 6 || cfg->log2_capacity > 34) return LPHT_ERR_INVALID;
   if (cfg->max_fill_num == 0 || cfg->max_fill_den == 0 || cfg->max_fill_num > cfg->max_fill_den)
     return LPHT_ERR_INVALID;
-  if (cfg->reserved0 != 0) return LPHT_ERR_INVALID;
+  if (cfg->full_keys > 1) return LPHT_ERR_INVALID;
   if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return LPHT_ERR_INVALID;
   lpht_table *t = new (std::nothrow) lpht_table();
   if (!t) return LPHT_ERR_OOM;
@@ -616,7 +621,16 @@ int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out) {
   t->log2c = cfg->log2_capacity;
   t->log2_min = cfg->log2_capacity;
   e = launch_fill_zero(t->cells, nb, t->launch, s);
+  if (e == hipSuccess && cfg->full_keys) {
+    t->special = (SpecialSlots *)dev_alloc(t, sizeof(SpecialSlots), s);
+    t->special_scratch = (uint32_t *)dev_alloc(t, kSpecialScratchBytes, s);
+    if (!t->special || !t->special_scratch) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) e = launch_fill_zero(t->special, sizeof(SpecialSlots), t->launch, s);
+    if (e == hipSuccess) e = launch_fill_zero(t->special_scratch, kSpecialScratchBytes, t->launch, s);
+  }
   if (e != hipSuccess) {
+    if (t->special) dev_free(t, t->special, sizeof(SpecialSlots), s);
+    if (t->special_scratch) dev_free(t, t->special_scratch, kSpecialScratchBytes, s);
     dev_free(t, t->cells, nb, s);
     dev_free(t, t->status, sizeof(DevStatus), s);
     delete t;
@@ -632,6 +646,7 @@ int lpht_clear(lpht_table *t, void *stream) {
   if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
   hipError_t e = launch_fill_zero(t->cells, (size_t)cell_bytes(t->cfg.layout) << t->log2c, t->launch, s);
   if (e == hipSuccess) e = launch_set_status(t->status, 0, 0, 1, s);
+  if (e == hipSuccess && t->special) e = launch_fill_zero(t->special, sizeof(SpecialSlots), t->launch, s);
   if (e != hipSuccess) return from_hip(e);
   t->known_used = t->known_live = 0;
   t->pending = 0;
@@ -645,6 +660,8 @@ int lpht_destroy(lpht_table *t, void *stream) {
   (void)hipSetDevice(t->device);
   dev_free(t, t->cells, (size_t)cell_bytes(t->cfg.layout) << t->log2c, s);
   dev_free(t, t->status, sizeof(DevStatus), s);
+  if (t->special) dev_free(t, t->special, sizeof(SpecialSlots), s);
+  if (t->special_scratch) dev_free(t, t->special_scratch, kSpecialScratchBytes, s);
   for (auto &tm : t->timed) {
     (void)hipEventDestroy(tm.start);
     (void)hipEventDestroy(tm.stop);
@@ -748,6 +765,13 @@ int bulk_merge(lpht_table *t, const void *keys, const void *vals, uint64_t n, ui
   t->pending = 0;
   t->mods_since_exact = 0;
   t->stats.bulk_merges++;
+  if (t->special) {
+    // the batch's keys 0 and 1, in index order, on the special slots (a
+    // build starts them empty)
+    e = launch_special(t->cfg.layout, OP_UPSERT, op, keys, vals, n, nullptr, nullptr, t->special,
+                       t->special_scratch, !keep_old, s);
+    if (e != hipSuccess) return from_hip(e);
+  }
   return LPHT_OK;
 }
 
@@ -844,6 +868,11 @@ int lpht_insert_async(lpht_table *t, const void *keys, const void *vals, uint64_
     t->log2c += fin;
   }
   t->stats.async_growths += fin;
+  if (t->special) {
+    e = launch_special(t->cfg.layout, add ? OP_UPSERT : OP_INSERT, add ? LPHT_ADD : LPHT_ASSIGN, keys, vals, n,
+                       nullptr, flags, t->special, t->special_scratch, false, s);
+    if (e != hipSuccess) return from_hip(e);
+  }
   // exact counts of the result
   e = launch_set_status(t->status, 0, 0, 0, s);
   if (e == hipSuccess) e = launch_recount(t->cells, t->log2c, t->cfg.layout, t->status, t->launch, s);
@@ -868,8 +897,16 @@ int lpht_count(lpht_table *t, uint64_t *used, uint64_t *live, void *stream) {
   if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
   int rc = sync_counts(t, (hipStream_t)stream);
   if (rc) return rc;
-  if (used) *used = t->known_used;
-  if (live) *live = t->known_live;
+  uint64_t sp = 0;
+  if (t->special) {
+    unsigned long long pr[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(pr, t->special, sizeof(pr), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return from_hip(e);
+    sp = pr[0] + pr[1];
+  }
+  if (used) *used = t->known_used + sp;
+  if (live) *live = t->known_live + sp;
   return LPHT_OK;
 }
 
@@ -935,7 +972,7 @@ int lpht_status(lpht_table *t, void *stream) {
     if (e != hipSuccess) return from_hip(e);
   }
   if (h.err & kErrFull) return LPHT_ERR_FULL;
-  if (h.err & kErrReserved) return LPHT_ERR_RESERVED_KEY;
+  if ((h.err & kErrReserved) && !t->special) return LPHT_ERR_RESERVED_KEY;
   return LPHT_OK;
 }
 

@@ -9,6 +9,10 @@
 #include "../../include/lpht.h"
 #include "lpht_internal.h"
 
+namespace lpht {
+struct SpecialSlots;
+}
+
 struct MigTiming {
   hipEvent_t start, stop;
 };
@@ -30,6 +34,9 @@ struct lpht_table {
   lpht_tuning tuning;
   lpht::LaunchCfg launch;
   lpht_stats stats;
+  // full key space: the slots of keys 0 and 1, and the per-call list scratch
+  lpht::SpecialSlots *special;
+  uint32_t *special_scratch;
   int timing;
   std::vector<MigTiming> timed;
 };

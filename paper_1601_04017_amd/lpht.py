@@ -46,7 +46,7 @@ class lpht_config(ctypes.Structure):
         ("max_fill_num", ctypes.c_uint32),
         ("max_fill_den", ctypes.c_uint32),
         ("auto_grow", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("full_keys", ctypes.c_uint32),
         ("alloc", _ALLOC_FN),
         ("free", _FREE_FN),
         ("alloc_ctx", ctypes.c_void_p),
@@ -200,7 +200,8 @@ class Table:
     """One device table.  Methods map one-to-one onto the C ABI calls."""
 
     def __init__(self, layout: int = KV64, log2_capacity: int = 12, auto_grow: bool = False,
-                 seed_hi: int = SEED_HI, seed_lo: int = SEED_LO, alpha=(1, 2), stream=None):
+                 seed_hi: int = SEED_HI, seed_lo: int = SEED_LO, alpha=(1, 2), stream=None,
+                 full_keys: bool = False):
         import torch
         L = load()
         self.layout = layout
@@ -214,6 +215,7 @@ class Table:
         cfg.seed_lo = seed_lo
         cfg.max_fill_num, cfg.max_fill_den = alpha
         cfg.auto_grow = 1 if auto_grow else 0
+        cfg.full_keys = 1 if full_keys else 0
         h = ctypes.c_void_p()
         self._stream = stream
         _check(L.lpht_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)), "lpht_create")
