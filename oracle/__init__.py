@@ -88,6 +88,21 @@ def load(path):
     L.orc_grow.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
     L.orc_migrate.restype = ctypes.c_int
     L.orc_migrate.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    L.orc_str_hash.restype = ctypes.c_uint64
+    L.orc_str_hash.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+    L.orc_str_create.restype = ctypes.c_void_p
+    L.orc_str_create.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_uint32, ctypes.c_int]
+    L.orc_str_destroy.argtypes = [ctypes.c_void_p]
+    L.orc_str_capacity.restype = ctypes.c_uint64
+    L.orc_str_capacity.argtypes = [ctypes.c_void_p]
+    L.orc_str_counts.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+    L.orc_str_bulk.restype = ctypes.c_int
+    L.orc_str_bulk.argtypes = [ctypes.c_void_p, ctypes.c_int, u8p, u8p, ctypes.c_uint64, u8p, ctypes.c_int, u8p, u8p]
+    L.orc_str_grow.restype = ctypes.c_int
+    L.orc_str_grow.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    L.orc_str_cell.restype = ctypes.c_int64
+    L.orc_str_cell.argtypes = [ctypes.c_void_p, ctypes.c_uint64, u8p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     L.orc_set_full_keys.restype = ctypes.c_int
     L.orc_set_full_keys.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.orc_bulk_merge.restype = ctypes.c_int
@@ -246,3 +261,83 @@ class OracleTable:
         rc = lib().orc_bulk_merge(self._t, _ptr(keys), _ptr(vals), keys.size, op, keep_old)
         if rc:
             raise RuntimeError(f"orc_bulk_merge failed: {rc}")
+
+
+def pack_strings(strings):
+    """A list of bytes -> (bytes buffer u8, offsets u64 with n + 1 entries)."""
+    offs = np.zeros(len(strings) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(x) for x in strings], dtype=np.uint64)
+    buf = np.frombuffer(b"".join(strings), dtype=np.uint8).copy() if strings else np.zeros(0, dtype=np.uint8)
+    if buf.size == 0:
+        buf = np.zeros(1, dtype=np.uint8)
+    return buf, offs
+
+
+def str_hash(s: bytes, seed_hi: int = SEED_HI, seed_lo: int = SEED_LO) -> int:
+    b = np.frombuffer(s, dtype=np.uint8).copy() if s else np.zeros(1, dtype=np.uint8)
+    return lib().orc_str_hash(b.ctypes.data, len(s), seed_hi, seed_lo)
+
+
+class OracleStrTable:
+    """Sequential linear-probing table with byte-string keys and u64 values."""
+
+    def __init__(self, log2c: int, seed_hi: int = SEED_HI, seed_lo: int = SEED_LO, alpha=(1, 2),
+                 auto_grow: bool = False):
+        self._t = lib().orc_str_create(log2c, seed_hi, seed_lo, alpha[0], alpha[1], 1 if auto_grow else 0)
+        if not self._t:
+            raise ValueError("oracle table creation failed")
+
+    def __del__(self):
+        t = getattr(self, "_t", None)
+        if t and lib is not None:
+            lib().orc_str_destroy(t)
+            self._t = None
+
+    @property
+    def capacity(self) -> int:
+        return lib().orc_str_capacity(self._t)
+
+    def counts(self):
+        u, l = ctypes.c_uint64(), ctypes.c_uint64()
+        lib().orc_str_counts(self._t, ctypes.byref(u), ctypes.byref(l))
+        return u.value, l.value
+
+    def _bulk(self, kind, strings, vals=None, op=ASSIGN):
+        buf, offs = pack_strings(strings)
+        n = len(strings)
+        v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint64)
+        out = np.zeros(max(n, 1), dtype=np.uint64)
+        flags = np.zeros(max(n, 1), dtype=np.uint8)
+        rc = lib().orc_str_bulk(self._t, kind, buf.ctypes.data, offs.ctypes.data, n,
+                                None if v is None else v.ctypes.data, op, out.ctypes.data, flags.ctypes.data)
+        if rc:
+            raise RuntimeError(f"orc_str_bulk failed: {rc}")
+        return flags[:n], out[:n]
+
+    def insert(self, strings, vals=None):
+        return self._bulk(0, strings, vals)[0]
+
+    def insert_or_update(self, strings, vals=None, op=ADD):
+        return self._bulk(1, strings, vals, op)[0]
+
+    def find(self, strings):
+        f, v = self._bulk(2, strings)
+        return v, f
+
+    def erase(self, strings):
+        return self._bulk(3, strings)[0]
+
+    def grow(self, log2_new: int):
+        rc = lib().orc_str_grow(self._t, log2_new)
+        if rc:
+            raise RuntimeError(f"orc_str_grow failed: {rc}")
+
+    def cells(self):
+        """Per cell: None (empty), False (tombstone) or (key bytes, value)."""
+        out = []
+        buf = np.zeros(1 << 16, dtype=np.uint8)
+        for i in range(self.capacity):
+            v = ctypes.c_uint64()
+            ln = lib().orc_str_cell(self._t, i, buf.ctypes.data, buf.size, ctypes.byref(v))
+            out.append(None if ln == -1 else False if ln == -2 else (bytes(buf[:ln]), v.value))
+        return out

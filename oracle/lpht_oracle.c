@@ -673,3 +673,214 @@ void orc_hash_bulk(const void *keys, uint64_t n, int key_bytes, uint32_t seed_hi
     out[i] = orc_hash(k, key_bytes, seed_hi, seed_lo);
   }
 }
+
+/* ------------------------------------------------------------------------- */
+/* String keys (Sec. 5.7, "Complex Keys"): the same linear-probing table     */
+/* whose keys are byte strings.  The oracle keeps its own copies of the       */
+/* strings; a cell holds 0 (empty), 1 (tombstone) or 2 + the index of the     */
+/* string, and a value.  The hash of a string is the pair of CRC-32C register */
+/* updates over its bytes with the two seeds (Sec. 8.3), as for word keys.    */
+/* ------------------------------------------------------------------------- */
+
+typedef struct orc_str_table {
+  uint32_t log2c, log2_min;
+  uint64_t cap;
+  uint64_t *ref; /* per cell */
+  uint64_t *val;
+  uint32_t seed_hi, seed_lo;
+  uint32_t alpha_num, alpha_den;
+  int auto_grow;
+  uint64_t used, live;
+  uint8_t **str;
+  uint64_t *len;
+  uint64_t nstr, strcap;
+} orc_str_table;
+
+uint64_t orc_str_hash(const uint8_t *s, uint64_t len, uint32_t seed_hi, uint32_t seed_lo) {
+  return ((uint64_t)orc_crc32c_bytes(seed_hi, s, len) << 32) | orc_crc32c_bytes(seed_lo, s, len);
+}
+
+orc_str_table *orc_str_create(uint32_t log2c, uint32_t seed_hi, uint32_t seed_lo, uint32_t alpha_num,
+                              uint32_t alpha_den, int auto_grow) {
+  if (log2c < 1 || log2c > 40 || alpha_num == 0 || alpha_den == 0 || alpha_num > alpha_den) return NULL;
+  orc_str_table *t = (orc_str_table *)calloc(1, sizeof(orc_str_table));
+  if (!t) return NULL;
+  t->log2c = t->log2_min = log2c;
+  t->cap = 1ull << log2c;
+  t->ref = (uint64_t *)calloc(t->cap, sizeof(uint64_t));
+  t->val = (uint64_t *)calloc(t->cap, sizeof(uint64_t));
+  t->seed_hi = seed_hi;
+  t->seed_lo = seed_lo;
+  t->alpha_num = alpha_num;
+  t->alpha_den = alpha_den;
+  t->auto_grow = auto_grow;
+  return t;
+}
+
+void orc_str_destroy(orc_str_table *t) {
+  if (!t) return;
+  for (uint64_t i = 0; i < t->nstr; ++i) free(t->str[i]);
+  free(t->str);
+  free(t->len);
+  free(t->ref);
+  free(t->val);
+  free(t);
+}
+
+uint64_t orc_str_capacity(const orc_str_table *t) { return t->cap; }
+void orc_str_counts(const orc_str_table *t, uint64_t *used, uint64_t *live) {
+  *used = t->used;
+  *live = t->live;
+}
+
+static uint64_t str_home(const orc_str_table *t, const uint8_t *s, uint64_t len, uint32_t log2c) {
+  return orc_home(orc_str_hash(s, len, t->seed_hi, t->seed_lo), log2c);
+}
+
+static int str_eq(const orc_str_table *t, uint64_t r, const uint8_t *s, uint64_t len) {
+  uint64_t i = r - 2;
+  return t->len[i] == len && (len == 0 || memcmp(t->str[i], s, len) == 0);
+}
+
+static int64_t str_keep(orc_str_table *t, const uint8_t *s, uint64_t len) {
+  if (t->nstr == t->strcap) {
+    uint64_t nc = t->strcap ? 2 * t->strcap : 64;
+    uint8_t **ns = (uint8_t **)realloc(t->str, nc * sizeof(uint8_t *));
+    if (!ns) return -1;
+    t->str = ns;
+    uint64_t *nl = (uint64_t *)realloc(t->len, nc * sizeof(uint64_t));
+    if (!nl) return -1;
+    t->len = nl;
+    t->strcap = nc;
+  }
+  uint8_t *c = (uint8_t *)malloc(len ? len : 1);
+  if (!c) return -1;
+  if (len) memcpy(c, s, len);
+  t->str[t->nstr] = c;
+  t->len[t->nstr] = len;
+  return (int64_t)(t->nstr++);
+}
+
+/* One operation: kind 0 insert, 1 insert-or-update (op), 2 find, 3 erase. */
+static uint8_t str_op(orc_str_table *t, int kind, const uint8_t *s, uint64_t len, uint64_t d, int op,
+                      uint64_t *out) {
+  uint64_t i = str_home(t, s, len, t->log2c);
+  if (out) *out = 0;
+  for (uint64_t probes = 0; probes < t->cap; ++probes) {
+    uint64_t r = t->ref[i];
+    if (r == 0) {
+      if (kind >= 2) return 0;
+      int64_t x = str_keep(t, s, len);
+      if (x < 0) return ORC_FLAG_FULL;
+      t->ref[i] = (uint64_t)x + 2;
+      t->val[i] = d;
+      t->used++;
+      t->live++;
+      return 1;
+    }
+    if (r != 1 && str_eq(t, r, s, len)) {
+      if (kind == 1) t->val[i] = (op == ORC_ADD) ? t->val[i] + d : d;
+      if (kind == 2 && out) *out = t->val[i];
+      if (kind == 3) {
+        t->ref[i] = 1;
+        t->live--;
+        return 1;
+      }
+      return kind == 2 ? 1 : 0;
+    }
+    i = (i + 1) & (t->cap - 1);
+  }
+  return kind >= 2 ? 0 : ORC_FLAG_FULL;
+}
+
+/* The sequential migration of the word table, for string keys. */
+static int str_migrate(orc_str_table *t, uint32_t log2_new) {
+  uint64_t nc = 1ull << log2_new;
+  if (t->live >= nc) return -3;
+  uint64_t *nr = (uint64_t *)calloc(nc, sizeof(uint64_t));
+  uint64_t *nv = (uint64_t *)calloc(nc, sizeof(uint64_t));
+  if (!nr || !nv) {
+    free(nr);
+    free(nv);
+    return -2;
+  }
+  uint64_t start = 0;
+  for (uint64_t i = 0; i < t->cap; ++i)
+    if (t->ref[i] == 0) {
+      start = (i + 1) & (t->cap - 1);
+      break;
+    }
+  uint64_t moved = 0;
+  for (uint64_t q = 0; q < t->cap; ++q) {
+    uint64_t i = (start + q) & (t->cap - 1);
+    uint64_t r = t->ref[i];
+    if (r < 2) continue;
+    uint64_t p = str_home(t, t->str[r - 2], t->len[r - 2], log2_new);
+    while (nr[p] != 0) p = (p + 1) & (nc - 1);
+    nr[p] = r;
+    nv[p] = t->val[i];
+    ++moved;
+  }
+  free(t->ref);
+  free(t->val);
+  t->ref = nr;
+  t->val = nv;
+  t->cap = nc;
+  t->log2c = log2_new;
+  t->used = t->live = moved;
+  return 0;
+}
+
+/* The word table's growth rule before a batch of b insertions. */
+static int str_grow_before(orc_str_table *t, uint64_t b) {
+  if (!t->auto_grow || b == 0) return 0;
+  if ((unsigned __int128)(t->used + b) * t->alpha_den <= (unsigned __int128)t->cap * t->alpha_num) return 0;
+  if ((unsigned __int128)(t->live + b) * 2 * t->alpha_den <= (unsigned __int128)t->cap * t->alpha_num) {
+    uint32_t target = t->log2c;
+    while (target > t->log2_min &&
+           (unsigned __int128)(t->live + b) * 4 * t->alpha_den <= ((unsigned __int128)1 << target) * t->alpha_num)
+      --target;
+    return str_migrate(t, target);
+  }
+  uint32_t target = t->log2c;
+  do {
+    ++target;
+  } while ((unsigned __int128)(t->live + b) * t->alpha_den > ((unsigned __int128)1 << target) * t->alpha_num);
+  while (t->log2c < target) {
+    int rc = str_migrate(t, t->log2c + 1);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+/* Bulk calls: string i is bytes[offsets[i] .. offsets[i+1]); vals may be
+ * NULL (every value 1).  kind: 0 insert, 1 insert-or-update with op, 2 find
+ * (vals_out), 3 erase. */
+int orc_str_bulk(orc_str_table *t, int kind, const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                 const uint64_t *vals, int op, uint64_t *vals_out, uint8_t *flags) {
+  if (kind <= 1) {
+    int rc = str_grow_before(t, n);
+    if (rc) return rc;
+  }
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t v = 0;
+    uint8_t f = str_op(t, kind, bytes + offsets[i], offsets[i + 1] - offsets[i], vals ? vals[i] : 1, op, &v);
+    if (flags) flags[i] = f;
+    if (vals_out) vals_out[i] = v;
+  }
+  return 0;
+}
+
+int orc_str_grow(orc_str_table *t, uint32_t log2_new) { return str_migrate(t, log2_new); }
+
+/* Cell i: -1 empty, -2 tombstone, else the stored string's length, copied to
+ * buf (up to cap bytes), and its value. */
+int64_t orc_str_cell(const orc_str_table *t, uint64_t i, uint8_t *buf, uint64_t cap, uint64_t *val) {
+  uint64_t r = t->ref[i];
+  *val = t->val[i];
+  if (r == 0) return -1;
+  if (r == 1) return -2;
+  uint64_t len = t->len[r - 2];
+  if (buf && len) memcpy(buf, t->str[r - 2], len < cap ? len : cap);
+  return (int64_t)len;
+}

@@ -13,6 +13,7 @@ from tests import test_oracle_bulk as TB
 from tests import test_oracle_fullkeys as TF
 from tests import test_oracle_hash as TH
 from tests import test_oracle_migration as TM
+from tests import test_oracle_strings as TS
 from tests import test_oracle_table as TT
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lpht_oracle.c")
@@ -45,6 +46,11 @@ MUTANTS = [
     ("special_erase_keeps_key", "op_erase", "t->sp_present[k] = 0;", ";"),
     ("special_upsert_assigns", "sp_insert", "if (is_upsert) t->sp_val[k] = apply_up(t, t->sp_val[k], v, op);",
      "if (is_upsert) t->sp_val[k] = v;"),
+    ("string_prefix_equal", "str_eq", "return t->len[i] == len && (len == 0 || memcmp(t->str[i], s, len) == 0);",
+     "return len <= t->len[i] && (len == 0 || memcmp(t->str[i], s, len) == 0);"),
+    ("string_find_stops_at_tombstone", "str_op", "if (r != 1 && str_eq(t, r, s, len)) {",
+     "if (r == 1 && kind >= 2) return 0;\n    if (r != 1 && str_eq(t, r, s, len)) {"),
+    ("string_hash_one_seed", "orc_str_hash", "orc_crc32c_bytes(seed_lo, s, len)", "orc_crc32c_bytes(seed_hi, s, len)"),
     ("bulk_keeps_first", "orc_bulk_merge", ": it[i].v;", ": it[d - 1].v;"),
     ("bulk_sorted_by_key", "item_cmp", "if (x->h != y->h) return x->h < y->h ? -1 : 1;",
      "if (x->k != y->k) return x->k < y->k ? -1 : 1;"),
@@ -98,6 +104,10 @@ def _pins():
         for seed in range(3):
             yield lambda layout=layout, seed=seed: TF.test_sequences_with_keys_0_and_1_match_dict_model(layout, seed)
         yield lambda layout=layout: TF.test_special_keys_survive_migration_and_follow_bulk_rules(layout)
+    yield TS.test_string_hash_equals_word_hash_and_seed_closed_form
+    for seed in range(3):
+        yield lambda seed=seed: TS.test_sequences_match_dict_model(seed)
+    yield TS.test_occupancy_independent_of_order_and_migration
 
 
 @pytest.mark.parametrize("name,func,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
