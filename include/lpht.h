@@ -483,6 +483,64 @@ const char *lpht_strerror(int code);
 /* Library version string. */
 const char *lpht_version(void);
 
+/* ---- string keys (Sec. 5.7, "Complex Keys") ----
+ *
+ * A table whose keys are byte strings (any length, the empty string
+ * included) and whose values are u64.  The table manages a byte pool for the
+ * keys: a cell holds a reference word, (signature << 48) | pool offset, and
+ * the value; the signature is the low 16 bits of the key's 64-bit hash (bits
+ * the position does not use), so a probe compares signatures before it
+ * follows a reference.  The hash is the pair of CRC-32C register updates
+ * over the key's bytes with the two seeds (Sec. 8.3) -- an 8-byte key hashes
+ * like the same word in a KV64 table.  A batch of n keys is a byte array and
+ * n + 1 u64 offsets (key i = bytes[offsets[i] .. offsets[i + 1])), both
+ * device memory; offsets must be non-decreasing.  Within a call operations
+ * run concurrently (as for word keys).  Erased keys' bytes stay in the pool
+ * until a migration, which copies only live keys into a new pool; a
+ * migration also happens when an inserting call might not fit the pool
+ * (records take length + 4 bytes rounded up to 8).  Inserting calls read
+ * offsets[0] and offsets[n] back (one synchronisation). */
+typedef struct lpht_str_table lpht_str_table;
+
+typedef struct lpht_str_config {
+  uint32_t log2_capacity; /* 6..34 */
+  uint32_t auto_grow;     /* the word tables' growth rule (including cleanup and shrink) */
+  uint32_t seed_hi, seed_lo;
+  uint32_t max_fill_num, max_fill_den;
+  uint32_t reserved[2];   /* must be 0 */
+  uint64_t pool_bytes;    /* initial key pool (>= 64) */
+} lpht_str_config;
+
+/* log2_capacity 12, seeds as lpht_config_default, alpha = 1/2, no growth,
+ * a 1 MiB pool. */
+void lpht_str_config_default(lpht_str_config *cfg);
+int lpht_str_create(const lpht_str_config *cfg, void *stream, lpht_str_table **out);
+int lpht_str_destroy(lpht_str_table *t, void *stream);
+/* insert: flag 1 = inserted, 0 = present (its value unchanged), 0xFF = no
+ * room (sticky FULL, lpht_str_status); vals may be NULL (1 each). */
+int lpht_str_insert(lpht_str_table *t, const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                    const uint64_t *vals, uint8_t *flags, void *stream);
+/* insertOrUpdate with up = LPHT_ASSIGN or LPHT_ADD (value + d mod 2^64). */
+int lpht_str_insert_or_update(lpht_str_table *t, const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                              const uint64_t *vals, uint32_t up, uint8_t *flags, void *stream);
+/* find: found[i] 1/0, vals_out[i] the value or 0 (either may be NULL). */
+int lpht_str_find(lpht_str_table *t, const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                  uint64_t *vals_out, uint8_t *found, void *stream);
+/* erase by tombstone: flag 1 for the operation that erased the key. */
+int lpht_str_erase(lpht_str_table *t, const uint8_t *bytes, const uint64_t *offsets, uint64_t n, uint8_t *flags,
+                   void *stream);
+/* Exact counts (non-empty cells, live keys); synchronises. */
+int lpht_str_count(lpht_str_table *t, uint64_t *used, uint64_t *live, void *stream);
+int lpht_str_capacity(lpht_str_table *t, uint64_t *cells, uint64_t *pool_used, uint64_t *pool_cap, void *stream);
+/* Migration into 2^log2 cells (larger, equal or smaller), compacting the
+ * pool.  Errors: INVALID, FULL (live keys would not leave an empty cell). */
+int lpht_str_grow(lpht_str_table *t, uint32_t log2_new_capacity, void *stream);
+/* Copies the cells (16 bytes each) and up to pool_dst_bytes of the pool
+ * (device destinations). */
+int lpht_str_export(lpht_str_table *t, void *cells_dst, void *pool_dst, uint64_t pool_dst_bytes, void *stream);
+/* Sticky error (LPHT_ERR_FULL after an insertion found no room), cleared. */
+int lpht_str_status(lpht_str_table *t, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblpht.so")
 
@@ -165,7 +167,7 @@ def load(path: str = LIB_PATH):
 
 
 def exported_symbols():
-    return list(_SIGS)
+    return list(_SIGS) + list(_STR_SIGS)
 
 
 class LphtError(RuntimeError):
@@ -477,6 +479,166 @@ class Batch:
             arr[j].kind_sel = o.get("kind_sel", 0)
             arr[j].count_sel = o.get("count_sel", 0)
         _check(load().lpht_batch_run(self._h, arr, len(ops), _stream_handle(stream)), "lpht_batch_run")
+
+
+# ---------------------------------------------------------------- string keys
+
+class lpht_str_config(ctypes.Structure):
+    _fields_ = [
+        ("log2_capacity", ctypes.c_uint32),
+        ("auto_grow", ctypes.c_uint32),
+        ("seed_hi", ctypes.c_uint32),
+        ("seed_lo", ctypes.c_uint32),
+        ("max_fill_num", ctypes.c_uint32),
+        ("max_fill_den", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 2),
+        ("pool_bytes", ctypes.c_uint64),
+    ]
+
+
+_STR_SIGS = {
+    "lpht_str_config_default": (None, [ctypes.POINTER(lpht_str_config)]),
+    "lpht_str_create": (ctypes.c_int, [ctypes.POINTER(lpht_str_config), _VP, ctypes.POINTER(_VP)]),
+    "lpht_str_destroy": (ctypes.c_int, [_VP, _VP]),
+    "lpht_str_insert": (ctypes.c_int, [_VP, _VP, _VP, _U64, _VP, _VP, _VP]),
+    "lpht_str_insert_or_update": (ctypes.c_int, [_VP, _VP, _VP, _U64, _VP, _U32, _VP, _VP]),
+    "lpht_str_find": (ctypes.c_int, [_VP, _VP, _VP, _U64, _VP, _VP, _VP]),
+    "lpht_str_erase": (ctypes.c_int, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    "lpht_str_count": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
+    "lpht_str_capacity": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
+    "lpht_str_grow": (ctypes.c_int, [_VP, _U32, _VP]),
+    "lpht_str_export": (ctypes.c_int, [_VP, _VP, _VP, _U64, _VP]),
+    "lpht_str_status": (ctypes.c_int, [_VP, _VP]),
+}
+
+
+def _str_lib():
+    L = load()
+    if not getattr(L, "_str_declared", False):
+        for name, (res, args) in _STR_SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        L._str_declared = True
+    return L
+
+
+def pack_strings(strings, device="cuda"):
+    """A list of bytes -> (device u8 tensor, device int64 offsets of n + 1)."""
+    import torch
+    offs = np.zeros(len(strings) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(x) for x in strings], dtype=np.int64)
+    raw = b"".join(strings) or b"\0"
+    buf = torch.from_numpy(np.frombuffer(raw, dtype=np.uint8).copy()).to(device)
+    return buf, torch.from_numpy(offs).to(device)
+
+
+class StrTable:
+    """A table with byte-string keys and u64 values (lpht_str_*)."""
+
+    def __init__(self, log2_capacity: int = 12, auto_grow: bool = False, pool_bytes: int = 1 << 20,
+                 seed_hi: int = SEED_HI, seed_lo: int = SEED_LO, alpha=(1, 2), stream=None):
+        L = _str_lib()
+        cfg = lpht_str_config()
+        L.lpht_str_config_default(ctypes.byref(cfg))
+        cfg.log2_capacity = log2_capacity
+        cfg.auto_grow = 1 if auto_grow else 0
+        cfg.pool_bytes = pool_bytes
+        cfg.seed_hi, cfg.seed_lo = seed_hi, seed_lo
+        cfg.max_fill_num, cfg.max_fill_den = alpha
+        h = ctypes.c_void_p()
+        self._stream = stream
+        _check(L.lpht_str_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)), "lpht_str_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _str_lib().lpht_str_destroy(self._h, _stream_handle(self._stream))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _run(self, name, strings, *extra):
+        import torch
+        buf, offs = pack_strings(strings)
+        n = len(strings)
+        flags = torch.zeros(max(n, 1), dtype=torch.uint8, device="cuda")
+        out = torch.zeros(max(n, 1), dtype=torch.int64, device="cuda")
+        args = [self._h, _ptr(buf), _ptr(offs), n]
+        if name == "lpht_str_find":
+            args += [_ptr(out), _ptr(flags)]
+        else:
+            args += list(extra) + [_ptr(flags)]
+        _check(getattr(_str_lib(), name)(*args, _stream_handle(self._stream)), name)
+        return flags[:n].cpu().numpy(), out[:n].cpu().numpy().view(np.uint64)
+
+    def _vals(self, vals):
+        import torch
+        if vals is None:
+            return None, None
+        t = torch.from_numpy(np.ascontiguousarray(vals, dtype=np.uint64).view(np.int64)).cuda()
+        return t, _ptr(t)
+
+    def insert(self, strings, vals=None):
+        keep, vp = self._vals(vals)
+        return self._run("lpht_str_insert", strings, vp)[0]
+
+    def insert_or_update(self, strings, vals=None, op=ADD):
+        keep, vp = self._vals(vals)
+        return self._run("lpht_str_insert_or_update", strings, vp, op)[0]
+
+    def find(self, strings):
+        f, v = self._run("lpht_str_find", strings)
+        return v, f
+
+    def erase(self, strings):
+        return self._run("lpht_str_erase", strings)[0]
+
+    def count(self):
+        u, l = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_str_lib().lpht_str_count(self._h, ctypes.byref(u), ctypes.byref(l), _stream_handle(self._stream)),
+               "lpht_str_count")
+        return u.value, l.value
+
+    def capacity(self):
+        c, pu, pc = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_str_lib().lpht_str_capacity(self._h, ctypes.byref(c), ctypes.byref(pu), ctypes.byref(pc),
+                                            _stream_handle(self._stream)), "lpht_str_capacity")
+        return c.value, pu.value, pc.value
+
+    def grow(self, log2_new: int):
+        _check(_str_lib().lpht_str_grow(self._h, log2_new, _stream_handle(self._stream)), "lpht_str_grow")
+
+    def status(self) -> int:
+        return _str_lib().lpht_str_status(self._h, _stream_handle(self._stream))
+
+    def cells(self):
+        """Per cell: None (empty), False (tombstone) or (key bytes, value),
+        decoded from the exported cells and pool."""
+        import torch
+        c, pu, _ = self.capacity()
+        cells = torch.zeros(2 * c, dtype=torch.int64, device="cuda")
+        pool = torch.zeros(max(pu, 8), dtype=torch.uint8, device="cuda")
+        _check(_str_lib().lpht_str_export(self._h, _ptr(cells), _ptr(pool), pool.numel(),
+                                          _stream_handle(self._stream)), "lpht_str_export")
+        w = cells.cpu().numpy().view(np.uint64)
+        pb = pool.cpu().numpy().tobytes()
+        out = []
+        for i in range(c):
+            r = int(w[2 * i])
+            if r == 0:
+                out.append(None)
+            elif r == 1:
+                out.append(False)
+            else:
+                off = r & ((1 << 48) - 1)
+                ln = int.from_bytes(pb[off:off + 4], "little")
+                out.append((pb[off + 4:off + 4 + ln], int(w[2 * i + 1])))
+        return out
 
 
 # ---------------------------------------------------------------- serving

@@ -87,7 +87,7 @@ def test_struct_layouts_match_header(tmp_path):
              ("lpht_stats", lpht.lpht_stats), ("lpht_autotune_report", lpht.lpht_autotune_report),
              ("lpht_batch_op", lpht.lpht_batch_op), ("lpht_server_config", lpht.lpht_server_config),
              ("lpht_request", lpht.lpht_request), ("lpht_completion", lpht.lpht_completion),
-             ("lpht_server_stats", lpht.lpht_server_stats)]
+             ("lpht_server_stats", lpht.lpht_server_stats), ("lpht_str_config", lpht.lpht_str_config)]
     sizes = _c_sizes(tmp_path, [c for c, _ in pairs])
     for (cname, py), n in zip(pairs, sizes):
         assert ctypes.sizeof(py) == n, cname

@@ -1,0 +1,132 @@
+"""String keys (Sec. 5.7) on the GPU against the oracle's string table:
+flags, found values and counts per batch, the capacity after every batch
+(the same growth rule), and at the end the occupied cells and each
+cluster's key set (concurrent insertion orders keys inside clusters
+differently)."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def _pool(rng, universe, maxlen):
+    out = set()
+    while len(out) < universe:
+        out.add(bytes(rng.integers(0, 256, int(rng.integers(0, maxlen + 1))).astype(np.uint8)))
+    return sorted(out)
+
+
+def _canon(keys, flags):
+    f = np.array(flags, dtype=np.uint8).copy()
+    seen = {}
+    for i, k in enumerate(keys):
+        if f[i] == 1:
+            f[i] = 0
+            seen.setdefault(k, i)
+    first = {}
+    for i, k in enumerate(keys):
+        first.setdefault(k, i)
+    for k, i in seen.items():
+        f[first[k]] = 1
+    return f
+
+
+def _clusters(cells):
+    c = len(cells)
+    occ = [x is not None for x in cells]
+    if all(occ):
+        return [frozenset(x[0] for x in cells if x)]
+    start = occ.index(False)
+    runs, cur = [], set()
+    for q in range(1, c + 1):
+        i = (start + q) % c
+        if cells[i] is None:
+            if cur:
+                runs.append(frozenset(cur))
+            cur = set()
+        elif cells[i]:
+            cur.add(cells[i][0])
+    return sorted(runs, key=lambda s: sorted(s))
+
+
+def _same_table(g, o):
+    gc, oc = g.cells(), o.cells()
+    assert [x is not None for x in gc] == [x is not None for x in oc]
+    assert _clusters(gc) == _clusters(oc)
+    assert {x[0]: x[1] for x in gc if x} == {x[0]: x[1] for x in oc if x}
+
+
+@pytest.mark.parametrize("seed,maxlen", [(1, 8), (2, 40), (3, 200)])
+def test_operation_sequences_match_oracle(seed, maxlen):
+    from paper_1601_04017_amd import lpht
+    rng = np.random.default_rng(seed)
+    pool = _pool(rng, 3000, maxlen) + [b""]
+    g = lpht.StrTable(log2_capacity=8, auto_grow=True, pool_bytes=4096)
+    o = oracle.OracleStrTable(8, auto_grow=True)
+    for step in range(24):
+        n = int(rng.integers(1, 2500))
+        keys = [pool[i] for i in rng.integers(0, len(pool), n)]
+        kind = step % 4
+        vals = rng.integers(0, 1 << 62, n).astype(np.uint64)
+        if kind == 0:
+            # equal concurrent inserts: one wins, which value is unspecified
+            uniq = list(dict.fromkeys(keys))
+            vals = vals[: len(uniq)]
+            gf = g.insert(uniq, vals)
+            of = o.insert(uniq, vals)
+            assert np.array_equal(gf, of)
+        elif kind == 1:
+            gf = g.insert_or_update(keys, vals, oracle.ADD)
+            of = o.insert_or_update(keys, vals, oracle.ADD)
+            assert np.array_equal(_canon(keys, gf), of)
+        elif kind == 2:
+            gv, gf = g.find(keys)
+            ov, of = o.find(keys)
+            assert np.array_equal(gf, of) and np.array_equal(gv, ov)
+        else:
+            uniq = list(dict.fromkeys(keys))[: n // 2]
+            gf = g.erase(uniq)
+            of = o.erase(uniq)
+            assert np.array_equal(gf, of)
+        assert g.count() == o.counts(), step
+        assert g.capacity()[0] == o.capacity, step
+    assert g.status() == 0
+    _same_table(g, o)
+
+
+def test_signature_collisions_and_pool_compaction():
+    from paper_1601_04017_amd import lpht
+    # keys whose 16-bit signatures (low hash bits) are equal
+    rng = np.random.default_rng(7)
+    by_sig = {}
+    for i in range(200_000):
+        k = b"key-%d" % i
+        by_sig.setdefault(oracle.str_hash(k) & 0xFFFF, []).append(k)
+    coll = [v for v in by_sig.values() if len(v) >= 3][:50]
+    keys = [k for v in coll for k in v]
+    g = lpht.StrTable(log2_capacity=10, auto_grow=True, pool_bytes=256)
+    o = oracle.OracleStrTable(10, auto_grow=True)
+    vals = np.arange(len(keys), dtype=np.uint64) + 1
+    assert np.array_equal(g.insert(keys, vals), o.insert(keys, vals))
+    gv, gf = g.find(keys + [b"absent"])
+    assert gf.tolist() == [1] * len(keys) + [0] and gv[: len(keys)].tolist() == vals.tolist()
+    # erase most keys, then insert new ones: the pool is compacted at the next migration
+    g.erase(keys[: len(keys) - 20])
+    o.erase(keys[: len(keys) - 20])
+    big = [bytes(rng.integers(0, 256, 300).astype(np.uint8)) for _ in range(400)]
+    assert np.array_equal(g.insert(big), o.insert(big))
+    c, pu, pc = g.capacity()
+    assert pu <= pc
+    assert g.count() == o.counts()
+    _same_table(g, o)
+    g.grow(g.capacity()[0].bit_length())  # doubling by hand
+    o.grow(o.capacity.bit_length())
+    _same_table(g, o)
