@@ -157,7 +157,8 @@ def _timed(fn, stream):
     return a.elapsed_time(b)
 
 
-SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "deletion", "bulk", "async", "zipf", "serving")
+SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "deletion", "bulk", "async", "strings", "zipf",
+               "serving")
 
 
 def run_suite(dev, reps=3, parts=SUITE_PARTS):
@@ -201,6 +202,8 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
         out["async_growth_one_call"] = _suite_async(up, reps, dkeys, dvals)
     if need_keys:
         del dkeys, dvals
+    if "strings" in parts:
+        out["string_keys"] = _suite_strings(stream, reps)
     if "zipf" in parts:
         out["zipf_increment"] = _suite_zipf(up, stream, reps)
     if "serving" in parts:
@@ -517,6 +520,51 @@ def _suite_async(up, reps, dkeys, dvals):
         out[name] = row
     del z
     return out
+
+
+def _suite_strings(stream, reps):
+    import torch
+
+    from paper_1601_04017_amd import lpht
+
+    # String keys: 10^7 distinct keys of 8..40 random bytes into a table of
+    # 2^25 cells (alpha = 1/2 leaves it at fill 0.3), then 10^7 successful
+    # and 10^7 unsuccessful finds.
+    log("suite: string keys")
+    n = 10 ** 7
+    rng = np.random.default_rng(77)
+    lens = rng.integers(8, 41, 2 * n)
+    offs = np.zeros(2 * n + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(lens)
+    raw = rng.integers(0, 256, int(offs[-1]), dtype=np.uint8)
+    # make every key distinct: its index in its first 8 bytes
+    view = np.arange(2 * n, dtype=np.uint64).view(np.uint8).reshape(-1, 8)
+    for b in range(8):
+        raw[offs[:-1] + b] = view[:, b]
+    dbytes = torch.from_numpy(raw).cuda()
+    doffs = torch.from_numpy(offs).cuda()
+    L = lpht._str_lib()
+    res = []
+    for r in range(reps + 1):
+        t = lpht.StrTable(log2_capacity=25, pool_bytes=int(offs[n]) + 12 * n + 64)
+        flags = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        vout = torch.zeros(n, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        ins = _timed(lambda: L.lpht_str_insert(t._h, lpht._ptr(dbytes), lpht._ptr(doffs), n, None,
+                                               lpht._ptr(flags), None), stream)
+        hit = _timed(lambda: L.lpht_str_find(t._h, lpht._ptr(dbytes), lpht._ptr(doffs), n, lpht._ptr(vout),
+                                             lpht._ptr(flags), None), stream)
+        miss_offs = doffs[n:]
+        miss = _timed(lambda: L.lpht_str_find(t._h, lpht._ptr(dbytes), lpht._ptr(miss_offs), n,
+                                              lpht._ptr(vout), lpht._ptr(flags), None), stream)
+        assert t.count() == (n, n)
+        if r:
+            res.append((ins, hit, miss))
+        t.close()
+    ins, hit, miss = np.mean(res, axis=0)
+    return {"keys": n, "mean_key_bytes": round(float(lens[:n].mean()), 1), "insert_ms": round(ins, 3),
+            "find_hit_ms": round(hit, 3), "find_miss_ms": round(miss, 3),
+            "insert_mops": round(n / ins / 1e3, 1), "find_hit_mops": round(n / hit / 1e3, 1)}
 
 
 def _suite_zipf(up, stream, reps):
