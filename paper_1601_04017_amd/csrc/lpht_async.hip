@@ -166,8 +166,10 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
   lane0_add(&ctl->arrived, 1);
   if (!wait_ge(&ctl->arrived, 2 * W, ticks)) return false;
   __threadfence();
-  // 3. clusters of the old table, each walked in order by the lane that owns
-  //    its first cell; their target ranges are disjoint (Lemma 1)
+  // 3. every live element of the old table, read lane-consecutively, is
+  //    inserted into the target with compare-and-swap (the target is a valid
+  //    table of the same keys; the order inside clusters is that of the
+  //    insertions)
   const u64 oc = 1ull << o.log2c;
   u64 moved = 0;
   for (;;) {
@@ -176,17 +178,19 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
     if (b0 >= oc) break;
     const u64 b1 = std::min<u64>(oc, b0 + kAsyncMigBlock);
     for (u64 i = b0 + lane; i < b1; i += 64) {
-      if (key_at<L>(o.cells, i) == kEmpty || key_at<L>(o.cells, (i - 1) & o.mask) != kEmpty) continue;
-      for (u64 j = i;; j = (j + 1) & o.mask) {
-        const u64 k = key_at<L>(o.cells, j);
-        if (k == kEmpty) break;
-        if (k == kTomb) continue;
-        const u64 v = L == 0 ? (ld64((const u64 *)o.cells + j) >> 32) : ld64((const u64 *)o.cells + 2 * j + 1);
-        u64 p = home_of<L>(T, k, a.crc_hi, a.crc_lo, nv.log2c);
-        while (key_at<L>(nv.cells, p) != kEmpty) p = (p + 1) & nv.mask;
-        put<L>(nv.cells, p, k, v);
-        ++moved;
+      const u64 k = key_at<L>(o.cells, i);
+      if (k == kEmpty || k == kTomb) continue;
+      const u64 v = L == 0 ? (ld64((const u64 *)o.cells + i) >> 32) : ld64((const u64 *)o.cells + 2 * i + 1);
+      u64 p = home_of<L>(T, k, a.crc_hi, a.crc_lo, nv.log2c);
+      for (u64 step = 0; step <= nv.mask; ++step, p = (p + 1) & nv.mask) {
+        if (L == 0) {
+          if (cas64((u64 *)nv.cells + p, kEmpty, k | (v << 32)) == kEmpty) break;
+        } else if (cas64((u64 *)nv.cells + 2 * p, kEmpty, k) == kEmpty) {
+          st64((u64 *)nv.cells + 2 * p + 1, v);
+          break;
+        }
       }
+      ++moved;
     }
   }
   const long long ms = wave_sum((long long)moved);
@@ -212,10 +216,21 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
   return true;
 }
 
+// Per-wavefront LDS table that combines equal keys of one round of 64
+// operations: the lane that claims a key's slot performs the operation
+// with the sum of the round's values of that key (insert: its own value).
+constexpr uint32_t kRoundSlots = 128;
+struct RoundLds {
+  u64 key[kRoundSlots];
+  u64 sum[kRoundSlots];
+};
+
 template <int L>
 __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, uint32_t W) {
   __shared__ uint32_t T[8][256];
+  __shared__ RoundLds rl[4];
   crc_tables_build(T);
+  RoundLds &R = rl[threadIdx.x >> 6];
   AsyncCtl *ctl = a.ctl;
   const uint32_t lane = threadIdx.x & 63;
   uint32_t *gen = &ctl->gen;
@@ -276,16 +291,43 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
       continue;
     }
     for (uint32_t rd = 0; rd < v.rounds; ++rd) {
-      // one operation per lane
+      // one operation per lane; equal keys of the round meet in LDS first
       const u64 i = base + 64ull * rd + lane;
       uint32_t inserted = 0;
+      R.key[lane] = 0;
+      R.key[lane + 64] = 0;
+      R.sum[lane] = 0;
+      R.sum[lane + 64] = 0;
+      wave_sync();
+      u64 key = 0, d = 0;
+      bool lead = false;
+      uint32_t slot = 0;
       if (i < a.n) {
-        const u64 key = L == 0 ? (u64)((const uint32_t *)a.keys)[i] : ((const u64 *)a.keys)[i];
-        const u64 d = a.vals ? (L == 0 ? (u64)((const uint32_t *)a.vals)[i] : ((const u64 *)a.vals)[i]) : 1;
+        key = L == 0 ? (u64)((const uint32_t *)a.keys)[i] : ((const u64 *)a.keys)[i];
+        d = a.vals ? (L == 0 ? (u64)((const uint32_t *)a.vals)[i] : ((const u64 *)a.vals)[i]) : 1;
+        if (key > kTomb) {
+          slot = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits
+          for (;;) {
+            const u64 prev = atomicCAS((unsigned long long *)&R.key[slot], 0ull, (unsigned long long)key);
+            if (prev == 0) {
+              lead = true;
+              break;
+            }
+            if (prev == key) break;
+            slot = (slot + 1) & (kRoundSlots - 1);
+          }
+          if (a.add) atomicAdd((unsigned long long *)&R.sum[slot], (unsigned long long)d);
+        }
+      }
+      wave_sync();
+      if (lead && a.add) d = R.sum[slot];
+      if (i < a.n) {
         uint8_t flag;
         if (key <= kTomb) {
           flag = kFlagReserved;
           err |= 4;
+        } else if (!lead) {
+          flag = 0;  // the lane that leads this key's group does the operation
         } else {
           flag = kFlagFull;
           u64 p = home_of<L>(T, key, a.crc_hi, a.crc_lo, v.log2c);
@@ -330,6 +372,7 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
         }
         if (a.flags) a.flags[i] = flag;
       }
+      wave_sync();
       local += (uint32_t)__popcll(__ballot(inserted));
       if (local >= flush_at) {
         uint32_t trig = 0;

@@ -126,6 +126,11 @@ __host__ __device__ constexpr uint32_t bulk_lds_bytes_per_wave(int op) {
   return ROUND * (op == OP_FIND ? 9u : 1u);
 }
 
+// Single-table calls also stage each round's keys and their home positions
+// in LDS (read with one coalesced load per lane, hashed once per operation),
+// so a group starts its next operation without a dependent global load.
+constexpr uint32_t kStageBytesPerWave = ROUND * 16u;
+
 // Marks, in the staged flags of a round, an operation that belongs to another
 // phase of a mixed request; its flag byte in memory is left as it is.
 constexpr uint8_t kSkipFlag = 0xFD;
@@ -149,7 +154,8 @@ template <int LAYOUT, int OP, int UP, int G, bool RESIDENT = false>
 __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T)[256], uint8_t *wflag,
                                            u64 *wout, const u64 rbase, const uint32_t cnt,
                                            long long &d_used, long long &d_live, uint32_t &err,
-                                           u64 *skeys = nullptr, uint8_t *skinds = nullptr) {
+                                           u64 *skeys = nullptr, uint8_t *skinds = nullptr,
+                                           u64 *shome = nullptr) {
   constexpr uint32_t NGW = 64 / G;            // groups per wavefront
   constexpr uint32_t PER_GROUP = ROUND / NGW; // operations per group per round
   const uint32_t lane = threadIdx.x & 63;
@@ -181,6 +187,17 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
     skinds[lane] = c0;
     skinds[lane + 64] = c1;
     wave_sync();
+  } else if (shome) {
+#pragma unroll
+    for (uint32_t q = 0; q < 2; ++q) {
+      const uint32_t loc = lane + 64 * q;
+      if (loc < cnt) {
+        const u64 kk = load_key_in<LAYOUT>(A.keys, rbase + loc);
+        skeys[loc] = kk;
+        shome[loc] = (kk == kEmpty || kk == kTomb) ? 0 : home_of<LAYOUT>(T, kk, A.crc_hi, A.crc_lo, A.log2c);
+      }
+    }
+    wave_sync();
   }
 
   // Takes the group's next operation of the round (reserved keys are
@@ -203,7 +220,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         ++j;
         continue;
       }
-      k = RESIDENT ? skeys[loc] : load_key_in<LAYOUT>(A.keys, i);
+      k = (RESIDENT || shome) ? skeys[loc] : load_key_in<LAYOUT>(A.keys, i);
       if (k == kEmpty || k == kTomb) {
         err |= kErrReserved;
         if (gl == 0) {
@@ -214,7 +231,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         continue;
       }
       d = A.vals ? ld_word<LAYOUT, RESIDENT>(A.vals, i) : 1;
-      const u64 h = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
+      const u64 h = (!RESIDENT && shome) ? shome[loc] : home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
       base = h & ~(u64)(G - 1);
       first = (uint32_t)(h & (G - 1));
       windows = 0;
@@ -453,6 +470,8 @@ __global__ void __launch_bounds__(1024) k_bulk(BulkArgs A) {
   const uint32_t nwb = blockDim.x >> 6;
   uint8_t *wflag = dyn_lds + (OP == OP_FIND ? nwb * ROUND * 8 : 0) + wave * ROUND;
   u64 *wout = (u64 *)dyn_lds + wave * ROUND;  // FIND only
+  u64 *skeys = (u64 *)(dyn_lds + nwb * bulk_lds_bytes_per_wave(OP)) + wave * 2 * ROUND;
+  u64 *shome = skeys + ROUND;
   long long d_used = 0, d_live = 0;
   uint32_t err = 0;
   const u64 nrounds = (A.n + ROUND - 1) / ROUND;
@@ -461,7 +480,7 @@ __global__ void __launch_bounds__(1024) k_bulk(BulkArgs A) {
   for (u64 r = gw; r < nrounds; r += nw) {
     const u64 rbase = r * ROUND;
     const uint32_t cnt = (uint32_t)((A.n - rbase) < ROUND ? (A.n - rbase) : ROUND);
-    bulk_round<LAYOUT, OP, UP, G>(A, T, wflag, wout, rbase, cnt, d_used, d_live, err);
+    bulk_round<LAYOUT, OP, UP, G>(A, T, wflag, wout, rbase, cnt, d_used, d_live, err, skeys, nullptr, shome);
   }
   flush_counts(A.status, d_used, d_live, err, s_acc, &s_err);
 }
@@ -527,8 +546,8 @@ __global__ void __launch_bounds__(1024) k_bulk_multi(const BulkArgs *descs, cons
 // The host only selects this kernel when the table cannot run out of empty
 // cells during the call, so no combined operation can fail with "full".
 
-constexpr int AGG_BLOCK = 256;
-constexpr int AGG_PER_THREAD = 4;
+constexpr int AGG_BLOCK = 1024;
+constexpr int AGG_PER_THREAD = 2;
 constexpr int AGG_CHUNK = AGG_BLOCK * AGG_PER_THREAD;  // operations per chunk
 constexpr int AGG_SLOTS = 2 * AGG_CHUNK;              // LDS hash slots per chunk
 constexpr int HOT_SLOTS = 256;                        // kernel-lifetime hot keys
@@ -1623,7 +1642,7 @@ template <int LAYOUT, int OP, int UP, int G>
 static hipError_t launch_g(const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
   const u64 nrounds = (a.n + ROUND - 1) / ROUND;
   const uint32_t grid = grid_for(nrounds * 64, cfg);
-  const size_t lds = (size_t)(cfg.block_threads / 64) * bulk_lds_bytes_per_wave(OP);
+  const size_t lds = (size_t)(cfg.block_threads / 64) * (bulk_lds_bytes_per_wave(OP) + kStageBytesPerWave);
   hipLaunchKernelGGL((k_bulk<LAYOUT, OP, UP, G>), dim3(grid), dim3(cfg.block_threads), lds, s, a);
   return hipGetLastError();
 }
