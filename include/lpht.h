@@ -287,9 +287,10 @@ int lpht_get_tuning(const lpht_table *t, lpht_tuning *tuning);
  *   - per fill quarter (fill 1/8, 3/8, 5/8, 7/8): the group width for finds
  *     (half present, half absent keys, a quarter of the capacity) and for
  *     inserts (the last capacity/16 keys before that fill), each over
- *     {1, 2, 4, 8, 16} -> g_find, g_modify; a quarter keeps the fill-3/8
- *     choice unless another width is more than 3 % faster; group_width = the
- *     fill-3/8 finds' choice;
+ *     {1, 2, 4, 8, 16} -> g_find, g_modify; a quarter's choice is the
+ *     narrowest width within 3 % of its fastest, and a quarter keeps the
+ *     fill-3/8 choice unless another width is more than 3 % faster;
+ *     group_width = the fill-3/8 finds' choice;
  *   - block_threads over {256, 512, 1024} at fill 3/8 with those widths;
  *   - migrate_block over {256, 512, 1024, 2048}: doubling a table at fill 7/16
  *     (lpht_grow);

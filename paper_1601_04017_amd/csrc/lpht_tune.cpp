@@ -132,14 +132,18 @@ extern "C" int lpht_autotune(uint32_t layout, uint32_t log2c, uint32_t reps, voi
       if (rc) return rc;
     }
   }
-  // Per quarter the fastest width; but a quarter keeps the width chosen for
-  // fill 3/8 unless another is more than kTie faster, so that timing noise
-  // does not split calls into launches of different widths.
+  // Per quarter the narrowest width within kTie of the fastest (fewer lanes
+  // per operation; near-ties then resolve the same way on every run); a
+  // quarter keeps the width chosen for fill 3/8 unless another is more than
+  // kTie faster, so that timing noise does not split calls into launches of
+  // different widths.
   auto choose = [&](const double (*ms)[5], uint8_t *g) {
     auto argmin = [&](int q) {
       int b = 0;
       for (int gi = 1; gi < 5; ++gi)
         if (ms[q][gi] < ms[q][b]) b = gi;
+      for (int gi = 0; gi < b; ++gi)
+        if (ms[q][gi] <= ms[q][b] * (1.0 + kTie)) return gi;
       return b;
     };
     const int ref = argmin(1);

@@ -38,17 +38,19 @@ def test_autotune_returns_valid_shape(layout, tmp_path, monkeypatch):
     assert all(g in WIDTHS for g in tuning["g_find"] + tuning["g_modify"])
     w = report["widths"]
     for key, ms in (("g_find", report["find_ms"]), ("g_modify", report["insert_ms"])):
-        ref = w[int(np.argmin(ms[1]))]
-        assert tuning[key][1] == ref  # the fastest at fill 3/8
+        def narrowest_near_best(q):
+            return next(g for g, x in zip(w, ms[q]) if x <= min(ms[q]) * 1.03)
+        ref = narrowest_near_best(1)
+        assert tuning[key][1] == ref  # fill 3/8: the narrowest within 3 % of the fastest
         for q in range(4):
             assert all(0 < x < 1e4 for x in ms[q])
             # the fill-3/8 width unless another is more than 3 % faster
-            best = min(ms[q])
+            b = narrowest_near_best(q)
             chosen = ms[q][w.index(tuning[key][q])]
             if tuning[key][q] == ref:
-                assert chosen <= best * 1.03 + 1e-9
+                assert chosen <= ms[q][w.index(b)] * 1.03 + 1e-9
             else:
-                assert chosen == best and ms[q][w.index(ref)] > best * 1.03
+                assert tuning[key][q] == b and ms[q][w.index(ref)] > ms[q][w.index(b)] * 1.03
     assert all(0 < x < 1e4 for x in report["block_ms"] + report["migrate_ms"])
     # the cache answers the second call with the same entry
     again, _ = lpht.autotune(layout, 18, reps=1, cache=True)
