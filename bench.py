@@ -642,12 +642,12 @@ def main():
     global TUNING
     tune_info = None
     if not args.no_autotune:
-        # launch shape for 16-byte cells, tuned on 2^26-cell scratch tables
-        # (HBM-resident, unlike smaller ones), outside every timed region
+        # launch shape for 16-byte cells, tuned on scratch tables of the
+        # headline capacity (2^28 cells, 4 GiB), outside every timed region
         log("autotune")
         t0 = time.perf_counter()
-        TUNING, _ = lpht.autotune(lpht.KV64, 26, reps=2)
-        tune_info = {"shape": TUNING, "scratch_log2_capacity": 26,
+        TUNING, _ = lpht.autotune(lpht.KV64, LOG2C, reps=2)
+        tune_info = {"shape": TUNING, "scratch_log2_capacity": LOG2C,
                      "seconds": round(time.perf_counter() - t0, 2)}
     if args.suite_only:
         print(json.dumps({"tuning": tune_info,
