@@ -16,7 +16,8 @@ struct alignas(128) StrCtl {      // device memory, one per table
   unsigned long long used, live;  // set by a recount
   unsigned int err;               // kErrFull: a record did not fit the pool
   unsigned int pad0;
-  unsigned long long pad[12];
+  unsigned long long pool_start;  // pool_used when the running inserting launch began
+  unsigned long long pad[11];
 };
 
 struct StrArgs {

@@ -12,8 +12,9 @@
 // A pool record is a 32-bit length followed by the bytes, rounded up to 8
 // bytes.  Records are allocated by bumping a device cursor; an insertion
 // writes its record, makes it visible (release fence), then publishes the
-// reference with compare-and-swap; a reader that meets the reference fences
-// (acquire) before reading the record.  Records of erased keys, and the rare
+// reference with compare-and-swap; a reader that meets a reference written
+// during its own launch fences (acquire) before reading the record.  Records
+// of erased keys, and the rare
 // record of an insertion that lost a race to an equal key, stay in the pool
 // until the next migration, which copies only live keys into a new pool
 // (the paper reclaims key space when the array is migrated).
@@ -62,100 +63,205 @@ __device__ __forceinline__ u64 ld_ref(const u64 *cells, u64 p) {
   return __hip_atomic_load(cells + 2 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One operation per thread.
+// Whether the cell's reference word r names the key s[0..len).  Records at
+// pool offsets below `fresh_from` were written by earlier launches, which
+// the kernel boundary has made visible; a record this launch may have
+// written is read after an acquire fence, which pairs with the writer's
+// release fence before its compare-and-swap.
+__device__ __forceinline__ bool same_key(const uint8_t *pool, u64 r, u64 sig, const uint8_t *s, u64 len,
+                                         u64 fresh_from) {
+  if (r == kTomb || (r >> 48) != sig) return false;
+  const u64 off = r & kOffMask;
+  if (off >= fresh_from) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return rec_equal(pool, off, s, len);
+}
+
+// Exclusive prefix sum of v over the wavefront's 64 lanes (all active);
+// `total` receives the sum.
+__device__ __forceinline__ u64 wave_excl_scan(u64 v, u64 &total) {
+  const int lane = threadIdx.x & 63;
+  u64 x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const u64 y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+// Operations per lane between release fences in inserting launches: the
+// fence writes back the L2 and costs far more than a probe.
+constexpr int kStrGroup = 8;
+
+// A lane takes K operations (K = kStrGroup when inserting, else 1); for each
+// a read-only probe ends at the key or at the first empty cell.  Inserting
+// operations that ended at an empty cell then take their records from one
+// pool allocation per wavefront, write them, make them visible with one
+// release fence per wavefront, and publish their references with
+// compare-and-swap from that cell on; a lost race continues the probe, and
+// finding the key there leaves the record unused until the next migration.
 template <int KIND>
 __global__ void __launch_bounds__(256) k_str_op(StrArgs a) {
+  constexpr bool kInserting = KIND == kStrInsert || KIND == kStrUpsert;
+  constexpr int K = kInserting ? kStrGroup : 1;
   __shared__ uint32_t T[8][256];
   crc_tables_build(T);
   const u64 mask = (1ull << a.log2c) - 1;
   u64 *cells = (u64 *)a.cells;
-  const u64 stride = (u64)gridDim.x * blockDim.x;
+  // A table is used from one stream at a time, so only an inserting launch
+  // can meet a record written while it runs.
+  const u64 fresh_from = kInserting ? a.ctl->pool_start : ~0ull;
+  const u64 stride = (u64)gridDim.x * blockDim.x * K;
   uint32_t err = 0;
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-    const u64 o0 = a.offsets[i], len = a.offsets[i + 1] - o0;
-    const uint8_t *s = a.bytes + o0;
-    const u64 h = str_hash(T, s, len, a.crc_hi, a.crc_lo);
-    const u64 sig = h & 0xFFFFull;
-    u64 p = h >> (64 - a.log2c);
-    const u64 d = a.vals ? a.vals[i] : 1;
-    uint8_t flag = (KIND == kStrFind || KIND == kStrErase) ? 0 : 0xFF;
-    u64 out = 0;
-    u64 mine = 0;  // reference of this operation's record, once written
-    for (u64 step = 0; step <= mask; ++step, p = (p + 1) & mask) {
-      u64 r = ld_ref(cells, p);
-      if (r == kEmpty) {
-        if (KIND == kStrFind || KIND == kStrErase) break;
-        if (!mine) {
-          const u64 need = rec_bytes(len);
-          const u64 off = atomicAdd((unsigned long long *)&a.ctl->pool_used, (unsigned long long)need);
-          if (off + need > a.pool_cap) {
-            err |= kErrFull;
-            break;  // flag stays 0xFF
-          }
-          *(uint32_t *)(a.pool + off) = (uint32_t)len;
-          for (u64 q = 0; q < len; ++q) a.pool[off + 4 + q] = s[q];
-          __threadfence();
-          mine = (sig << 48) | off;
-        }
-        const u64 prev = cas64(cells + 2 * p, kEmpty, mine);
-        if (prev == kEmpty) {
-          if (KIND == kStrInsert || a.up == 0)
-            __hip_atomic_store(cells + 2 * p + 1, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          else
-            add64(cells + 2 * p + 1, d);
-          flag = 1;
+  // the bound is uniform over the workgroup: every lane reaches the
+  // wavefront's allocation, idle lanes with nothing to allocate
+  for (u64 i0 = (u64)blockIdx.x * blockDim.x * K; i0 < a.n; i0 += stride) {
+    u64 len[K], sig[K], p[K], step[K], r[K], d[K], mine[K];
+    const uint8_t *s[K];
+    bool found[K], at_empty[K];
+    uint8_t flag[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const u64 i = i0 + (u64)j * blockDim.x + threadIdx.x;
+      len[j] = sig[j] = p[j] = step[j] = mine[j] = 0;
+      r[j] = kEmpty;
+      d[j] = 1;
+      s[j] = nullptr;
+      found[j] = at_empty[j] = false;
+      flag[j] = kInserting ? 0xFF : 0;
+      if (i >= a.n) continue;
+      const u64 o0 = a.offsets[i];
+      len[j] = a.offsets[i + 1] - o0;
+      s[j] = a.bytes + o0;
+      if (a.vals) d[j] = a.vals[i];
+      const u64 h = str_hash(T, s[j], len[j], a.crc_hi, a.crc_lo);
+      sig[j] = h & 0xFFFFull;
+      p[j] = h >> (64 - a.log2c);
+      for (; step[j] <= mask; ++step[j], p[j] = (p[j] + 1) & mask) {
+        r[j] = ld_ref(cells, p[j]);
+        if (r[j] == kEmpty) {
+          at_empty[j] = true;
           break;
         }
-        r = prev;
-      }
-      if (r == kTomb || (r >> 48) != sig) continue;
-      __threadfence();
-      if (!rec_equal(a.pool, r & kOffMask, s, len)) continue;
-      // the key is present in cell p
-      if (KIND == kStrFind) {
-        out = __hip_atomic_load(cells + 2 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        flag = 1;
-      } else if (KIND == kStrErase) {
-        flag = cas64(cells + 2 * p, r, kTomb) == r ? 1 : 0;
-      } else {
-        if (KIND == kStrUpsert) {
-          if (a.up == 0)
-            __hip_atomic_store(cells + 2 * p + 1, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          else
-            add64(cells + 2 * p + 1, d);
+        if (same_key(a.pool, r[j], sig[j], s[j], len[j], fresh_from)) {
+          found[j] = true;
+          break;
         }
-        flag = 0;
       }
-      break;
     }
-    if ((KIND == kStrInsert || KIND == kStrUpsert) && flag == 0xFF) err |= kErrFull;
-    if (a.flags) a.flags[i] = flag;
-    if (KIND == kStrFind && a.vals_out) a.vals_out[i] = out;
+    if (kInserting) {
+      // one allocation per wavefront, laid out by j: the records of the
+      // wavefront's j-th operations are consecutive
+      u64 total = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) total += (u64)wave_sum((long long)(at_empty[j] ? rec_bytes(len[j]) : 0));
+      u64 base = 0;
+      if ((threadIdx.x & 63) == 0 && total)
+        base = atomicAdd((unsigned long long *)&a.ctl->pool_used, (unsigned long long)total);
+      base = __shfl(base, 0, 64);
+      bool wrote = false;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const u64 need = at_empty[j] ? rec_bytes(len[j]) : 0;
+        u64 tj;
+        const u64 off = base + wave_excl_scan(need, tj);
+        base += tj;
+        if (!need) continue;
+        if (off + need > a.pool_cap) {
+          err |= kErrFull;  // flag stays 0xFF
+        } else {
+          *(uint32_t *)(a.pool + off) = (uint32_t)len[j];
+          for (u64 q = 0; q < len[j]; ++q) a.pool[off + 4 + q] = s[j][q];
+          mine[j] = (sig[j] << 48) | off;
+          wrote = true;
+        }
+      }
+      if (wrote) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        if (!mine[j]) continue;
+        // cell p[j] was empty when the probe passed it
+        for (r[j] = kEmpty; step[j] <= mask; ++step[j], p[j] = (p[j] + 1) & mask, r[j] = ld_ref(cells, p[j])) {
+          if (r[j] == kEmpty) {
+            const u64 prev = cas64(cells + 2 * p[j], kEmpty, mine[j]);
+            if (prev == kEmpty) {
+              if (KIND == kStrInsert || a.up == 0)
+                __hip_atomic_store(cells + 2 * p[j] + 1, d[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              else
+                add64(cells + 2 * p[j] + 1, d[j]);
+              flag[j] = 1;
+              break;
+            }
+            r[j] = prev;
+          }
+          if (same_key(a.pool, r[j], sig[j], s[j], len[j], fresh_from)) {
+            found[j] = true;
+            break;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const u64 i = i0 + (u64)j * blockDim.x + threadIdx.x;
+      if (i >= a.n) continue;
+      u64 out = 0;
+      if (found[j]) {
+        // the key is present in cell p[j], whose reference word is r[j]
+        const u64 q = p[j];
+        if (KIND == kStrFind) {
+          out = __hip_atomic_load(cells + 2 * q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          flag[j] = 1;
+        } else if (KIND == kStrErase) {
+          flag[j] = cas64(cells + 2 * q, r[j], kTomb) == r[j] ? 1 : 0;
+        } else {
+          if (KIND == kStrUpsert) {
+            if (a.up == 0)
+              __hip_atomic_store(cells + 2 * q + 1, d[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+              add64(cells + 2 * q + 1, d[j]);
+          }
+          flag[j] = 0;
+        }
+      }
+      if (kInserting && flag[j] == 0xFF) err |= kErrFull;
+      if (a.flags) a.flags[i] = flag[j];
+      if (KIND == kStrFind && a.vals_out) a.vals_out[i] = out;
+    }
   }
   if (err) atomicOr(&a.ctl->err, err);
 }
 
-// Migration: every live key of the old table is copied into the new pool and
-// inserted into the new (zeroed) table with compare-and-swap.
+// Migration: every live key of the old table is copied into the new pool
+// (one allocation per wavefront) and inserted into the new (zeroed) table
+// with compare-and-swap.
 __global__ void __launch_bounds__(256) k_str_migrate(StrMigArgs a) {
   __shared__ uint32_t T[8][256];
   crc_tables_build(T);
   const u64 oc = 1ull << a.log2_old, nmask = (1ull << a.log2_new) - 1;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   uint32_t err = 0;
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < oc; i += stride) {
-    const u64 r = a.old_cells[2 * i];
-    if (r == kEmpty || r == kTomb) continue;
+  for (u64 i0 = (u64)blockIdx.x * blockDim.x; i0 < oc; i0 += stride) {
+    const u64 i = i0 + threadIdx.x;
+    const u64 r = i < oc ? a.old_cells[2 * i] : kEmpty;
+    const bool live = r != kEmpty && r != kTomb;
     const u64 off = r & kOffMask;
-    const u64 len = *(const uint32_t *)(a.old_pool + off);
-    const uint8_t *s = a.old_pool + off + 4;
-    const u64 h = str_hash(T, s, len, a.crc_hi, a.crc_lo);
-    const u64 need = rec_bytes(len);
-    const u64 noff = atomicAdd((unsigned long long *)&a.ctl->pool_used, (unsigned long long)need);
+    const u64 len = live ? *(const uint32_t *)(a.old_pool + off) : 0;
+    const u64 need = live ? rec_bytes(len) : 0;
+    u64 total;
+    const u64 pre = wave_excl_scan(need, total);
+    u64 base = 0;
+    if ((threadIdx.x & 63) == 0 && total)
+      base = atomicAdd((unsigned long long *)&a.ctl->pool_used, (unsigned long long)total);
+    base = __shfl(base, 0, 64);
+    if (!live) continue;
+    const u64 noff = base + pre;
     if (noff + need > a.new_pool_cap) {
       err |= kErrFull;
       continue;
     }
+    const uint8_t *s = a.old_pool + off + 4;
+    const u64 h = str_hash(T, s, len, a.crc_hi, a.crc_lo);
     // records are 8-byte aligned: copy whole words
     for (u64 q = 0; q < need; q += 8) *(u64 *)(a.new_pool + noff + q) = *(const u64 *)(a.old_pool + off + q);
     const u64 ref = ((h & 0xFFFFull) << 48) | noff;
@@ -186,6 +292,11 @@ __global__ void __launch_bounds__(256) k_str_recount(const u64 *cells, u64 cap, 
   }
 }
 
+// Marks where records of the next launch will start.
+__global__ void k_str_snap(StrCtl *ctl) {
+  if (threadIdx.x == 0) ctl->pool_start = ctl->pool_used;
+}
+
 __global__ void k_str_ctl(StrCtl *ctl, u64 pool_used, int keep_pool) {
   if (threadIdx.x == 0) {
     ctl->used = 0;
@@ -204,7 +315,13 @@ uint32_t grid_of(u64 items, uint32_t num_cus) {
 }  // namespace
 
 hipError_t launch_str_op(int kind, const StrArgs &a, uint32_t num_cus, hipStream_t s) {
-  const uint32_t g = grid_of(a.n, num_cus);
+  const bool inserting = kind == kStrInsert || kind == kStrUpsert;
+  const uint32_t g = grid_of(inserting ? (a.n + kStrGroup - 1) / kStrGroup : a.n, num_cus);
+  if (inserting) {
+    hipLaunchKernelGGL(k_str_snap, dim3(1), dim3(64), 0, s, a.ctl);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   switch (kind) {
     case kStrInsert: hipLaunchKernelGGL(k_str_op<kStrInsert>, dim3(g), dim3(256), 0, s, a); break;
     case kStrUpsert: hipLaunchKernelGGL(k_str_op<kStrUpsert>, dim3(g), dim3(256), 0, s, a); break;

@@ -130,3 +130,26 @@ def test_signature_collisions_and_pool_compaction():
     g.grow(g.capacity()[0].bit_length())  # doubling by hand
     o.grow(o.capacity.bit_length())
     _same_table(g, o)
+
+
+def test_equal_keys_in_one_batch_add_exactly():
+    # many lanes of one launch insert the same keys at once: the losers of a
+    # race follow the winner's record, written during the same launch
+    from paper_1601_04017_amd import lpht
+    rng = np.random.default_rng(11)
+    pool = _pool(rng, 2000, 60) + [b""]
+    ranks = np.minimum(rng.zipf(1.3, 300_000) - 1, len(pool) - 1)
+    keys = [pool[i] for i in ranks]
+    vals = rng.integers(0, 1 << 40, len(keys)).astype(np.uint64)
+    g = lpht.StrTable(log2_capacity=6, auto_grow=True, pool_bytes=64)
+    o = oracle.OracleStrTable(6, auto_grow=True)
+    gf = g.insert_or_update(keys, vals, oracle.ADD)
+    of = o.insert_or_update(keys, vals, oracle.ADD)
+    assert np.array_equal(_canon(keys, gf), of)
+    assert g.count() == o.counts()
+    assert g.capacity()[0] == o.capacity
+    gv, gfl = g.find(pool)
+    ov, ofl = o.find(pool)
+    assert np.array_equal(gfl, ofl) and np.array_equal(gv, ov)
+    assert g.status() == 0
+    _same_table(g, o)
