@@ -37,11 +37,29 @@ __device__ __forceinline__ uint32_t crc_byte(const uint32_t (*T)[256], uint32_t 
   return (r >> 8) ^ T[0][(r ^ b) & 0xFFu];
 }
 
-// 64-bit hash of bytes s[0..len) (global memory, any alignment).
+// 8 bytes at any alignment (one or two wide loads; never past p + 7).
+__device__ __forceinline__ u64 ld8(const uint8_t *p) {
+  u64 x;
+  __builtin_memcpy(&x, p, 8);
+  return x;
+}
+
+__device__ __forceinline__ void st8(uint8_t *p, u64 x) { __builtin_memcpy(p, &x, 8); }
+
+// 64-bit hash of bytes s[0..len) (global memory, any alignment).  Eight
+// bytes at a time: with the register XORed into their low word, the
+// register after them is CRC(0, chunk) (the slicing tables); then the tail
+// byte by byte.
 __device__ __forceinline__ u64 str_hash(const uint32_t (*T)[256], const uint8_t *s, u64 len, uint32_t seed_hi,
                                         uint32_t seed_lo) {
   uint32_t hi = seed_hi, lo = seed_lo;
-  for (u64 i = 0; i < len; ++i) {
+  u64 i = 0;
+  for (; i + 8 <= len; i += 8) {
+    const u64 x = ld8(s + i);
+    hi = crc0_u64(T, x ^ hi);
+    lo = crc0_u64(T, x ^ lo);
+  }
+  for (; i < len; ++i) {
     const uint32_t b = s[i];
     hi = crc_byte(T, hi, b);
     lo = crc_byte(T, lo, b);
@@ -54,9 +72,21 @@ __device__ __forceinline__ u64 rec_bytes(u64 len) { return (4 + len + 7) & ~7ull
 __device__ __forceinline__ bool rec_equal(const uint8_t *pool, u64 off, const uint8_t *s, u64 len) {
   if (*(const uint32_t *)(pool + off) != (uint32_t)len) return false;
   const uint8_t *r = pool + off + 4;
-  for (u64 i = 0; i < len; ++i)
+  u64 i = 0;
+  for (; i + 8 <= len; i += 8)
+    if (ld8(r + i) != ld8(s + i)) return false;
+  for (; i < len; ++i)
     if (r[i] != s[i]) return false;
   return true;
+}
+
+// Writes the record of s[0..len) at pool offset off (8-aligned).
+__device__ __forceinline__ void rec_write(uint8_t *pool, u64 off, const uint8_t *s, u64 len) {
+  *(uint32_t *)(pool + off) = (uint32_t)len;
+  uint8_t *r = pool + off + 4;
+  u64 i = 0;
+  for (; i + 8 <= len; i += 8) st8(r + i, ld8(s + i));
+  for (; i < len; ++i) r[i] = s[i];
 }
 
 __device__ __forceinline__ u64 ld_ref(const u64 *cells, u64 p) {
@@ -170,8 +200,7 @@ __global__ void __launch_bounds__(256) k_str_op(StrArgs a) {
         if (off + need > a.pool_cap) {
           err |= kErrFull;  // flag stays 0xFF
         } else {
-          *(uint32_t *)(a.pool + off) = (uint32_t)len[j];
-          for (u64 q = 0; q < len[j]; ++q) a.pool[off + 4 + q] = s[j][q];
+          rec_write(a.pool, off, s[j], len[j]);
           mine[j] = (sig[j] << 48) | off;
           wrote = true;
         }
