@@ -153,3 +153,34 @@ def test_equal_keys_in_one_batch_add_exactly():
     assert np.array_equal(gfl, ofl) and np.array_equal(gv, ov)
     assert g.status() == 0
     _same_table(g, o)
+
+
+def test_full_table_without_growth():
+    # 100 distinct keys into 64 cells, no growth: which 64 get in is decided
+    # by concurrency; exactly the table's capacity is inserted, the rest get
+    # 0xFF and the sticky FULL error, and probes of a table with no empty
+    # cell end after one round
+    from paper_1601_04017_amd import lpht
+    rng = np.random.default_rng(13)
+    keys = _pool(rng, 100, 30)
+    vals = np.arange(1, 101, dtype=np.uint64)
+    g = lpht.StrTable(log2_capacity=6, auto_grow=False, pool_bytes=1 << 16)
+    f = g.insert(keys, vals)
+    assert sorted(set(f.tolist())) == [1, 0xFF] and int((f == 1).sum()) == 64
+    assert g.status() == lpht.ERR_FULL and g.status() == 0
+    assert g.count() == (64, 64)
+    gv, gf = g.find(keys + [b"absent"])
+    assert np.array_equal(gf[:100], (f == 1).astype(np.uint8)) and gf[100] == 0
+    assert np.array_equal(gv[:100][f == 1], vals[f == 1])
+    # erasing makes tombstones, not room: a new key still finds no empty cell
+    inside = [k for k, x in zip(keys, f) if x == 1]
+    assert g.erase(inside[:10]).tolist() == [1] * 10
+    assert g.insert([b"new key"]).tolist() == [0xFF]
+    assert g.status() == lpht.ERR_FULL
+    assert g.count() == (64, 54)
+    # a same-size migration drops the tombstones; then it fits
+    g.grow(6)
+    assert g.count() == (54, 54)
+    assert g.insert([b"new key"]).tolist() == [1]
+    _, gf = g.find(inside[10:] + [b"new key"])
+    assert gf.tolist() == [1] * 55
