@@ -26,6 +26,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_kernels.hip", "lpht_device.h", "lpht_internal.h")]
 SHRINK_SRCS = [os.path.join(PKG, "csrc", f)
                for f in ("lpht_shrink.hip", "lpht_shrink.h", "lpht_device.h", "lpht_internal.h")]
+STR_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_str.hip", "lpht_str.h", "lpht_device.h", "lpht_internal.h")]
 
 
 def kernel_source_sha(srcs=None) -> str:
@@ -96,7 +97,8 @@ def main():
     lines = [f"# rocprofv3 summary: {os.path.basename(a.out)}", "", "Commands:", "", "```"]
     lines += a.cmd.split(";;")
     lines += ["```", "", f"Kernel source sha256[:16]: `{kernel_source_sha()}` "
-              f"(shrink kernels: `{kernel_source_sha(SHRINK_SRCS)}`)", "",
+              f"(shrink kernels: `{kernel_source_sha(SHRINK_SRCS)}`, "
+              f"string-key kernels: `{kernel_source_sha(STR_SRCS)}`)", "",
               "## Kernel durations (--kernel-trace --stats)", "",
               "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
     for s in stats[:a.rows]:
