@@ -1,0 +1,94 @@
+"""The headline workload at full size, in the launch shape the benchmark
+times (the autotuner's shape for 2^28 KV64 cells), on the benchmark's own
+seeded inputs: 10^8 distinct keys inserted into a presized 2^28-cell table,
+10^8 successful and 10^8 unsuccessful finds, and 10^8 Zipf(1.0)
+insert-or-increments over a universe of 10^8.
+
+Replaying 10^8 operations through the oracle does not fit a test, so these
+checks are exact properties that hold at any size:
+  * distinct keys: every insert reports 1 and the counts are exactly 10^8;
+    every key is found with its value (its index), every absent key is not;
+    empty cells hold value 0; and for a sample of the stored keys, the key is
+    reachable from its home (the oracle's hash) along non-empty cells;
+  * Zipf: the final value of every distinct key equals its count in the
+    stream (sort + unique + count), and nothing else is stored.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_04017_amd import inputs
+from tests import helpers as H
+from tests.gpu_util import cells_host, to_dev, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N = 10 ** 8
+LOG2C = 28
+
+
+@pytest.fixture(scope="module")
+def tuned():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1601_04017_amd import lpht
+    shape, _ = lpht.autotune(lpht.KV64, LOG2C, reps=2)
+    return shape
+
+
+def _table(shape):
+    from paper_1601_04017_amd import lpht
+    t = lpht.Table(layout=lpht.KV64, log2_capacity=LOG2C)
+    t.apply_tuning(shape)
+    return t
+
+
+def test_distinct_inserts_and_finds_full_size(tuned):
+    import torch
+    print(f"full size: {N} distinct keys into 2^{LOG2C} cells, shape {tuned}", flush=True)
+    keys = inputs.distinct_keys_u64(N, 201)
+    dk = to_dev(keys)
+    dv = torch.arange(N, dtype=torch.int64, device="cuda")
+    t = _table(tuned)
+    f = t.insert(dk, dv)
+    assert int((f == 1).sum()) == N
+    assert t.count() == (N, N) and t.status() == 0
+    perm = torch.from_numpy(inputs.permutation(N, 203)).cuda()
+    v, found = t.find(dk[perm])
+    assert bool((found == 1).all())
+    assert torch.equal(v, perm)
+    del v, found, dv
+    miss = to_dev(inputs.distinct_keys_u64(N, 201, absent=True))
+    v, found = t.find(miss)
+    assert not bool(found.any()) and not bool(v.any())
+    del v, found, miss, dk, perm
+    cells = cells_host(t)
+    t.close()
+    ks, vs = H.split_cells(cells, oracle.KV64)
+    del cells
+    occ = ks != H.EMPTY
+    assert int(occ.sum()) == N
+    assert not vs[~occ].any(), "empty cell with a nonzero value"
+    # reachability for every fifth stored key: its home lies in the run of
+    # non-empty cells that ends at its cell
+    q = np.flatnonzero(occ)[::5]
+    p = H.homes(ks[q], oracle.KV64, LOG2C)
+    rs = H.run_start(occ)[q]
+    assert np.all((q - p) % (1 << LOG2C) <= q - rs), "stored key not reachable from its home"
+    # the sampled keys are the inserted keys at the stored indices
+    assert np.array_equal(ks[q], keys[vs[q].astype(np.int64)])
+
+
+def test_zipf_increments_full_size(tuned):
+    from paper_1601_04017_amd import lpht
+    z = inputs.zipf_keys_u64(N, N, 1.0, seed=402)
+    uk, cnt = np.unique(z, return_counts=True)
+    print(f"full size: {N} Zipf(1.0) increments, {uk.size} distinct keys", flush=True)
+    t = _table(tuned)
+    t.insert_or_update(to_dev(z), None, op=lpht.ADD, flags=False)
+    del z
+    assert t.count() == (uk.size, uk.size) and t.status() == 0
+    v, found = t.find(to_dev(uk))
+    assert bool((found == 1).all())
+    assert np.array_equal(to_host(v, np.uint64), cnt.astype(np.uint64))
+    t.close()
