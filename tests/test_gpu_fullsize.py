@@ -92,3 +92,55 @@ def test_zipf_increments_full_size(tuned):
     assert bool((found == 1).all())
     assert np.array_equal(to_host(v, np.uint64), cnt.astype(np.uint64))
     t.close()
+
+
+def test_growing_from_4096_full_size(tuned):
+    # 10^8 distinct keys in batches of 2^20 into a table created with 4096
+    # cells (alpha = 1/2): after every batch the capacity is the smallest
+    # power of two >= 4096 that holds the keys so far at fill <= 1/2 (the
+    # oracle's growth rule for distinct keys, checked against it on small
+    # runs), and at the end every key is found with its value
+    import torch
+    from paper_1601_04017_amd import lpht
+    b = 1 << 20
+    print(f"full size: {N} distinct keys from 4096 cells in batches of {b}", flush=True)
+    dk = to_dev(inputs.distinct_keys_u64(N, 201))
+    dv = torch.arange(N, dtype=torch.int64, device="cuda")
+    t = lpht.Table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+    t.apply_tuning(tuned)
+    for lo in range(0, N, b):
+        hi = min(N, lo + b)
+        t.insert(dk[lo:hi], dv[lo:hi], flags=False)
+        assert t.log2_capacity == max(12, (2 * hi - 1).bit_length()), hi
+    assert t.count() == (N, N) and t.status() == 0
+    perm = torch.from_numpy(inputs.permutation(N, 203)).cuda()
+    v, found = t.find(dk[perm])
+    assert bool((found == 1).all()) and torch.equal(v, perm)
+    t.close()
+
+
+@pytest.mark.parametrize("s", [0.5, 1.0, 1.25, 1.5])
+def test_zipf_presized_and_growing_full_size(tuned, s):
+    # the suite's Zipf streams: 10^8 keys from a universe of 10^8, counted
+    # into a presized 2^28-cell table in one call and into a table growing
+    # from 4096 cells in batches of 2^20; both must hold the exact histogram
+    from paper_1601_04017_amd import lpht
+    z = inputs.zipf_keys_u64(N, N, s, seed=400 + int(s * 4))
+    uk, cnt = np.unique(z, return_counts=True)
+    print(f"full size: Zipf({s}) increments, {uk.size} distinct keys", flush=True)
+    dz, du = to_dev(z), to_dev(uk)
+    del z
+    for grow in (False, True):
+        if grow:
+            t = lpht.Table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+            t.apply_tuning(tuned)
+            for lo in range(0, N, 1 << 20):
+                t.insert_or_update(dz[lo:lo + (1 << 20)], None, op=lpht.ADD, flags=False)
+        else:
+            t = _table(tuned)
+            t.insert_or_update(dz, None, op=lpht.ADD, flags=False)
+        assert t.count() == (uk.size, uk.size) and t.status() == 0, grow
+        v, found = t.find(du)
+        assert bool((found == 1).all()), grow
+        assert np.array_equal(to_host(v, np.uint64), cnt.astype(np.uint64)), grow
+        t.close()
