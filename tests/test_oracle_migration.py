@@ -330,3 +330,17 @@ def test_full_table_migrates_at_same_size(layout):
     assert t.counts() == (64, 64) and H.live_dict(t.cells(), layout) == before
     with pytest.raises(RuntimeError):
         t.grow(5)
+
+
+def test_growth_capacity_of_distinct_batches_closed_form():
+    # distinct keys in batches from 4096 cells at alpha = 1/2: after each
+    # batch the capacity is the smallest power of two >= 4096 with
+    # 2 * (keys so far) <= c (the full-size GPU test relies on this form)
+    b = 1 << 12
+    n = 70 * b + 333
+    keys = inputs.distinct_keys_u64(n, 5)
+    o = oracle.OracleTable(oracle.KV64, 12, auto_grow=True)
+    for lo in range(0, n, b):
+        hi = min(n, lo + b)
+        o.insert(keys[lo:hi])
+        assert o.capacity == 1 << max(12, (2 * hi - 1).bit_length()), hi
