@@ -1,12 +1,13 @@
 """The headline workload at full size, in the launch shape the benchmark
 times (the autotuner's shape for 2^28 KV64 cells), on the benchmark's own
-seeded inputs: 10^8 distinct keys inserted into a presized 2^28-cell table,
-10^8 successful and 10^8 unsuccessful finds, and 10^8 Zipf(1.0)
-insert-or-increments over a universe of 10^8.
+seeded inputs: 10^8 distinct keys inserted into a presized 2^28-cell table
+(and the fills 0.25, 0.5, 0.75), as many successful and unsuccessful finds,
+10^8 keys inserted in batches into a table growing from 4096 cells, and
+10^8 Zipf insert-or-increments over a universe of 10^8, presized and growing.
 
 Replaying 10^8 operations through the oracle does not fit a test, so these
 checks are exact properties that hold at any size:
-  * distinct keys: every insert reports 1 and the counts are exactly 10^8;
+  * distinct keys: every insert reports 1 and the counts equal the keys;
     every key is found with its value (its index), every absent key is not;
     empty cells hold value 0; and for a sample of the stored keys, the key is
     reachable from its home (the oracle's hash) along non-empty cells;
@@ -43,22 +44,22 @@ def _table(shape):
     return t
 
 
-def test_distinct_inserts_and_finds_full_size(tuned):
+def _distinct_inserts_and_finds(shape, n, sample_every):
     import torch
-    print(f"full size: {N} distinct keys into 2^{LOG2C} cells, shape {tuned}", flush=True)
-    keys = inputs.distinct_keys_u64(N, 201)
+    print(f"full size: {n} distinct keys into 2^{LOG2C} cells, shape {shape}", flush=True)
+    keys = inputs.distinct_keys_u64(n, 201)
     dk = to_dev(keys)
-    dv = torch.arange(N, dtype=torch.int64, device="cuda")
-    t = _table(tuned)
+    dv = torch.arange(n, dtype=torch.int64, device="cuda")
+    t = _table(shape)
     f = t.insert(dk, dv)
-    assert int((f == 1).sum()) == N
-    assert t.count() == (N, N) and t.status() == 0
-    perm = torch.from_numpy(inputs.permutation(N, 203)).cuda()
+    assert int((f == 1).sum()) == n
+    assert t.count() == (n, n) and t.status() == 0
+    perm = torch.from_numpy(inputs.permutation(n, 203)).cuda()
     v, found = t.find(dk[perm])
     assert bool((found == 1).all())
     assert torch.equal(v, perm)
     del v, found, dv
-    miss = to_dev(inputs.distinct_keys_u64(N, 201, absent=True))
+    miss = to_dev(inputs.distinct_keys_u64(n, 201, absent=True))
     v, found = t.find(miss)
     assert not bool(found.any()) and not bool(v.any())
     del v, found, miss, dk, perm
@@ -67,16 +68,27 @@ def test_distinct_inserts_and_finds_full_size(tuned):
     ks, vs = H.split_cells(cells, oracle.KV64)
     del cells
     occ = ks != H.EMPTY
-    assert int(occ.sum()) == N
+    assert int(occ.sum()) == n
     assert not vs[~occ].any(), "empty cell with a nonzero value"
-    # reachability for every fifth stored key: its home lies in the run of
-    # non-empty cells that ends at its cell
-    q = np.flatnonzero(occ)[::5]
+    # reachability for a sample of the stored keys: its home lies in the run
+    # of non-empty cells that ends at its cell
+    q = np.flatnonzero(occ)[::sample_every]
     p = H.homes(ks[q], oracle.KV64, LOG2C)
     rs = H.run_start(occ)[q]
     assert np.all((q - p) % (1 << LOG2C) <= q - rs), "stored key not reachable from its home"
     # the sampled keys are the inserted keys at the stored indices
     assert np.array_equal(ks[q], keys[vs[q].astype(np.int64)])
+
+
+def test_distinct_inserts_and_finds_full_size(tuned):
+    _distinct_inserts_and_finds(tuned, N, 5)
+
+
+@pytest.mark.parametrize("fill", [0.25, 0.5, 0.75])
+def test_fill_sweep_full_size(tuned, fill):
+    # the same at the swept fills of the 2^28-cell table; at 0.75 the insert
+    # is split where a fill quarter changes the group width
+    _distinct_inserts_and_finds(tuned, int(fill * (1 << LOG2C)), 20)
 
 
 def test_zipf_increments_full_size(tuned):
