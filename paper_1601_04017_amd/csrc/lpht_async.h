@@ -12,16 +12,19 @@ namespace lpht {
 
 constexpr uint32_t kAsyncLadder = 16;     // most doublings one call can make
 constexpr uint32_t kAsyncChunk = 64;      // operations of one round (one per lane)
-constexpr uint32_t kAsyncMaxRounds = 16;  // rounds per chunk a wavefront takes at a time (at most)
+constexpr uint32_t kAsyncMaxRounds = 64;  // rounds per chunk a wavefront takes at a time (at most)
 constexpr uint32_t kAsyncFlushMax = 64;   // on the smallest tables a local count is flushed after 1..64 insertions
 constexpr uint32_t kAsyncMigBlock = 4096; // old cells per migration work item
 
-// Device control block (zeroed by the launcher).
+// Device control block (zeroed by the launcher).  The two counters every
+// wavefront updates while inserting, the chunk dispatch and the approximate
+// count, sit on separate 128-byte lines: atomics on one line serialize.
 struct alignas(128) AsyncCtl {
   unsigned long long next;       // next operation index handed out
+  unsigned long long pad_next[15];
   unsigned long long I;          // flushed count of non-empty cells (the approximate counter)
   unsigned long long moved;      // elements moved by the running migration
-  unsigned long long pad0[5];
+  unsigned long long pad0[14];
   unsigned int gen;              // 2 * epoch + 1 from a growth's trigger to its end, else 2 * epoch
   unsigned int arrived;          // wavefronts through the current growth's barriers
   unsigned int epoch;            // completed migrations; the current table is ladder[epoch]
