@@ -29,10 +29,14 @@ struct alignas(128) AsyncCtl {
   unsigned int arrived;          // wavefronts through the current growth's barriers
   unsigned int epoch;            // completed migrations; the current table is ladder[epoch]
   unsigned int finished;         // wavefronts that found no work left
-  unsigned int zero_next;        // next zero-fill work item of the running migration
-  unsigned int mig_next;         // next migration work item
   unsigned int err;              // 1: a wait passed its bound; 2: the ladder ran out
-  unsigned int pad1[9];
+  unsigned int pad1[27];
+  // work items of a running migration, apart from the line waiting
+  // wavefronts poll
+  unsigned int zero_next;        // next zero-fill work item
+  unsigned int pad2[31];
+  unsigned int mig_next;         // next migration work item
+  unsigned int pad3[31];
 };
 
 struct AsyncArgs {

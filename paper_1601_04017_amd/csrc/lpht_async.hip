@@ -400,8 +400,7 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
 }
 
 __global__ void k_async_init(AsyncCtl *ctl, u64 used0) {
-  static_assert(sizeof(AsyncCtl) / 8 <= 64, "one word per thread of the 64 launched");
-  if (threadIdx.x < sizeof(AsyncCtl) / 8) ((unsigned long long *)ctl)[threadIdx.x] = 0;
+  for (uint32_t i = threadIdx.x; i < sizeof(AsyncCtl) / 8; i += blockDim.x) ((unsigned long long *)ctl)[i] = 0;
   __syncthreads();
   if (threadIdx.x == 0) ctl->I = used0;
 }
