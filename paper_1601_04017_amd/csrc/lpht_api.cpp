@@ -837,6 +837,13 @@ int lpht_insert_async(lpht_table *t, const void *keys, const void *vals, uint64_
       release(0);
       return LPHT_ERR_OOM;
     }
+    // the kernel migrates into zeroed tables: clearing them here, at the
+    // zero-fill kernel's rate, spares every growth a phase and a barrier
+    const hipError_t ze = launch_fill_zero(a.ladder[i], cb << (t->log2c + i), t->launch, s);
+    if (ze != hipSuccess) {
+      release(0);
+      return from_hip(ze);
+    }
   }
   AsyncCtl *ctl = (AsyncCtl *)dev_alloc(t, sizeof(AsyncCtl), s);
   if (!ctl) {

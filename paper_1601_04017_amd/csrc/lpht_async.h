@@ -33,10 +33,8 @@ struct alignas(128) AsyncCtl {
   unsigned int pad1[27];
   // work items of a running migration, apart from the line waiting
   // wavefronts poll
-  unsigned int zero_next;        // next zero-fill work item
-  unsigned int pad2[31];
   unsigned int mig_next;         // next migration work item
-  unsigned int pad3[31];
+  unsigned int pad2[31];
 };
 
 struct AsyncArgs {
@@ -45,7 +43,7 @@ struct AsyncArgs {
   const void *keys, *vals;  // vals may be null: every value is 1
   uint64_t n;
   uint8_t *flags;         // may be null
-  void *ladder[kAsyncLadder + 1];  // ladder[0]: the table; ladder[i]: 2^(log2c + i) cells
+  void *ladder[kAsyncLadder + 1];  // ladder[0]: the table; ladder[i]: 2^(log2c + i) zeroed cells
   uint32_t nladder;       // tables in the ladder (>= 1)
   uint32_t log2c;         // capacity of ladder[0]
   uint64_t used0;         // non-empty cells of ladder[0] at the start (exact)

@@ -3,22 +3,25 @@
 // protocol and the approximate size of Sec. 5.2).
 //
 // One cooperative launch (every workgroup resident) processes a batch of
-// insertions (or insert-or-add operations).  Wavefronts take chunks of 64
-// operations from a shared counter, one operation per lane (linear probing
-// with compare-and-swap, Alg. 1).  Each wavefront counts its successful
-// insertions locally and adds the count to the global counter I after a
-// randomised number (1..64) of them; when the addition makes I reach
-// alpha * c, it raises the growing flag.
+// insertions (or insert-or-add operations).  Wavefronts take chunks of 64 r
+// operations from a shared counter (r rounds, up to 64, fewer while the
+// table's free cells are few), one operation per lane per round (linear
+// probing with compare-and-swap, Alg. 1; equal keys of a round are combined
+// in LDS first).  Each wavefront counts its successful insertions locally
+// and adds the count to the global counter I after a randomised number
+// (1..64 r) of them; when the addition makes I reach alpha * c, it raises
+// the growing flag.
 //
 // The protocol of the synchronized variant: a wavefront looks at the flag
 // before taking each chunk (its "busy" period is one chunk); when it is
 // raised the wavefront drops its local count and arrives at the growth.  Once
 // every wavefront has arrived nobody touches the old table, and all of them
 // migrate it together (the dedicated helpers are the kernel's own
-// wavefronts): they clear the target table of twice the size, then walk the
-// old table's clusters in parallel, each cluster in order by one lane, into
-// disjoint target ranges (Lemma 1).  The last to finish publishes the new
-// table version, with I = the number of moved elements, and clears the flag.
+// wavefronts) into the table of twice the size, which the host reserved and
+// zeroed before the launch: work items of old cells, read lane-consecutively,
+// each live element inserted into the target with compare-and-swap.  The
+// last to finish publishes the new table version, with I = the number of
+// moved elements, and clears the flag.
 //
 // The growing flag and the version share one word, gen = 2 * epoch + flag,
 // so a wavefront can never confuse a finished growth with a pending one.
@@ -40,7 +43,6 @@ namespace lpht {
 
 namespace {
 
-constexpr uint32_t kZeroBlock = 1u << 16;  // target cells per zero-fill work item
 constexpr uint8_t kFlagReserved = 0xFE;
 constexpr uint8_t kFlagFull = 0xFF;
 
@@ -148,25 +150,7 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
   lane0_add(&ctl->arrived, 1);
   if (!wait_ge(&ctl->arrived, W, ticks)) return false;
   __threadfence();
-  // 2. clear the target
-  const u64 nc = 1ull << nv.log2c;
-  for (;;) {
-    const u64 item = lane0_add(&ctl->zero_next, 1);
-    const u64 z0 = item * kZeroBlock;
-    if (z0 >= nc) break;
-    const u64 z1 = std::min<u64>(nc, z0 + kZeroBlock);
-    if (L == 0) {
-      for (u64 i = z0 + lane; i < z1; i += 64) ((u64 *)nv.cells)[i] = 0;
-    } else {
-      const u64x2 zero = {0, 0};
-      for (u64 i = z0 + lane; i < z1; i += 64) ((u64x2 *)nv.cells)[i] = zero;
-    }
-  }
-  __threadfence();
-  lane0_add(&ctl->arrived, 1);
-  if (!wait_ge(&ctl->arrived, 2 * W, ticks)) return false;
-  __threadfence();
-  // 3. every live element of the old table, read lane-consecutively, is
+  // 2. every live element of the old table, read lane-consecutively, is
   //    inserted into the target with compare-and-swap (the target is a valid
   //    table of the same keys; the order inside clusters is that of the
   //    insertions)
@@ -196,16 +180,15 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
   const long long ms = wave_sum((long long)moved);
   if (lane == 0 && ms) __hip_atomic_fetch_add(&ctl->moved, (unsigned long long)ms, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
-  // 4. the last to arrive publishes the new version
+  // 3. the last to arrive publishes the new version
   __threadfence();
   const uint32_t before = lane0_add(&ctl->arrived, 1);
-  if (before == 3 * W - 1) {
+  if (before == 2 * W - 1) {
     if (lane == 0) {
       __threadfence();
       const unsigned long long mv = __hip_atomic_load(&ctl->moved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->I, mv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->moved, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->zero_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->mig_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->epoch, e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
