@@ -199,23 +199,37 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
   return true;
 }
 
-// Per-wavefront LDS table that combines equal keys of one round of 64
-// operations: the lane that claims a key's slot performs the operation
-// with the sum of the round's values of that key (insert: its own value).
-constexpr uint32_t kRoundSlots = 128;
-struct RoundLds {
-  u64 key[kRoundSlots];
-  u64 sum[kRoundSlots];
+// Per-wavefront LDS table that combines equal keys of one chunk (up to 64
+// rounds of 64 operations): the first operation of a key in the chunk claims
+// its slot and represents it; at the chunk's end the wavefront applies each
+// slot once to the table, with the sum of the chunk's values of that key
+// (insert: the representative's value), and the representative gets the
+// operation's flag (the others 0).  A key that finds no free slot within
+// kChunkProbe steps is applied at once, on its own; once three quarters of
+// the slots are taken, keys only look for their slot (plain loads) and
+// claim none, so a chunk of distinct keys pays little for the table.
+constexpr uint32_t kChunkSlots = 512;
+constexpr uint32_t kChunkProbe = 16;
+constexpr uint32_t kChunkLookup = 8;
+struct ChunkLds {
+  u64 key[kChunkSlots];
+  u64 acc[kChunkSlots];
+  u64 rep[kChunkSlots];
 };
 
 template <int L>
 __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, uint32_t W) {
   __shared__ uint32_t T[8][256];
-  __shared__ RoundLds rl[4];
+  __shared__ ChunkLds cl[4];
   crc_tables_build(T);
-  RoundLds &R = rl[threadIdx.x >> 6];
+  ChunkLds &C = cl[threadIdx.x >> 6];
   AsyncCtl *ctl = a.ctl;
   const uint32_t lane = threadIdx.x & 63;
+  for (uint32_t q = lane; q < kChunkSlots; q += 64) {
+    C.key[q] = 0;
+    C.acc[q] = 0;
+  }
+  wave_sync();
   uint32_t *gen = &ctl->gen;
   uint32_t my = 0;
   View v = view_of(a, 0, W);
@@ -273,90 +287,47 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
       lane0_add(&ctl->finished, 1);
       continue;
     }
-    for (uint32_t rd = 0; rd < v.rounds; ++rd) {
-      // one operation per lane; equal keys of the round meet in LDS first
-      const u64 i = base + 64ull * rd + lane;
-      uint32_t inserted = 0;
-      R.key[lane] = 0;
-      R.key[lane + 64] = 0;
-      R.sum[lane] = 0;
-      R.sum[lane + 64] = 0;
-      wave_sync();
-      u64 key = 0, d = 0;
-      bool lead = false;
-      uint32_t slot = 0;
-      if (i < a.n) {
-        key = L == 0 ? (u64)((const uint32_t *)a.keys)[i] : ((const u64 *)a.keys)[i];
-        d = a.vals ? (L == 0 ? (u64)((const uint32_t *)a.vals)[i] : ((const u64 *)a.vals)[i]) : 1;
-        if (key > kTomb) {
-          slot = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits
-          for (;;) {
-            const u64 prev = atomicCAS((unsigned long long *)&R.key[slot], 0ull, (unsigned long long)key);
-            if (prev == 0) {
-              lead = true;
-              break;
+    // the table operation for key with value d in the current table: 1
+    // inserted, 0 present (d added in add mode), kFlagFull no empty cell
+    auto apply_op = [&](u64 key, u64 d) -> uint8_t {
+      u64 p = home_of<L>(T, key, a.crc_hi, a.crc_lo, v.log2c);
+      for (u64 step = 0; step <= v.mask; ++step, p = (p + 1) & v.mask) {
+        u64 cur = key_at<L>(v.cells, p);
+        if (cur == kEmpty) {
+          if (L == 0) {
+            const u64 want = key | ((d & 0xFFFFFFFFull) << 32);
+            const u64 w = cas64((u64 *)v.cells + p, kEmpty, want);
+            if (w == kEmpty) return 1;
+            cur = w & 0xFFFFFFFFull;
+          } else {
+            const u64 w = cas64((u64 *)v.cells + 2 * p, kEmpty, key);
+            if (w == kEmpty) {
+              if (a.add)
+                add64((u64 *)v.cells + 2 * p + 1, d);
+              else
+                st64((u64 *)v.cells + 2 * p + 1, d);
+              return 1;
             }
-            if (prev == key) break;
-            slot = (slot + 1) & (kRoundSlots - 1);
-          }
-          if (a.add) atomicAdd((unsigned long long *)&R.sum[slot], (unsigned long long)d);
-        }
-      }
-      wave_sync();
-      if (lead && a.add) d = R.sum[slot];
-      if (i < a.n) {
-        uint8_t flag;
-        if (key <= kTomb) {
-          flag = kFlagReserved;
-          err |= 4;
-        } else if (!lead) {
-          flag = 0;  // the lane that leads this key's group does the operation
-        } else {
-          flag = kFlagFull;
-          u64 p = home_of<L>(T, key, a.crc_hi, a.crc_lo, v.log2c);
-          for (u64 step = 0; step <= v.mask; ++step, p = (p + 1) & v.mask) {
-            u64 cur = key_at<L>(v.cells, p);
-            if (cur == kEmpty) {
-              if (L == 0) {
-                const u64 want = key | ((d & 0xFFFFFFFFull) << 32);
-                const u64 w = cas64((u64 *)v.cells + p, kEmpty, want);
-                if (w == kEmpty) {
-                  flag = 1;
-                  inserted = 1;
-                  break;
-                }
-                cur = w & 0xFFFFFFFFull;
-              } else {
-                const u64 w = cas64((u64 *)v.cells + 2 * p, kEmpty, key);
-                if (w == kEmpty) {
-                  if (a.add)
-                    add64((u64 *)v.cells + 2 * p + 1, d);
-                  else
-                    st64((u64 *)v.cells + 2 * p + 1, d);
-                  flag = 1;
-                  inserted = 1;
-                  break;
-                }
-                cur = w;
-              }
-            }
-            if (cur == key) {
-              if (a.add) {
-                if (L == 0)
-                  __hip_atomic_fetch_add((uint32_t *)((u64 *)v.cells + p) + 1, (uint32_t)d, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-                else
-                  add64((u64 *)v.cells + 2 * p + 1, d);
-              }
-              flag = 0;
-              break;
-            }
+            cur = w;
           }
         }
-        if (a.flags) a.flags[i] = flag;
+        if (cur == key) {
+          if (a.add) {
+            if (L == 0)
+              __hip_atomic_fetch_add((uint32_t *)((u64 *)v.cells + p) + 1, (uint32_t)d, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+            else
+              add64((u64 *)v.cells + 2 * p + 1, d);
+          }
+          return 0;
+        }
       }
-      wave_sync();
-      local += (uint32_t)__popcll(__ballot(inserted));
+      return kFlagFull;
+    };
+    // adds the wavefront's new insertions to its local count, flushing it to
+    // I (and raising the growing flag) when it reaches the random bound
+    auto account = [&](uint32_t ins) {
+      local += ins;
       if (local >= flush_at) {
         uint32_t trig = 0;
         if (lane == 0) {
@@ -372,7 +343,77 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
                                                __HIP_MEMORY_SCOPE_AGENT);
         }
       }
+    };
+    uint32_t taken = 0;  // slots claimed in this chunk (wavefront-uniform)
+    for (uint32_t rd = 0; rd < v.rounds; ++rd) {
+      // one operation per lane; equal keys of the chunk meet in LDS
+      const u64 i = base + 64ull * rd + lane;
+      const bool claim = taken < kChunkSlots / 4 * 3;
+      uint32_t inserted = 0;
+      bool lead = false;
+      if (i < a.n) {
+        const u64 key = L == 0 ? (u64)((const uint32_t *)a.keys)[i] : ((const u64 *)a.keys)[i];
+        const u64 d = a.vals ? (L == 0 ? (u64)((const uint32_t *)a.vals)[i] : ((const u64 *)a.vals)[i]) : 1;
+        if (key <= kTomb) {
+          err |= 4;
+          if (a.flags) a.flags[i] = kFlagReserved;
+        } else {
+          uint32_t slot = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 55);  // 9 bits
+          bool held = false;
+          if (claim) {
+            for (uint32_t t = 0; t < kChunkProbe; ++t, slot = (slot + 1) & (kChunkSlots - 1)) {
+              const u64 prev = atomicCAS((unsigned long long *)&C.key[slot], 0ull, (unsigned long long)key);
+              if (prev == 0) {
+                lead = held = true;
+                break;
+              }
+              if (prev == key) {
+                held = true;
+                break;
+              }
+            }
+          } else {
+            // no lane claims a slot in this round: the keys are fixed
+            for (uint32_t t = 0; t < kChunkLookup; ++t, slot = (slot + 1) & (kChunkSlots - 1)) {
+              const u64 k = C.key[slot];
+              if (k == key) {
+                held = true;
+                break;
+              }
+              if (k == 0) break;
+            }
+          }
+          if (held) {
+            if (lead) {
+              C.rep[slot] = i;
+              if (!a.add) C.acc[slot] = d;
+            }
+            if (a.add) atomicAdd((unsigned long long *)&C.acc[slot], (unsigned long long)d);
+            if (!lead && a.flags) a.flags[i] = 0;  // the representative's flag is the operation's
+          } else {
+            const uint8_t f = apply_op(key, d);
+            inserted = f == 1;
+            if (a.flags) a.flags[i] = f;
+          }
+        }
+      }
+      taken += (uint32_t)__popcll(__ballot(lead));
+      account((uint32_t)__popcll(__ballot(inserted)));
     }
+    // the chunk's combined operations, one per distinct key
+    wave_sync();
+    uint32_t ins = 0;
+    for (uint32_t q = lane; q < kChunkSlots; q += 64) {
+      const u64 k = C.key[q];
+      if (k == 0) continue;
+      const uint8_t f = apply_op(k, C.acc[q]);
+      ins += f == 1;
+      if (a.flags) a.flags[C.rep[q]] = f;
+      C.key[q] = 0;
+      C.acc[q] = 0;
+    }
+    wave_sync();
+    account((uint32_t)wave_sum((long long)ins));
   }
   // timeouts are set by the whole wavefront, reserved keys by single lanes
   const uint32_t werr = uni(err & 3u) | (__ballot((err & 4u) != 0) ? 4u : 0u);
