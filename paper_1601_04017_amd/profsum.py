@@ -27,6 +27,8 @@ KERNEL_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_kernels.hip", "lpht_
 SHRINK_SRCS = [os.path.join(PKG, "csrc", f)
                for f in ("lpht_shrink.hip", "lpht_shrink.h", "lpht_device.h", "lpht_internal.h")]
 STR_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_str.hip", "lpht_str.h", "lpht_device.h", "lpht_internal.h")]
+ASYNC_SRCS = [os.path.join(PKG, "csrc", f)
+              for f in ("lpht_async.hip", "lpht_async.h", "lpht_device.h", "lpht_internal.h")]
 
 
 def kernel_source_sha(srcs=None) -> str:
@@ -98,7 +100,8 @@ def main():
     lines += a.cmd.split(";;")
     lines += ["```", "", f"Kernel source sha256[:16]: `{kernel_source_sha()}` "
               f"(shrink kernels: `{kernel_source_sha(SHRINK_SRCS)}`, "
-              f"string-key kernels: `{kernel_source_sha(STR_SRCS)}`)", "",
+              f"string-key kernels: `{kernel_source_sha(STR_SRCS)}`, "
+              f"in-kernel growth: `{kernel_source_sha(ASYNC_SRCS)}`)", "",
               "## Kernel durations (--kernel-trace --stats)", "",
               "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
     for s in stats[:a.rows]:
