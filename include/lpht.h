@@ -285,7 +285,8 @@ int lpht_get_tuning(const lpht_table *t, lpht_tuning *tuning);
  * 2^log2_capacity cells of `layout` (auto_grow off), filled with synthetic
  * distinct keys generated on the device, and returns in `out` the fastest:
  *   - per fill quarter (fill 1/8, 3/8, 5/8, 7/8): the group width for finds
- *     (half present, half absent keys, a quarter of the capacity) and for
+ *     (half present keys, spread evenly over the insertion order, half
+ *     absent keys, a quarter of the capacity) and for
  *     inserts (the last capacity/16 keys before that fill), each over
  *     {1, 2, 4, 8, 16} -> g_find, g_modify; a quarter's choice is the
  *     narrowest width within 3 % of its fastest, and a quarter keeps the

@@ -36,13 +36,13 @@ lpht_tuning default_tuning() {
 struct Scratch {
   hipStream_t s = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
-  void *keys = nullptr, *absent = nullptr, *vals = nullptr;
+  void *keys = nullptr, *absent = nullptr, *present = nullptr, *vals = nullptr;
   uint8_t *found = nullptr;
   lpht_table *t = nullptr;
   ~Scratch() {
     if (t) lpht_destroy(t, (void *)s);
     (void)hipStreamSynchronize(s);
-    for (void *p : {keys, absent, vals, (void *)found})
+    for (void *p : {keys, absent, present, vals, (void *)found})
       if (p) (void)hipFree(p);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -88,6 +88,7 @@ extern "C" int lpht_autotune(uint32_t layout, uint32_t log2c, uint32_t reps, voi
   const uint64_t m_ins = c / 16, m_half = c / 8;  // timed inserts; finds: m_half present + m_half absent
   if (hipEventCreate(&x.ev[0]) != hipSuccess || hipEventCreate(&x.ev[1]) != hipSuccess ||
       hipMalloc(&x.keys, c * kb) != hipSuccess || hipMalloc(&x.absent, m_half * kb) != hipSuccess ||
+      hipMalloc(&x.present, m_half * kb) != hipSuccess ||
       hipMalloc(&x.vals, m_half * kb) != hipSuccess || hipMalloc((void **)&x.found, m_half) != hipSuccess)
     return LPHT_ERR_OOM;
   if (launch_gen_keys(x.keys, c, layout, 1, x.s) != hipSuccess ||
@@ -101,9 +102,15 @@ extern "C" int lpht_autotune(uint32_t layout, uint32_t log2c, uint32_t reps, voi
   std::memset(&rep, 0, sizeof(rep));
 
   // Builds the table to fill end - m_ins with the default shape, then times
-  // the last m_ins inserts and the finds with shape `u`.
+  // the last m_ins inserts and the finds with shape `u`.  The present keys
+  // of the finds are every (end / m_half)-th inserted key (end is an odd
+  // multiple of m_half), so their probe lengths average the table's
+  // successful search rather than those of the earliest insertions.
   auto measure = [&](uint64_t end, const lpht_tuning &u, double &ins_ms, double &find_ms) -> int {
     ins_ms = find_ms = std::numeric_limits<double>::infinity();
+    if (hipMemcpy2DAsync(x.present, kb, K, kb * (end / m_half), kb, m_half, hipMemcpyDeviceToDevice, x.s) !=
+        hipSuccess)
+      return LPHT_ERR_DEVICE;
     for (uint32_t r = 0; r < reps; ++r) {
       int e = lpht_set_tuning(x.t, &base);
       if (!e) e = lpht_clear(x.t, (void *)x.s);
@@ -114,7 +121,7 @@ extern "C" int lpht_autotune(uint32_t layout, uint32_t log2c, uint32_t reps, voi
                           return lpht_insert(x.t, K + (end - m_ins) * kb, nullptr, m_ins, nullptr, (void *)x.s);
                         }));
       find_ms = std::min(find_ms, timed(x, [&] {
-                           int f = lpht_find(x.t, K, m_half, x.vals, x.found, (void *)x.s);
+                           int f = lpht_find(x.t, x.present, m_half, x.vals, x.found, (void *)x.s);
                            if (!f) f = lpht_find(x.t, x.absent, m_half, x.vals, x.found, (void *)x.s);
                            return f;
                          }));
