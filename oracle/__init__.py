@@ -25,6 +25,9 @@ FLAG_FULL = 0xFF
 STICKY_FULL = 1
 STICKY_RESERVED = 2
 
+HASH_CRC32C_PAIR = 0
+HASH_MULSHIFT = 1
+
 SEED_HI = 0x9E3779B9
 SEED_LO = 0xFFFFFFFF
 
@@ -105,6 +108,10 @@ def load(path):
     L.orc_str_cell.argtypes = [ctypes.c_void_p, ctypes.c_uint64, u8p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     L.orc_set_full_keys.restype = ctypes.c_int
     L.orc_set_full_keys.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.orc_mulshift.restype = ctypes.c_uint64
+    L.orc_mulshift.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    L.orc_set_hash.restype = ctypes.c_int
+    L.orc_set_hash.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]
     L.orc_bulk_merge.restype = ctypes.c_int
     L.orc_bulk_merge.argtypes = [ctypes.c_void_p, u8p, u8p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
     return L
@@ -130,6 +137,11 @@ def hash_bulk(keys: np.ndarray, key_bytes: int, seed_hi: int = SEED_HI,
     return out
 
 
+def mulshift(key: int, mul: int) -> int:
+    """The multiplicative hash (mul * key) mod 2^64 of HASH_MULSHIFT tables."""
+    return lib().orc_mulshift(key, mul)
+
+
 def home(h: int, log2c: int) -> int:
     return lib().orc_home(h, log2c)
 
@@ -145,7 +157,8 @@ class OracleTable:
     """Sequential linear-probing table with the device table's cell layout."""
 
     def __init__(self, layout: int, log2c: int, seed_hi: int = SEED_HI, seed_lo: int = SEED_LO,
-                 alpha=(1, 2), auto_grow: bool = False, full_keys: bool = False):
+                 alpha=(1, 2), auto_grow: bool = False, full_keys: bool = False,
+                 hash: int = HASH_CRC32C_PAIR, mul: int = 0):
         self.layout = layout
         self.kdt = np.uint32 if layout == PACKED32 else np.uint64
         self._t = lib().orc_create(layout, log2c, seed_hi, seed_lo, alpha[0], alpha[1],
@@ -154,6 +167,8 @@ class OracleTable:
             raise ValueError("oracle table creation failed")
         if full_keys:
             lib().orc_set_full_keys(self._t, 1)
+        if hash != HASH_CRC32C_PAIR and lib().orc_set_hash(self._t, hash, mul):
+            raise ValueError("bad hash choice (MULSHIFT needs an odd multiplier)")
 
     def __del__(self):
         t = getattr(self, "_t", None)

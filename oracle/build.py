@@ -17,7 +17,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(OUT) and os.path.getmtime(OUT) >= os.path.getmtime(SRC):
         return OUT
     tmp = OUT + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, SRC]
+    cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, SRC]
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)
     return OUT

@@ -39,6 +39,9 @@
 #define ORC_FLAG_RESERVED 0xFE
 #define ORC_FLAG_FULL 0xFF
 
+#define ORC_HASH_CRC32C_PAIR 0
+#define ORC_HASH_MULSHIFT 1
+
 #define ORC_STICKY_FULL 1
 #define ORC_STICKY_RESERVED 2
 
@@ -78,6 +81,15 @@ uint64_t orc_hash(uint64_t key, int key_bytes, uint32_t seed_hi, uint32_t seed_l
   return (hi << 32) | lo;
 }
 
+/* Multiplicative hashing, the alternative hash function of a table created
+ * with ORC_HASH_MULSHIFT: h(x) = (a * x) mod 2^64 for an odd multiplier a
+ * (the textbook multiply-shift scheme of Dietzfelbinger et al., 1997, whose
+ * "shift" is the scaling map below: the position keeps the top bits).  The
+ * paper leaves the hash function open apart from its CRC-32C choice
+ * (Sec. 8.3).  With an odd multiplier the map is a bijection of the 64-bit
+ * keys. */
+uint64_t orc_mulshift(uint64_t key, uint64_t mul) { return key * mul; }
+
 /* Scaling map of Sec. 5.3.1: h_c(x) = floor(h(x) * c / U) with U = 2^64 and
  * c = 2^log2c, i.e. the top log2c bits of h. */
 uint64_t orc_home(uint64_t h, uint32_t log2c) {
@@ -96,6 +108,8 @@ typedef struct orc_table {
   uint64_t cap;
   uint64_t *cells;
   uint32_t seed_hi, seed_lo;
+  int hash_kind; /* ORC_HASH_CRC32C_PAIR (default) or ORC_HASH_MULSHIFT */
+  uint64_t mul;  /* odd multiplier of ORC_HASH_MULSHIFT */
   uint32_t alpha_num, alpha_den;
   int auto_grow;
   uint64_t used; /* non-empty cells (live keys and tombstones) */
@@ -132,8 +146,14 @@ static void set_cell(const orc_table *t, uint64_t *cells, uint64_t i, uint64_t k
 
 static uint64_t words_per_cell(const orc_table *t) { return t->layout == ORC_PACKED32 ? 1 : 2; }
 
+/* The table's 64-bit hash of key k. */
+static uint64_t table_hash(const orc_table *t, uint64_t k) {
+  if (t->hash_kind == ORC_HASH_MULSHIFT) return orc_mulshift(k, t->mul);
+  return orc_hash(k, key_bytes(t), t->seed_hi, t->seed_lo);
+}
+
 static uint64_t home_of(const orc_table *t, uint64_t k, uint32_t log2c) {
-  return orc_home(orc_hash(k, key_bytes(t), t->seed_hi, t->seed_lo), log2c);
+  return orc_home(table_hash(t, k), log2c);
 }
 
 /* Wrapping update function `up` of Algorithm 1: overwrite or add (modulo the
@@ -190,6 +210,23 @@ void orc_counts(const orc_table *t, uint64_t *used, uint64_t *live) {
 int orc_set_full_keys(orc_table *t, int on) {
   if (t->sp_present[0] || t->sp_present[1]) return -1;
   t->full_keys = on ? 1 : 0;
+  return 0;
+}
+
+/* Selects the hash function of an empty table: ORC_HASH_CRC32C_PAIR (the
+ * seeds given at creation) or ORC_HASH_MULSHIFT with the odd multiplier
+ * `mul`.  Returns -1 for a table that holds elements, an unknown kind or an
+ * even multiplier. */
+int orc_set_hash(orc_table *t, int kind, uint64_t mul) {
+  if (t->used || t->sp_present[0] || t->sp_present[1]) return -1;
+  if (kind == ORC_HASH_CRC32C_PAIR) {
+    t->hash_kind = kind;
+    t->mul = 0;
+    return 0;
+  }
+  if (kind != ORC_HASH_MULSHIFT || (mul & 1u) == 0) return -1;
+  t->hash_kind = kind;
+  t->mul = mul;
   return 0;
 }
 
@@ -553,9 +590,14 @@ typedef struct orc_item {
   uint64_t h, k, v, seq;
 } orc_item;
 
+/* The order of Sec. 5.5's sort: by the upper 32 hash bits (they hold every
+ * position bit of a table of up to 2^32 cells), then by key, then by sequence
+ * number.  For the CRC-32C pair equal upper halves mean equal CRC values and
+ * therefore equal lower halves, so this is the order of the whole 64-bit
+ * hash; for the multiplicative hash it breaks ties of the upper bits by key. */
 static int item_cmp(const void *a, const void *b) {
   const orc_item *x = (const orc_item *)a, *y = (const orc_item *)b;
-  if (x->h != y->h) return x->h < y->h ? -1 : 1;
+  if ((x->h >> 32) != (y->h >> 32)) return (x->h >> 32) < (y->h >> 32) ? -1 : 1;
   if (x->k != y->k) return x->k < y->k ? -1 : 1;
   if (x->seq != y->seq) return x->seq < y->seq ? -1 : 1;
   return 0;
@@ -565,8 +607,8 @@ static int item_cmp(const void *a, const void *b) {
  * or merges the batch into it (keep_old = 1), following the sort-based bulk
  * operation of Sec. 5.5:
  *   1. the elements (the table's live elements first, then the batch in index
- *      order) are sorted by their hash value; equal hashes by key, equal keys
- *      by sequence number;
+ *      order) are sorted by their hash value (its upper 32 bits, see
+ *      item_cmp); equal hashes by key, equal keys by sequence number;
  *   2. among equal keys all but the last are removed; with ORC_ADD the kept
  *      element carries the wrapping sum of all their values, with ORC_ASSIGN
  *      its own value (the batch's last occurrence overrides the table);
@@ -588,7 +630,7 @@ int orc_bulk_merge(orc_table *t, const void *keys, const void *vals, uint64_t n,
     for (uint64_t i = 0; i < t->cap; ++i) {
       uint64_t k = key_at(t, t->cells, i);
       if (k == ORC_EMPTY || k == ORC_TOMB) continue;
-      it[m].h = orc_hash(k, key_bytes(t), t->seed_hi, t->seed_lo);
+      it[m].h = table_hash(t, k);
       it[m].k = k;
       it[m].v = val_at(t, t->cells, i);
       it[m].seq = 0;
@@ -611,7 +653,7 @@ int orc_bulk_merge(orc_table *t, const void *keys, const void *vals, uint64_t n,
       t->sticky |= ORC_STICKY_RESERVED;
       continue;
     }
-    it[m].h = orc_hash(k, key_bytes(t), t->seed_hi, t->seed_lo);
+    it[m].h = table_hash(t, k);
     it[m].k = k;
     it[m].v = vals ? load_word(t, vals, i) : 1;
     it[m].seq = i + 1;

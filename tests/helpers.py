@@ -21,10 +21,23 @@ def split_cells(cells: np.ndarray, layout: int):
     return cells[0::2].copy(), cells[1::2].copy()
 
 
-def homes(keys: np.ndarray, layout: int, log2c: int, seed_hi=oracle.SEED_HI, seed_lo=oracle.SEED_LO):
-    kb = 4 if layout == oracle.PACKED32 else 8
-    k = keys.astype(np.uint32 if kb == 4 else np.uint64)
-    h = oracle.hash_bulk(k, kb, seed_hi, seed_lo)
+def mulshift_hash(keys: np.ndarray, mul: int) -> np.ndarray:
+    """(mul * key) mod 2^64 by numpy's wrapping u64 product (the closed form
+    of the multiplicative hash, computed without the oracle)."""
+    with np.errstate(over="ignore"):
+        return np.asarray(keys).astype(np.uint64) * np.uint64(mul)
+
+
+def homes(keys: np.ndarray, layout: int, log2c: int, seed_hi=oracle.SEED_HI, seed_lo=oracle.SEED_LO,
+          mul=None):
+    """Home cells: the top log2c bits of the CRC-32C pair hash, or of the
+    multiplicative hash when `mul` is given."""
+    if mul is not None:
+        h = mulshift_hash(keys, mul)
+    else:
+        kb = 4 if layout == oracle.PACKED32 else 8
+        k = keys.astype(np.uint32 if kb == 4 else np.uint64)
+        h = oracle.hash_bulk(k, kb, seed_hi, seed_lo)
     return (h >> np.uint64(64 - log2c)).astype(np.int64)
 
 
@@ -44,7 +57,7 @@ def run_start(occ: np.ndarray) -> np.ndarray:
 
 
 def check_invariants(cells, layout, log2c, used=None, live=None, seed_hi=oracle.SEED_HI,
-                     seed_lo=oracle.SEED_LO):
+                     seed_lo=oracle.SEED_LO, mul=None):
     """U: no live key twice.  R: every live key is reachable from its home
     along non-empty cells.  C: counters match the cells.  V: empty cells hold
     value 0."""
@@ -65,7 +78,7 @@ def check_invariants(cells, layout, log2c, used=None, live=None, seed_hi=oracle.
     q = np.flatnonzero(live_mask)
     if q.size == 0:
         return
-    p = homes(keys[q], layout, log2c, seed_hi, seed_lo)
+    p = homes(keys[q], layout, log2c, seed_hi, seed_lo, mul)
     rs = run_start(occ)[q]
     # home must lie in [run_start, q] cyclically: distance from home to q
     # (mod c) must not exceed distance from run start to q.

@@ -13,6 +13,7 @@ from tests import test_oracle_bulk as TB
 from tests import test_oracle_fullkeys as TF
 from tests import test_oracle_hash as TH
 from tests import test_oracle_migration as TM
+from tests import test_oracle_mulshift as TMS
 from tests import test_oracle_strings as TS
 from tests import test_oracle_table as TT
 
@@ -52,8 +53,16 @@ MUTANTS = [
      "if (r == 1 && kind >= 2) return 0;\n    if (r != 1 && str_eq(t, r, s, len)) {"),
     ("string_hash_one_seed", "orc_str_hash", "orc_crc32c_bytes(seed_lo, s, len)", "orc_crc32c_bytes(seed_hi, s, len)"),
     ("bulk_keeps_first", "orc_bulk_merge", ": it[i].v;", ": it[d - 1].v;"),
-    ("bulk_sorted_by_key", "item_cmp", "if (x->h != y->h) return x->h < y->h ? -1 : 1;",
+    ("bulk_sorted_by_key", "item_cmp",
+     "if ((x->h >> 32) != (y->h >> 32)) return (x->h >> 32) < (y->h >> 32) ? -1 : 1;",
      "if (x->k != y->k) return x->k < y->k ? -1 : 1;"),
+    ("bulk_order_by_whole_hash", "item_cmp",
+     "if ((x->h >> 32) != (y->h >> 32)) return (x->h >> 32) < (y->h >> 32) ? -1 : 1;",
+     "if (x->h != y->h) return x->h < y->h ? -1 : 1;"),
+    ("mulshift_32bit_product", "orc_mulshift", "return key * mul;",
+     "return (uint64_t)(uint32_t)key * (uint32_t)mul;"),
+    ("mulshift_ignored_by_table", "table_hash", "if (t->hash_kind == ORC_HASH_MULSHIFT) return orc_mulshift(k, t->mul);",
+     ";"),
     ("bulk_add_drops_table_value", "orc_bulk_merge", "it[m].v = val_at(t, t->cells, i);", "it[m].v = 0;"),
     ("bulk_no_dedup", "orc_bulk_merge", "if (d > 0 && it[d - 1].k == it[i].k) {", "if (0) {"),
     ("bulk_never_grows", "orc_bulk_merge", "while (!within_fill(t, old_n + n, 1ull << log2c)) {",
@@ -104,6 +113,10 @@ def _pins():
         for seed in range(3):
             yield lambda layout=layout, seed=seed: TF.test_sequences_with_keys_0_and_1_match_dict_model(layout, seed)
         yield lambda layout=layout: TF.test_special_keys_survive_migration_and_follow_bulk_rules(layout)
+    yield TMS.test_mulshift_closed_form
+    for layout in TT.LAYOUTS:
+        yield lambda layout=layout: TMS.test_keys_with_distinct_homes_sit_at_their_homes(layout, TMS.MULS[0])
+        yield lambda layout=layout: TMS.test_bulk_build_order_upper_half_then_key(layout)
     yield TS.test_string_hash_equals_word_hash_and_seed_closed_form
     for seed in range(3):
         yield lambda seed=seed: TS.test_sequences_match_dict_model(seed)
