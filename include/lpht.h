@@ -82,6 +82,17 @@ extern "C" {
 #define LPHT_ASSIGN 0u
 #define LPHT_ADD 1u
 
+/* ---- hash functions (lpht_config.hash) ----
+ * LPHT_HASH_CRC32C_PAIR: h(x) = CRC(seed_hi, x) * 2^32 + CRC(seed_lo, x), the
+ *   CRC-32C register update over the key's 4 (PACKED32) or 8 (KV64)
+ *   little-endian bytes, as the paper computes it with two crc32 instructions
+ *   (Sec. 8.3).
+ * LPHT_HASH_MULSHIFT: h(x) = (mul * x) mod 2^64 with an odd `mul`
+ *   (multiplicative hashing); a bijection of the 64-bit keys, one multiply per
+ *   operation.  Not available for string tables. */
+#define LPHT_HASH_CRC32C_PAIR 0u
+#define LPHT_HASH_MULSHIFT 1u
+
 /* Allocator hook: returns device memory of `bytes` bytes (256-byte aligned)
  * usable in stream order on `stream`, or NULL.  `free` releases it in stream
  * order.  Both NULL selects the library's pool (hipMallocFromPoolAsync /
@@ -108,6 +119,12 @@ typedef struct lpht_config {
   uint32_t full_keys;     /* 0: keys 0 and 1 are reserved; 1: full key space (Sec. 5.6): keys 0
                            * and 1 are stored in two special slots of the table object; the
                            * batch and serving APIs do not take such tables */
+  uint32_t hash;          /* LPHT_HASH_CRC32C_PAIR (default): the paper's two CRC-32C with
+                           * seed_hi / seed_lo (Sec. 8.3); LPHT_HASH_MULSHIFT: h(x) = mul * x
+                           * mod 2^64.  Either way the position is the top log2 c bits of h
+                           * (the scaling map of Sec. 5.3.1), so migration works unchanged */
+  uint32_t reserved0;     /* must be 0 */
+  uint64_t mul;           /* LPHT_HASH_MULSHIFT: the multiplier, odd; ignored otherwise */
   lpht_alloc_fn alloc;
   lpht_free_fn free;
   void *alloc_ctx;
@@ -145,13 +162,14 @@ typedef struct lpht_stats {
 
 typedef struct lpht_table lpht_table; /* opaque; owned by the library */
 
-/* Fills `cfg` with: KV64, log2_capacity 12, seeds 0x9E3779B9 / 0xFFFFFFFF,
- * alpha = 1/2, auto_grow 0, default allocator. */
+/* Fills `cfg` with: KV64, log2_capacity 12, the CRC-32C pair hash with seeds
+ * 0x9E3779B9 / 0xFFFFFFFF, alpha = 1/2, auto_grow 0, default allocator. */
 void lpht_config_default(lpht_config *cfg);
 
 /* Creates an empty table on the current HIP device: every cell is set to
- * empty_key with value 0 (Sec. 4, "Initialization").  Errors: INVALID, OOM,
- * DEVICE.  On error *out is NULL. */
+ * empty_key with value 0 (Sec. 4, "Initialization").  Errors: INVALID (a
+ * field out of range, an unknown hash, an even MULSHIFT multiplier, reserved0
+ * not 0), OOM, DEVICE.  On error *out is NULL. */
 int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out);
 
 /* Empties the table in place: every cell becomes empty_key with value 0,
@@ -208,11 +226,13 @@ int lpht_grow(lpht_table *t, uint32_t log2_new_capacity, void *stream);
 
 /* Insertion that grows the table while the kernel runs (Sec. 5.3.2, the
  * (semi-)synchronized protocol, with the approximate size of Sec. 5.2): one
- * cooperative launch inserts the n keys (add = 0: insert, the first of equal
- * keys wins, flag 1 for the operation that inserted the key, 0 when present;
- * add = 1: insert-or-add, the value gets the sum of all values (vals NULL: 1
- * each), exact).  Wavefronts keep local counts of successful insertions and
- * add them to a global counter after a random number (1..64) of them; when
+ * cooperative launch inserts the n keys (add = 0: insert; of equal absent
+ * keys exactly one operation inserts, flag 1, and the stored value is its
+ * value, the others get 0 like operations on present keys; add = 1:
+ * insert-or-add, the value gets the sum of all values (vals NULL: 1 each),
+ * exact).  Wavefronts keep local counts of successful insertions and add them
+ * to a global counter after a random number (1..64 r, r = rounds of 64
+ * operations per chunk, 1..64 growing with the table) of them; when
  * that counter reaches alpha * capacity all wavefronts stop taking work,
  * migrate the table together into one of twice the size, and go on.  The
  * capacity therefore follows the number of distinct keys actually inserted,
@@ -254,11 +274,19 @@ int lpht_build(lpht_table *t, const void *keys, const void *vals, uint64_t n, ui
  * capacity.  Errors and synchronisation as lpht_build. */
 int lpht_merge(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, void *stream);
 
-/* Exact counts: `used` non-empty cells (live keys and tombstones), `live`
- * keys.  Synchronises `stream`.  Either pointer may be NULL. */
+/* Size (Sec. 4, "Size"; the counters of Sec. 5.2): `used` = non-empty cells
+ * (live keys and tombstones, the quantity the growth trigger of Sec. 5.4
+ * watches), `live` = live keys (the table's size).  Exact: every kernel adds
+ * its per-wavefront deltas before it ends, so at a call boundary the counts
+ * equal a sequential table's.  Synchronises `stream`.  Either pointer may be
+ * NULL.  Errors: INVALID (NULL table), DEVICE. */
 int lpht_count(lpht_table *t, uint64_t *used, uint64_t *live, void *stream);
 
-/* Current capacity in cells and its log2 (host-side, no synchronisation). */
+/* Capacity (Sec. 7: capacities are powers of two, so the scaling map of
+ * Sec. 5.3.1 is a shift): `cells` = 2^log2_capacity cells, as created or as
+ * left by the last migration; either pointer may be NULL.  Host-side, no
+ * synchronisation (migrations are decided on the host, so the host always
+ * knows the capacity).  Errors: INVALID (NULL table). */
 int lpht_capacity(const lpht_table *t, uint64_t *cells, uint32_t *log2_capacity);
 
 /* Bytes of one cell: 8 (PACKED32) or 16 (KV64). */
@@ -484,6 +512,15 @@ const char *lpht_strerror(int code);
 
 /* Library version string. */
 const char *lpht_version(void);
+
+/* Orderly shutdown: waits for every device that has a library memory pool,
+ * returns the pools' memory and destroys them, so that nothing of the
+ * library is left for the HIP runtime's own teardown at process exit.  Call
+ * it after every table, string table and server has been destroyed (their
+ * memory comes from the pools); a table created afterwards makes a new pool.
+ * Errors: INVALID (pool memory still in use: some object is alive; nothing is
+ * released), DEVICE. */
+int lpht_release_pools(void);
 
 /* ---- string keys (Sec. 5.7, "Complex Keys") ----
  *

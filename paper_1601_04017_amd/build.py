@@ -40,16 +40,40 @@ def _stale(out, sources, headers) -> bool:
     return False
 
 
-def _hipcc(out, sources, verbose):
-    tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp]
-    cmd += [os.path.join(CSRC, f) for f in sources]
+OBJ_DIR = os.path.join(ROOT, "_build")
+
+
+def _run(cmd, what, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True), what
+
+
+def _hipcc(out, sources, verbose):
+    """Compiles every source to an object in parallel (each translation unit
+    carries its own gfx950 code object), then links the shared library."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    cflags = [f for f in FLAGS if f != "-shared"]
+    objs, procs = [], []
+    for f in sources:
+        obj = os.path.join(OBJ_DIR, os.path.splitext(f)[0] + ".o")
+        objs.append(obj)
+        procs.append(_run([HIPCC, *cflags, *inc, "-c", "-o", obj, os.path.join(CSRC, f)], f, verbose))
+    failed = []
+    for p, what in procs:
+        log = p.communicate()[0]
+        if p.returncode != 0:
+            sys.stderr.write(log)
+            failed.append(what)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
+    tmp = out + ".tmp"
+    p, _ = _run([HIPCC, *FLAGS, "-o", tmp, *objs], out, verbose)
+    log = p.communicate()[0]
+    if p.returncode != 0:
+        sys.stderr.write(log)
+        raise RuntimeError(f"hipcc failed linking {os.path.basename(out)}")
     os.replace(tmp, out)
 
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -58,6 +59,8 @@ uint64_t cell_bytes(uint32_t layout) { return layout == LPHT_PACKED32 ? 8u : 16u
 constexpr int kMaxDevices = 64;
 std::mutex g_pool_mu;
 hipMemPool_t g_pools[kMaxDevices];
+// blocks handed out by pool_alloc and not yet given back to pool_free
+std::atomic<long long> g_pool_blocks{0};
 
 hipMemPool_t device_pool(int dev) {
   if (dev < 0 || dev >= kMaxDevices) return nullptr;
@@ -82,7 +85,36 @@ void *pool_alloc(int device, size_t bytes, hipStream_t s) {
   if (!pool) return nullptr;
   void *p = nullptr;
   if (hipMallocFromPoolAsync(&p, bytes, pool, s) != hipSuccess) return nullptr;
+  g_pool_blocks.fetch_add(1);
   return p;
+}
+
+void pool_free(void *p, hipStream_t s) {
+  if (!p) return;
+  (void)hipFreeAsync(p, s);
+  g_pool_blocks.fetch_sub(1);
+}
+
+int release_pools() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool_blocks.load() != 0) return LPHT_ERR_INVALID;
+  int cur = 0;
+  bool have_cur = false;
+  int rc = LPHT_OK;
+  for (int d = 0; d < kMaxDevices; ++d) {
+    if (!g_pools[d]) continue;
+    if (!have_cur) {
+      if (hipGetDevice(&cur) != hipSuccess) return LPHT_ERR_DEVICE;
+      have_cur = true;
+    }
+    // the frees of destroyed tables complete in stream order: wait for them
+    if (hipSetDevice(d) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        hipMemPoolTrimTo(g_pools[d], 0) != hipSuccess || hipMemPoolDestroy(g_pools[d]) != hipSuccess)
+      rc = LPHT_ERR_DEVICE;
+    g_pools[d] = nullptr;
+  }
+  if (have_cur) (void)hipSetDevice(cur);
+  return rc;
 }
 
 void *dev_alloc(lpht_table *t, size_t bytes, hipStream_t s) {
@@ -96,7 +128,7 @@ void dev_free(lpht_table *t, void *p, size_t bytes, hipStream_t s) {
     t->cfg.free(p, bytes, (void *)s, t->cfg.alloc_ctx);
     return;
   }
-  (void)hipFreeAsync(p, s);
+  pool_free(p, s);
 }
 
 void fill_launch(lpht_table *t) {
@@ -222,10 +254,10 @@ int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s) {
   }
   hipError_t e = launch_set_status(t->status, 0, 0, 0, s);
   if (e == hipSuccess && shrink)
-    e = launch_shrink(t->cells, t->log2c, nc, log2_new, t->cfg.layout, t->crc_hi, t->crc_lo, scratch,
+    e = launch_shrink(t->cells, t->log2c, nc, log2_new, t->cfg.layout, t->crc_hi, t->crc_lo, t->mul, scratch,
                       t->status, t->launch, s);
   else if (e == hipSuccess)
-    e = launch_migrate(t->cells, t->log2c, nc, log2_new, t->cfg.layout, t->crc_hi, t->crc_lo,
+    e = launch_migrate(t->cells, t->log2c, nc, log2_new, t->cfg.layout, t->crc_hi, t->crc_lo, t->mul,
                        old_full, t->status, t->launch, s);
   if (scratch) dev_free(t, scratch, sb, s);
   if (e != hipSuccess) {
@@ -317,6 +349,7 @@ BulkArgs make_args(lpht_table *t) {
   a.layout = t->cfg.layout;
   a.crc_hi = t->crc_hi;
   a.crc_lo = t->crc_lo;
+  a.mul = t->mul;
   a.status = t->status;
   return a;
 }
@@ -575,6 +608,9 @@ int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out) {
   if (cfg->max_fill_num == 0 || cfg->max_fill_den == 0 || cfg->max_fill_num > cfg->max_fill_den)
     return LPHT_ERR_INVALID;
   if (cfg->full_keys > 1) return LPHT_ERR_INVALID;
+  if (cfg->reserved0 != 0) return LPHT_ERR_INVALID;
+  if (cfg->hash != LPHT_HASH_CRC32C_PAIR && cfg->hash != LPHT_HASH_MULSHIFT) return LPHT_ERR_INVALID;
+  if (cfg->hash == LPHT_HASH_MULSHIFT && (cfg->mul & 1u) == 0) return LPHT_ERR_INVALID;
   if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return LPHT_ERR_INVALID;
   lpht_table *t = new (std::nothrow) lpht_table();
   if (!t) return LPHT_ERR_OOM;
@@ -599,6 +635,7 @@ int lpht_create(const lpht_config *cfg, void *stream, lpht_table **out) {
   const int kb = cfg->layout == LPHT_PACKED32 ? 4 : 8;
   t->crc_hi = crc0_bytes(cfg->seed_hi, kb);
   t->crc_lo = crc0_bytes(cfg->seed_lo, kb);
+  t->mul = cfg->hash == LPHT_HASH_MULSHIFT ? cfg->mul : 0;
   hipStream_t s = (hipStream_t)stream;
   t->status = (DevStatus *)dev_alloc(t, sizeof(DevStatus), s);
   if (!t->status) {
@@ -743,6 +780,7 @@ int bulk_merge(lpht_table *t, const void *keys, const void *vals, uint64_t n, ui
   a.log2_new = log2_new;
   a.crc_hi = t->crc_hi;
   a.crc_lo = t->crc_lo;
+  a.mul = t->mul;
   a.status = t->status;
   a.scratch = scratch;
   a.num_cus = t->launch.num_cus;
@@ -824,6 +862,7 @@ int lpht_insert_async(lpht_table *t, const void *keys, const void *vals, uint64_
   a.alpha_den = t->cfg.max_fill_den;
   a.crc_hi = t->crc_hi;
   a.crc_lo = t->crc_lo;
+  a.mul = t->mul;
   a.status = t->status;
   a.grid = grid;
   const size_t cb = cell_bytes(t->cfg.layout);
@@ -1030,5 +1069,7 @@ const char *lpht_strerror(int code) {
 }
 
 const char *lpht_version(void) { return "lpht 0.1 gfx950"; }
+
+int lpht_release_pools(void) { return release_pools(); }
 
 }  // extern "C"

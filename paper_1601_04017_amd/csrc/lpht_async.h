@@ -49,6 +49,7 @@ struct AsyncArgs {
   uint64_t used0;         // non-empty cells of ladder[0] at the start (exact)
   uint32_t alpha_num, alpha_den;
   uint32_t crc_hi, crc_lo;
+  uint64_t mul;           // nonzero: multiplicative hash mul * key (else the CRC-32C pair)
   AsyncCtl *ctl;
   DevStatus *status;      // sticky error bits (reserved keys)
   uint32_t grid;          // workgroups of 256 threads, all resident (cooperative launch)

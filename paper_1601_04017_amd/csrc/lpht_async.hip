@@ -6,8 +6,8 @@
 // insertions (or insert-or-add operations).  Wavefronts take chunks of 64 r
 // operations from a shared counter (r rounds, up to 64, fewer while the
 // table's free cells are few), one operation per lane per round (linear
-// probing with compare-and-swap, Alg. 1; equal keys of a round are combined
-// in LDS first).  Each wavefront counts its successful insertions locally
+// probing with compare-and-swap, Alg. 1); equal keys of a chunk are combined
+// in LDS and applied once at the chunk's end.  Each wavefront counts its successful insertions locally
 // and adds the count to the global counter I after a randomised number
 // (1..64 r) of them; when the addition makes I reach alpha * c, it raises
 // the growing flag.
@@ -165,7 +165,7 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
       const u64 k = key_at<L>(o.cells, i);
       if (k == kEmpty || k == kTomb) continue;
       const u64 v = L == 0 ? (ld64((const u64 *)o.cells + i) >> 32) : ld64((const u64 *)o.cells + 2 * i + 1);
-      u64 p = home_of<L>(T, k, a.crc_hi, a.crc_lo, nv.log2c);
+      u64 p = home_of<L>(T, k, a.crc_hi, a.crc_lo, a.mul, nv.log2c);
       for (u64 step = 0; step <= nv.mask; ++step, p = (p + 1) & nv.mask) {
         if (L == 0) {
           if (cas64((u64 *)nv.cells + p, kEmpty, k | (v << 32)) == kEmpty) break;
@@ -206,11 +206,13 @@ __device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e
 // (insert: the representative's value), and the representative gets the
 // operation's flag (the others 0).  A key that finds no free slot within
 // kChunkProbe steps is applied at once, on its own; once three quarters of
-// the slots are taken, keys only look for their slot (plain loads) and
-// claim none, so a chunk of distinct keys pays little for the table.
+// the slots are taken, keys only look for their slot (plain loads over the
+// same kChunkProbe steps, stopping at an empty slot) and claim none, so a
+// chunk of distinct keys pays little for the table.  A claimed key sits
+// fewer than kChunkProbe steps from its start with no empty slot before it,
+// so every later operation of that key in the chunk finds it.
 constexpr uint32_t kChunkSlots = 512;
 constexpr uint32_t kChunkProbe = 16;
-constexpr uint32_t kChunkLookup = 8;
 struct ChunkLds {
   u64 key[kChunkSlots];
   u64 acc[kChunkSlots];
@@ -290,7 +292,7 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
     // the table operation for key with value d in the current table: 1
     // inserted, 0 present (d added in add mode), kFlagFull no empty cell
     auto apply_op = [&](u64 key, u64 d) -> uint8_t {
-      u64 p = home_of<L>(T, key, a.crc_hi, a.crc_lo, v.log2c);
+      u64 p = home_of<L>(T, key, a.crc_hi, a.crc_lo, a.mul, v.log2c);
       for (u64 step = 0; step <= v.mask; ++step, p = (p + 1) & v.mask) {
         u64 cur = key_at<L>(v.cells, p);
         if (cur == kEmpty) {
@@ -374,7 +376,7 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
             }
           } else {
             // no lane claims a slot in this round: the keys are fixed
-            for (uint32_t t = 0; t < kChunkLookup; ++t, slot = (slot + 1) & (kChunkSlots - 1)) {
+            for (uint32_t t = 0; t < kChunkProbe; ++t, slot = (slot + 1) & (kChunkSlots - 1)) {
               const u64 k = C.key[slot];
               if (k == key) {
                 held = true;

@@ -26,6 +26,7 @@ struct BulkMergeArgs {
   void *new_cells;         // 2^log2_new cells, need not be initialised
   uint32_t log2_new;       // 6 .. kBulkMaxLog2
   uint32_t crc_hi, crc_lo;
+  uint64_t mul;            // nonzero: multiplicative hash mul * key (else the CRC-32C pair)
   DevStatus *status;       // counts zeroed by the caller; receives used = live = distinct keys
   void *scratch;           // bulk_merge_scratch_bytes(...) bytes of device memory
   uint32_t num_cus;

@@ -83,6 +83,7 @@ struct BmK {
   uint64_t c, nblocks, per, ntiles;
   uint64_t cap_items;  // staging entries (an upper bound of the elements)
   uint32_t crc_hi, crc_lo;
+  u64 mul;             // nonzero: multiplicative hash
   DevStatus *st;
   BulkMergeCtl *ctl;
   void *keyA, *valA;
@@ -95,8 +96,11 @@ struct BmK {
 
 __device__ __forceinline__ uint32_t top_bits(uint32_t u, uint32_t bits) { return bits ? u >> (32 - bits) : 0u; }
 
+// The upper 32 bits of the table's hash: the sort key (ties broken by key),
+// holding every position bit of a table of up to 2^32 cells.
 template <int L>
-__device__ __forceinline__ uint32_t sort_hash(const uint32_t (*T)[256], KT<L> k, uint32_t crc_hi) {
+__device__ __forceinline__ uint32_t sort_hash(const uint32_t (*T)[256], KT<L> k, uint32_t crc_hi, u64 mul) {
+  if (mul) return (uint32_t)(((u64)k * mul) >> 32);
   const uint32_t c = (L == 0) ? crc0_u32(T, (uint32_t)k) : crc0_u64(T, (u64)k);
   return c ^ crc_hi;
 }
@@ -263,7 +267,7 @@ __global__ void __launch_bounds__(256) k_bm_count(BmK k) {
     KT<L> key, val;
     uint32_t seq;
     if (!load_elem<L>(k, e, key, val, seq, err)) continue;
-    atomicAdd(&hist[top_bits(sort_hash<L>(T, key, k.crc_hi), k.l1_bits)], 1u);
+    atomicAdd(&hist[top_bits(sort_hash<L>(T, key, k.crc_hi, k.mul), k.l1_bits)], 1u);
   }
   if (err) atomicOr(&s_err, err);
   __syncthreads();
@@ -342,7 +346,7 @@ __global__ void __launch_bounds__(256) k_bm_scatter(BmK k) {
       const u64 e = tile + threadIdx.x + 256 * j;
       KT<L> key = 0;
       ok[j] = e < hi && load_elem<L>(k, e, key, vv[j], sq[j], err);
-      slot[j] = ok[j] ? combine_claim<L>(cb, key, sort_hash<L>(T, key, k.crc_hi)) : 0;
+      slot[j] = ok[j] ? combine_claim<L>(cb, key, sort_hash<L>(T, key, k.crc_hi, k.mul)) : 0;
     }
     __syncthreads();
 #pragma unroll
@@ -363,7 +367,7 @@ __global__ void __launch_bounds__(256) k_bm_scatter(BmK k) {
       const uint32_t i = threadIdx.x + 256 * j;
       bin[j] = ~0u;
       if (cb.key[i] != 0) {
-        bin[j] = top_bits(sort_hash<L>(T, cb.key[i], k.crc_hi), k.l1_bits);
+        bin[j] = top_bits(sort_hash<L>(T, cb.key[i], k.crc_hi, k.mul), k.l1_bits);
         rk[j] = atomicAdd(&toff[bin[j]], 1u);
       }
     }
@@ -441,7 +445,7 @@ __global__ void __launch_bounds__(1024) k_bm_partition(BmK k) {
   for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) {
     const KT<L> key = keyA[out0 + j];
     if (key == 0) continue;
-    atomicAdd(&hist[top_bits(sort_hash<L>(T, key, k.crc_hi), k.nb_bits) & mask2], 1u);
+    atomicAdd(&hist[top_bits(sort_hash<L>(T, key, k.crc_hi, k.mul), k.nb_bits) & mask2], 1u);
   }
   __syncthreads();
   // block regions inside the bin's output range, sized by the raw counts
@@ -473,7 +477,7 @@ __global__ void __launch_bounds__(1024) k_bm_partition(BmK k) {
     if (ok) {
       val = valA[out0 + j];
       seq = k.seqA[out0 + j];
-      p = combine_claim<L>(cb, key, sort_hash<L>(T, key, k.crc_hi));
+      p = combine_claim<L>(cb, key, sort_hash<L>(T, key, k.crc_hi, k.mul));
     }
     __syncthreads();
     combine_values<L>(cb, ok, p, val, seq, k.op);
@@ -481,7 +485,7 @@ __global__ void __launch_bounds__(1024) k_bm_partition(BmK k) {
     for (uint32_t i = threadIdx.x; i < kSlots; i += blockDim.x) {
       const KT<L> kk = cb.key[i];
       if (kk == 0) continue;
-      const uint32_t u = sort_hash<L>(T, kk, k.crc_hi);
+      const uint32_t u = sort_hash<L>(T, kk, k.crc_hi, k.mul);
       const uint32_t q = atomicAdd(&hist[top_bits(u, k.nb_bits) & mask2], 1u);
       keyB[out0 + q] = kk;
       valB[out0 + q] = cb.val[i];
@@ -601,7 +605,7 @@ __global__ void __launch_bounds__(256) k_bm_block_wave(BmK k) {
       b.key[i] = keyB[(u64)off + i];
       b.val[i] = valB[(u64)off + i];
       b.seq[i] = k.seqB[(u64)off + i];
-      b.u[i] = sort_hash<L>(T, b.key[i], k.crc_hi);
+      b.u[i] = sort_hash<L>(T, b.key[i], k.crc_hi, k.mul);
       b.ix[i] = (uint16_t)i;
     }
     wave_sync();
@@ -692,7 +696,7 @@ __global__ void __launch_bounds__(256) k_bm_block(BmK k) {
       b.key[i] = keyB[(u64)off + i];
       b.val[i] = valB[(u64)off + i];
       b.seq[i] = k.seqB[(u64)off + i];
-      b.u[i] = sort_hash<L>(T, b.key[i], k.crc_hi);
+      b.u[i] = sort_hash<L>(T, b.key[i], k.crc_hi, k.mul);
       b.ix[i] = (uint16_t)i;
     }
     __syncthreads();
@@ -768,7 +772,7 @@ __global__ void __launch_bounds__(256) k_bm_big_block(BmK k) {
     const u64 blk = k.big_list[bi];
     const u64 off = k.blk_off[blk];
     const uint32_t cnt = k.blk_cnt[blk];
-    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) uu[off + i] = sort_hash<L>(T, keyB[off + i], k.crc_hi);
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) uu[off + i] = sort_hash<L>(T, keyB[off + i], k.crc_hi, k.mul);
     __syncthreads();
     u64 P = 1;
     while (P < cnt) P <<= 1;
@@ -1169,6 +1173,7 @@ hipError_t launch_bulk_merge(const BulkMergeArgs &a, hipStream_t s) {
   k.ntiles = g.ntiles;
   k.crc_hi = a.crc_hi;
   k.crc_lo = a.crc_lo;
+  k.mul = a.mul;
   k.st = a.status;
   Carve cv{(unsigned char *)a.scratch};
   carve_all(cv, a.max_items, g, a.layout, k);

@@ -51,12 +51,25 @@ __device__ __forceinline__ uint32_t crc0_u32(const uint32_t (*T)[256], uint32_t 
   return T[3][x & 0xFF] ^ T[2][(x >> 8) & 0xFF] ^ T[1][(x >> 16) & 0xFF] ^ T[0][x >> 24];
 }
 
+// The table's 64-bit hash of a key.  mul == 0: the CRC-32C pair
+// h = CRC(seed_hi, x) * 2^32 + CRC(seed_lo, x) (Sec. 8.3), where the CRC
+// register update is linear over GF(2), so CRC(seed, x) = CRC(0, x) ^
+// CRC(seed, 0) and both halves come from one table evaluation plus the host's
+// constants crc_hi = CRC(seed_hi, 0), crc_lo = CRC(seed_lo, 0).  Otherwise the
+// multiplicative hash mul * x mod 2^64.
+template <int LAYOUT>
+__device__ __forceinline__ u64 hash_of(const uint32_t (*T)[256], u64 key, uint32_t crc_hi,
+                                       uint32_t crc_lo, u64 mul) {
+  if (mul) return key * mul;
+  uint32_t c = (LAYOUT == 0) ? crc0_u32(T, (uint32_t)key) : crc0_u64(T, key);
+  return ((u64)(c ^ crc_hi) << 32) | (u64)(c ^ crc_lo);
+}
+
+// Position (Sec. 5.3.1's scaling map with U = 2^64): the top log2c bits.
 template <int LAYOUT>
 __device__ __forceinline__ u64 home_of(const uint32_t (*T)[256], u64 key, uint32_t crc_hi,
-                                       uint32_t crc_lo, uint32_t log2c) {
-  uint32_t c = (LAYOUT == 0) ? crc0_u32(T, (uint32_t)key) : crc0_u64(T, key);
-  u64 h = ((u64)(c ^ crc_hi) << 32) | (u64)(c ^ crc_lo);
-  return h >> (64 - log2c);
+                                       uint32_t crc_lo, u64 mul, uint32_t log2c) {
+  return hash_of<LAYOUT>(T, key, crc_hi, crc_lo, mul) >> (64 - log2c);
 }
 
 // ---------------------------------------------------------------- atomics

@@ -24,7 +24,8 @@ struct lpht_table {
   uint32_t log2_min;  // the created capacity: the growth rule never shrinks below it
   void *cells;
   lpht::DevStatus *status;
-  uint32_t crc_hi, crc_lo;
+  uint32_t crc_hi, crc_lo;  // CRC-32C of the seeds over zero key bytes (the hash's constants)
+  uint64_t mul;             // nonzero: the multiplicative hash mul * key instead of the CRC pair
   // host view of the counts for the growth rule: exact at the last
   // synchronisation, plus an upper bound of insertions since then
   uint64_t known_used, known_live, pending;
@@ -63,6 +64,7 @@ uint64_t cell_bytes(uint32_t layout);
 void *dev_alloc(lpht_table *t, size_t bytes, hipStream_t s);
 void dev_free(lpht_table *t, void *p, size_t bytes, hipStream_t s);
 void *pool_alloc(int device, size_t bytes, hipStream_t s);
+void pool_free(void *p, hipStream_t s);
 void fill_launch(lpht_table *t);
 bool tuning_ok(const lpht_tuning *u);
 bool within_fill(const lpht_table *t, uint64_t x, uint64_t c);

@@ -53,6 +53,7 @@ struct BulkArgs {
   const uint8_t *kinds; // may be null; else only operations with kinds[i] == kind_sel run
   uint32_t kind_sel;
   uint32_t pad;
+  uint64_t mul;         // nonzero: multiplicative hash mul * key; 0: the CRC-32C pair
 };
 
 struct LaunchCfg {
@@ -86,7 +87,8 @@ hipError_t launch_recount(const void *cells, uint32_t log2c, uint32_t layout, De
 // counts (the caller zeroes them first).
 hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_cells,
                           uint32_t log2_new, uint32_t layout, uint32_t crc_hi, uint32_t crc_lo,
-                          int old_is_full, DevStatus *st, const LaunchCfg &cfg, hipStream_t s);
+                          uint64_t mul, int old_is_full, DevStatus *st, const LaunchCfg &cfg,
+                          hipStream_t s);
 
 // ---- persistent serving kernel ----
 // Requests are posted by the host into a ring in pinned host memory; one

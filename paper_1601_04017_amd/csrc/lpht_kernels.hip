@@ -194,7 +194,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
       if (loc < cnt) {
         const u64 kk = load_key_in<LAYOUT>(A.keys, rbase + loc);
         skeys[loc] = kk;
-        shome[loc] = (kk == kEmpty || kk == kTomb) ? 0 : home_of<LAYOUT>(T, kk, A.crc_hi, A.crc_lo, A.log2c);
+        shome[loc] = (kk == kEmpty || kk == kTomb) ? 0 : home_of<LAYOUT>(T, kk, A.crc_hi, A.crc_lo, A.mul, A.log2c);
       }
     }
     wave_sync();
@@ -231,7 +231,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         continue;
       }
       d = A.vals ? ld_word<LAYOUT, RESIDENT>(A.vals, i) : 1;
-      const u64 h = (!RESIDENT && shome) ? shome[loc] : home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
+      const u64 h = (!RESIDENT && shome) ? shome[loc] : home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.mul, A.log2c);
       base = h & ~(u64)(G - 1);
       first = (uint32_t)(h & (G - 1));
       windows = 0;
@@ -561,7 +561,7 @@ __device__ __forceinline__ uint8_t upsert_add_one(const BulkArgs &A, const uint3
                                                   u64 d, long long &d_used, long long &d_live,
                                                   uint32_t &err) {
   const u64 cap = 1ull << A.log2c, mask = cap - 1;
-  u64 p = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.log2c);
+  u64 p = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.mul, A.log2c);
   for (u64 probes = 0; probes < cap; ++probes, p = (p + 1) & mask) {
     if (LAYOUT == 0) {
       u64 *w = (u64 *)A.cells + p;
@@ -795,7 +795,7 @@ template <int LAYOUT>
 __global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, uint32_t log2_old,
                                                         void *new_cells, uint32_t log2_new,
                                                         uint32_t crc_hi, uint32_t crc_lo,
-                                                        int old_is_full, int guarded,
+                                                        u64 mul, int old_is_full, int guarded,
                                                         DevStatus *st) {
   __shared__ uint32_t T[8][256];
   __shared__ long long s_acc[2];
@@ -833,7 +833,7 @@ __global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, u
       }
       if (key == kEmpty) break;
       if (key == kTomb) continue;
-      u64 p = home_of<LAYOUT>(T, key, crc_hi, crc_lo, log2_new);
+      u64 p = home_of<LAYOUT>(T, key, crc_hi, crc_lo, mul, log2_new);
       if (LAYOUT == 0) {
         u64 *nc = (u64 *)new_cells;
         while ((nc[p] & 0xFFFFFFFFull) != kEmpty) p = (p + 1) & nmask;
@@ -893,7 +893,7 @@ constexpr int32_t kCellEmpty = -1, kCellTomb = -2, kCellFar = -3;  // window cel
 template <int LAYOUT, int Q>
 __global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint32_t log2_old,
                                                      void *new_cells, uint32_t g, uint32_t crc_hi,
-                                                     uint32_t crc_lo, DevStatus *st) {
+                                                     uint32_t crc_lo, u64 mul, DevStatus *st) {
   __shared__ uint32_t T[8][256];
   __shared__ long long s_acc[2];
   __shared__ uint32_t s_err;
@@ -964,7 +964,7 @@ __global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint
       int32_t rel = key == kEmpty ? kCellEmpty : kCellTomb;
       if (key != kEmpty && key != kTomb) {
         // new home, unwrapped consistently with this cell's old position
-        const u64 hn = home_of<LAYOUT>(T, key, crc_hi, crc_lo, log2_new);
+        const u64 hn = home_of<LAYOUT>(T, key, crc_hi, crc_lo, mul, log2_new);
         const u64 oh = hn >> g;
         const long long x = wbase + (long long)t;
         const u64 delta = ((u64)x - oh) & mask;
@@ -1803,7 +1803,8 @@ hipError_t launch_recount(const void *cells, uint32_t log2c, uint32_t layout, De
 
 hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_cells,
                           uint32_t log2_new, uint32_t layout, uint32_t crc_hi, uint32_t crc_lo,
-                          int old_is_full, DevStatus *st, const LaunchCfg &cfg, hipStream_t s) {
+                          uint64_t mul, int old_is_full, DevStatus *st, const LaunchCfg &cfg,
+                          hipStream_t s) {
   const u64 cap = 1ull << log2_old;
   const u64 new_bytes = (1ull << log2_new) * (layout == 0 ? 8ull : 16ull);
   const uint32_t g = log2_new - log2_old;
@@ -1827,7 +1828,7 @@ hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_ce
     if (grid > need) grid = need;
 #define LPHT_MIG_LAUNCH(L, Q)                                                                    \
   hipLaunchKernelGGL((k_migrate_lds<L, Q>), dim3((uint32_t)grid), dim3(64 * wpb), lds, s, old_cells, \
-                     log2_old, new_cells, g, crc_hi, crc_lo, st)
+                     log2_old, new_cells, g, crc_hi, crc_lo, (u64)mul, st)
     switch (mig_window(mb) / 64) {
       case 8: if (layout == 0) LPHT_MIG_LAUNCH(0, 8); else LPHT_MIG_LAUNCH(1, 8); break;
       case 12: if (layout == 0) LPHT_MIG_LAUNCH(0, 12); else LPHT_MIG_LAUNCH(1, 12); break;
@@ -1850,10 +1851,10 @@ hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_ce
   const int guarded = lds_path ? 1 : 0;
   if (layout == 0)
     hipLaunchKernelGGL(k_migrate_simple<0>, dim3(sgrid), dim3(256), 0, s, old_cells, log2_old,
-                       new_cells, log2_new, crc_hi, crc_lo, old_is_full, guarded, st);
+                       new_cells, log2_new, crc_hi, crc_lo, (u64)mul, old_is_full, guarded, st);
   else
     hipLaunchKernelGGL(k_migrate_simple<1>, dim3(sgrid), dim3(256), 0, s, old_cells, log2_old,
-                       new_cells, log2_new, crc_hi, crc_lo, old_is_full, guarded, st);
+                       new_cells, log2_new, crc_hi, crc_lo, (u64)mul, old_is_full, guarded, st);
   return hipGetLastError();
 }
 

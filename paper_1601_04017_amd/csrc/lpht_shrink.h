@@ -28,7 +28,7 @@ size_t shrink_scratch_bytes(uint32_t log2_old, uint32_t log2_new);
 // live counts (the caller zeroes them first); sets kErrFull if an element
 // found no empty cell.
 hipError_t launch_shrink(void *old_cells, uint32_t log2_old, void *new_cells, uint32_t log2_new,
-                         uint32_t layout, uint32_t crc_hi, uint32_t crc_lo, uint32_t *scratch,
+                         uint32_t layout, uint32_t crc_hi, uint32_t crc_lo, uint64_t mul, uint32_t *scratch,
                          DevStatus *st, const LaunchCfg &cfg, hipStream_t s);
 
 }  // namespace lpht

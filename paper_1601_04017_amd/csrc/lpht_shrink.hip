@@ -87,7 +87,7 @@ __device__ __forceinline__ bool insert_absent(void *cells, u64 mask, u64 home, u
 template <int LAYOUT>
 __global__ void __launch_bounds__(64 * kWavesPerBlock)
     k_shrink_local(void *old_cells, uint32_t log2_old, void *new_cells, uint32_t log2_new,
-                   uint32_t crc_hi, uint32_t crc_lo, uint32_t *counts, DevStatus *st) {
+                   uint32_t crc_hi, uint32_t crc_lo, u64 mul, uint32_t *counts, DevStatus *st) {
   __shared__ uint32_t T[8][256];
   __shared__ u64 s_key[kWavesPerBlock][kShrinkBlock];  // PACKED32: whole cell words
   __shared__ u64 s_val[LAYOUT == 0 ? 1 : kWavesPerBlock][LAYOUT == 0 ? 1 : kShrinkBlock];
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock)
         const u64 key = key_word<LAYOUT>(cur[k]);
         bool spill = false;
         if (key != kEmpty && key != kTomb) {
-          const u64 h = home_of<LAYOUT>(T, key, crc_hi, crc_lo, log2_new);
+          const u64 h = home_of<LAYOUT>(T, key, crc_hi, crc_lo, mul, log2_new);
           if ((h >> 8) != j) {
             spill = true;
           } else {
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock)
 template <int LAYOUT, bool ALL>
 __global__ void __launch_bounds__(256)
     k_shrink_rest(const void *old_cells, uint32_t log2_old, void *new_cells, uint32_t log2_new,
-                  uint32_t crc_hi, uint32_t crc_lo, const uint32_t *counts, DevStatus *st) {
+                  uint32_t crc_hi, uint32_t crc_lo, u64 mul, const uint32_t *counts, DevStatus *st) {
   __shared__ uint32_t T[8][256];
   __shared__ long long s_acc[2];
   __shared__ uint32_t s_err;
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256)
   auto move = [&](u64x2 c) {
     const u64 key = key_word<LAYOUT>(c);
     if (key == kEmpty || key == kTomb) return;
-    const u64 h = home_of<LAYOUT>(T, key, crc_hi, crc_lo, log2_new);
+    const u64 h = home_of<LAYOUT>(T, key, crc_hi, crc_lo, mul, log2_new);
     if (insert_absent<LAYOUT>(new_cells, mask, h, c))
       ++placed;
     else
@@ -239,7 +239,7 @@ size_t shrink_scratch_bytes(uint32_t log2_old, uint32_t log2_new) {
 }
 
 hipError_t launch_shrink(void *old_cells, uint32_t log2_old, void *new_cells, uint32_t log2_new,
-                         uint32_t layout, uint32_t crc_hi, uint32_t crc_lo, uint32_t *scratch,
+                         uint32_t layout, uint32_t crc_hi, uint32_t crc_lo, uint64_t mul, uint32_t *scratch,
                          DevStatus *st, const LaunchCfg &cfg, hipStream_t s) {
   if (log2_new >= log2_old || log2_old > 40 || layout > 1) return hipErrorInvalidValue;
   if (log2_new >= kShrinkLocalLog2) {
@@ -248,19 +248,19 @@ hipError_t launch_shrink(void *old_cells, uint32_t log2_old, void *new_cells, ui
     const uint32_t grid = (uint32_t)((nblocks + kWavesPerBlock - 1) / kWavesPerBlock);
     if (layout == 0)
       hipLaunchKernelGGL(k_shrink_local<0>, dim3(grid), dim3(64 * kWavesPerBlock), 0, s, old_cells, log2_old,
-                         new_cells, log2_new, crc_hi, crc_lo, scratch, st);
+                         new_cells, log2_new, crc_hi, crc_lo, (u64)mul, scratch, st);
     else
       hipLaunchKernelGGL(k_shrink_local<1>, dim3(grid), dim3(64 * kWavesPerBlock), 0, s, old_cells, log2_old,
-                         new_cells, log2_new, crc_hi, crc_lo, scratch, st);
+                         new_cells, log2_new, crc_hi, crc_lo, (u64)mul, scratch, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint32_t g2 = capped_grid(nblocks, 256, cfg);
     if (layout == 0)
       hipLaunchKernelGGL((k_shrink_rest<0, false>), dim3(g2), dim3(256), 0, s, old_cells, log2_old, new_cells,
-                         log2_new, crc_hi, crc_lo, scratch, st);
+                         log2_new, crc_hi, crc_lo, (u64)mul, scratch, st);
     else
       hipLaunchKernelGGL((k_shrink_rest<1, false>), dim3(g2), dim3(256), 0, s, old_cells, log2_old, new_cells,
-                         log2_new, crc_hi, crc_lo, scratch, st);
+                         log2_new, crc_hi, crc_lo, (u64)mul, scratch, st);
     return hipGetLastError();
   }
   hipError_t e = launch_fill_zero(new_cells, (size_t)(layout == 0 ? 8 : 16) << log2_new, cfg, s);
@@ -268,10 +268,10 @@ hipError_t launch_shrink(void *old_cells, uint32_t log2_old, void *new_cells, ui
   const uint32_t g = capped_grid(1ull << log2_old, 256, cfg);
   if (layout == 0)
     hipLaunchKernelGGL((k_shrink_rest<0, true>), dim3(g), dim3(256), 0, s, old_cells, log2_old, new_cells,
-                       log2_new, crc_hi, crc_lo, nullptr, st);
+                       log2_new, crc_hi, crc_lo, (u64)mul, nullptr, st);
   else
     hipLaunchKernelGGL((k_shrink_rest<1, true>), dim3(g), dim3(256), 0, s, old_cells, log2_old, new_cells,
-                       log2_new, crc_hi, crc_lo, nullptr, st);
+                       log2_new, crc_hi, crc_lo, (u64)mul, nullptr, st);
   return hipGetLastError();
 }
 

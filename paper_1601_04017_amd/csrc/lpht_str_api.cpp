@@ -27,9 +27,7 @@ struct lpht_str_table {
 namespace {
 
 void *alloc(lpht_str_table *t, size_t bytes, hipStream_t s) { return pool_alloc(t->device, bytes, s); }
-void release(void *p, hipStream_t s) {
-  if (p) (void)hipFreeAsync(p, s);
-}
+void release(void *p, hipStream_t s) { pool_free(p, s); }
 
 LaunchCfg fill_cfg(const lpht_str_table *t) {
   LaunchCfg c{};

@@ -8,8 +8,11 @@ back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -32,6 +35,9 @@ KV64 = 1
 ASSIGN = 0
 ADD = 1
 
+HASH_CRC32C_PAIR = 0
+HASH_MULSHIFT = 1
+
 SEED_HI = 0x9E3779B9
 SEED_LO = 0xFFFFFFFF
 
@@ -49,6 +55,9 @@ class lpht_config(ctypes.Structure):
         ("max_fill_den", ctypes.c_uint32),
         ("auto_grow", ctypes.c_uint32),
         ("full_keys", ctypes.c_uint32),
+        ("hash", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("mul", ctypes.c_uint64),
         ("alloc", _ALLOC_FN),
         ("free", _FREE_FN),
         ("alloc_ctx", ctypes.c_void_p),
@@ -146,9 +155,46 @@ _SIGS = {
     "lpht_batch_run": (ctypes.c_int, [_VP, ctypes.POINTER(lpht_batch_op), _U32, _VP]),
     "lpht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lpht_version": (ctypes.c_char_p, []),
+    "lpht_release_pools": (ctypes.c_int, []),
 }
 
 _lib = None
+
+
+# Every open library object, so that the exit hook can close them in order
+# (servers, then batches, then tables) while the HIP runtime is still whole.
+_live = weakref.WeakValueDictionary()
+_live_seq = [0]
+
+
+def _track(obj):
+    _live_seq[0] += 1
+    _live[_live_seq[0]] = obj
+
+
+def shutdown():
+    """Closes every open server, batch and table of this process, then
+    returns the library's pool memory (lpht_release_pools).  Registered with
+    atexit when the library is loaded; may also be called directly."""
+    if _lib is None:
+        return
+    objs = [o for _, o in sorted(_live.items())]
+    for kind in (Server, Batch, StrTable, Table):
+        for o in reversed(objs):
+            if isinstance(o, kind):
+                try:
+                    o.close()
+                except Exception:  # noqa: BLE001 - best effort at exit
+                    pass
+    if "torch" in sys.modules:
+        import torch
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    _lib.lpht_release_pools()
+
+
+def _finalizing():
+    return sys.is_finalizing()
 
 
 def load(path: str = LIB_PATH):
@@ -163,6 +209,13 @@ def load(path: str = LIB_PATH):
             f.restype = res
             f.argtypes = args
         _lib = L
+        # atexit runs its hooks last-registered first: importing torch here
+        # first makes this hook run before torch's own exit handlers
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        atexit.register(shutdown)
     return _lib
 
 
@@ -203,7 +256,7 @@ class Table:
 
     def __init__(self, layout: int = KV64, log2_capacity: int = 12, auto_grow: bool = False,
                  seed_hi: int = SEED_HI, seed_lo: int = SEED_LO, alpha=(1, 2), stream=None,
-                 full_keys: bool = False):
+                 full_keys: bool = False, hash: int = HASH_CRC32C_PAIR, mul: int = 0):
         import torch
         L = load()
         self.layout = layout
@@ -218,10 +271,13 @@ class Table:
         cfg.max_fill_num, cfg.max_fill_den = alpha
         cfg.auto_grow = 1 if auto_grow else 0
         cfg.full_keys = 1 if full_keys else 0
+        cfg.hash = hash
+        cfg.mul = mul
         h = ctypes.c_void_p()
         self._stream = stream
         _check(L.lpht_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)), "lpht_create")
         self._h = h
+        _track(self)
 
     def close(self, stream=None):
         if getattr(self, "_h", None):
@@ -229,6 +285,8 @@ class Table:
             self._h = None
 
     def __del__(self):
+        if _finalizing():  # the exit hook closed it already; no HIP calls now
+            return
         try:
             self.close()
         except Exception:
@@ -447,6 +505,7 @@ class Batch:
         h = ctypes.c_void_p()
         _check(load().lpht_batch_create(max_ops, ctypes.byref(h)), "lpht_batch_create")
         self._h = h
+        _track(self)
         self.max_ops = max_ops
 
     def close(self):
@@ -455,6 +514,8 @@ class Batch:
             self._h = None
 
     def __del__(self):
+        if _finalizing():  # the exit hook closed it already; no HIP calls now
+            return
         try:
             self.close()
         except Exception:
@@ -550,6 +611,7 @@ class StrTable:
         self._stream = stream
         _check(L.lpht_str_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)), "lpht_str_create")
         self._h = h
+        _track(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -557,6 +619,8 @@ class StrTable:
             self._h = None
 
     def __del__(self):
+        if _finalizing():  # the exit hook closed it already; no HIP calls now
+            return
         try:
             self.close()
         except Exception:
@@ -742,6 +806,7 @@ class Server:
         h = ctypes.c_void_p()
         _check(L.lpht_server_create(ctypes.byref(cfg), ctypes.byref(h)), "lpht_server_create")
         self._h = h
+        _track(self)
         self.ntables = len(log2_caps)
 
     def close(self):
@@ -750,6 +815,8 @@ class Server:
             self._h = None
 
     def __del__(self):
+        if _finalizing():  # the exit hook closed it already; no HIP calls now
+            return
         try:
             self.close()
         except Exception:

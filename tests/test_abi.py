@@ -99,3 +99,20 @@ def test_autotune_arguments_rejected_on_host(lib):
     assert lib.lpht_autotune(lpht.KV64, 10, 1, None, ctypes.byref(t), None) == lpht.ERR_INVALID
     assert lib.lpht_autotune(lpht.KV64, 20, 0, None, ctypes.byref(t), None) == lpht.ERR_INVALID
     assert lib.lpht_autotune(lpht.KV64, 20, 1, None, None, None) == lpht.ERR_INVALID
+
+
+def test_hash_choice_validated_on_host(lib):
+    out = ctypes.c_void_p()
+    cfg = lpht.lpht_config()
+    lib.lpht_config_default(ctypes.byref(cfg))
+    assert (cfg.hash, cfg.reserved0, cfg.mul) == (lpht.HASH_CRC32C_PAIR, 0, 0)
+    cfg.hash = lpht.HASH_MULSHIFT
+    cfg.mul = 0x9E3779B97F4A7C14  # even
+    assert lib.lpht_create(ctypes.byref(cfg), None, ctypes.byref(out)) == lpht.ERR_INVALID
+    cfg.hash = 7
+    cfg.mul = 3
+    assert lib.lpht_create(ctypes.byref(cfg), None, ctypes.byref(out)) == lpht.ERR_INVALID
+    cfg.hash = lpht.HASH_MULSHIFT
+    cfg.reserved0 = 1
+    assert lib.lpht_create(ctypes.byref(cfg), None, ctypes.byref(out)) == lpht.ERR_INVALID
+    assert not out.value
