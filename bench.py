@@ -53,20 +53,27 @@ def knuth(alpha):
     return ls, lu
 
 
+def lines_per_op(alpha):
+    """Expected 128-byte lines a probe run touches at fill alpha (successful,
+    unsuccessful): a run of L cells starting at a uniformly random cell
+    touches 1 + (L-1)/8 lines."""
+    ls, lu = knuth(alpha)
+    return 1 + (ls - 1) / CELLS_PER_LINE, 1 + (lu - 1) / CELLS_PER_LINE
+
+
 def algorithmic_bytes_per_op(alpha):
     """Bytes the method must move per operation at fill alpha, counting the
-    random table accesses in 128-byte lines: a probe run of L cells starting
-    at a uniformly random cell touches 1 + (L-1)/8 lines on average."""
-    ls, lu = knuth(alpha)
-    lines_s = 1 + (ls - 1) / CELLS_PER_LINE
-    lines_u = 1 + (lu - 1) / CELLS_PER_LINE
+    random table accesses in whole 128-byte lines.  The timed calls write
+    found flags for finds and no flags for inserts."""
+    lines_s, lines_u = lines_per_op(alpha)
     return {
-        # key in + value out + flag out
+        # key in + value out + found flag out
         "find_hit": lines_s * LINE + 17,
         "find_miss": lines_u * LINE + 17,
         # average insertion cost over the fill from 0 to alpha equals the
-        # successful-search cost; the line is read and written back
-        "insert": 2 * lines_s * LINE + 17,
+        # successful-search cost; the line is read and written back; key and
+        # value in
+        "insert": 2 * lines_s * LINE + 16,
     }
 
 
@@ -120,23 +127,51 @@ def measured_traffic(phase, widths):
     return round(total)
 
 
-def cpu_baseline(keys, fkeys_hit, fkeys_miss, zipf, budget_s=25.0):
-    """The oracle, single-threaded, on a bounded sample of the same workload:
-    the first n keys of each stream into a 2^25-cell table (same fill as
-    10^8 in 2^28)."""
+def _host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(keys, miss, zipf):
+    """The oracle (plain sequential C, -O3), one thread pinned to one core, on
+    a bounded sample of the same workload: the first n keys of each stream
+    into 2^25-cell tables (the fill of 10^8 keys in 2^28 cells), each phase
+    timed on its own.  Inputs are prepared before any timing."""
     import oracle
+    from paper_1601_04017_amd import inputs
 
     log2c = 25
     n = int(N_OPS * (1 << log2c) / (1 << LOG2C))
-    t0 = time.perf_counter()
-    o = oracle.OracleTable(oracle.KV64, log2c)
-    o.insert(keys[:n], np.arange(n, dtype=np.uint64))
-    present = keys[:n]
-    o.find(present[np.random.default_rng(0).permutation(n)])
-    o.find(fkeys_miss[:n])
-    o2 = oracle.OracleTable(oracle.KV64, log2c)
-    o2.insert_or_update(zipf[:n], None, oracle.ADD)
-    el = time.perf_counter() - t0
+    ins_k = np.ascontiguousarray(keys[:n])
+    ins_v = np.arange(n, dtype=np.uint64)
+    hit_k = ins_k[inputs.permutation(n, 203)]  # the inserted keys, shuffled
+    miss_k = np.ascontiguousarray(miss[:n])
+    zipf_k = np.ascontiguousarray(zipf[:n])
+    model, ncpu, nallowed = _host_cpu()
+    saved = os.sched_getaffinity(0)
+    core = max(saved)
+    os.sched_setaffinity(0, {core})
+    try:
+        o = oracle.OracleTable(oracle.KV64, log2c)
+        o2 = oracle.OracleTable(oracle.KV64, log2c)
+        ph = {}
+        for name, fn in (("insert", lambda: o.insert(ins_k, ins_v)),
+                         ("find_hit", lambda: o.find(hit_k)),
+                         ("find_miss", lambda: o.find(miss_k)),
+                         ("upsert_zipf", lambda: o2.insert_or_update(zipf_k, None, oracle.ADD))):
+            t0 = time.perf_counter()
+            fn()
+            ph[name] = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, saved)
+    el = sum(ph.values())
     return {
         "value": round(4 * n / el / 1e6, 3),
         "unit": "Mops/s",
@@ -144,6 +179,13 @@ def cpu_baseline(keys, fkeys_hit, fkeys_miss, zipf, budget_s=25.0):
         "kind": "oracle",
         "sample": f"{n} inserts + {n} hit finds + {n} miss finds + {n} Zipf(1.0) increments, "
                   f"2^{log2c}-cell tables (same fill as the 2^{LOG2C} workload), {el:.1f} s",
+        "phase_mops": {k: round(n / v / 1e6, 3) for k, v in ph.items()},
+        "phase_s": {k: round(v, 3) for k, v in ph.items()},
+        "pinned_core": core,
+        "host_cpu": model,
+        "host_nproc": ncpu,
+        "host_cpus_allowed": nallowed,
+        "build": "gcc -O3 -std=c11",
     }
 
 
@@ -212,27 +254,15 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
 
 
 def serving_trace(nreq, seed=500, median=16384, lo=1024, hi=1 << 20):
-    """64 tables with 2^e cells, e uniform in 12..26; requests to uniformly
-    random tables; sizes lognormal (median 16384, sigma 1.35) clipped to
-    [1024, 2^20] (the small-request trace: median 1024 in [64, 16384]); kinds
-    find / insert-or-increment / erase = 60/30/10 %; keys Zipf(1.0) over 10^8
-    (key = rank + 1)."""
+    """64 tables of 2^12..2^26 cells, lognormal requests (median 16384,
+    sigma 1.35, clipped to [1024, 2^20]), find / insert-or-increment / erase
+    = 60/30/10 %, keys Zipf(1.0) over 10^8 (see inputs.serving_trace)."""
     from paper_1601_04017_amd import inputs
 
-    rng_caps = np.random.default_rng(seed + 1)
-    caps = [int(e) for e in rng_caps.integers(12, 27, size=64)]
-    tabs = np.random.default_rng(seed + 2).integers(0, 64, size=nreq)
-    sizes = inputs.lognormal_sizes(nreq, median, 1.35, lo, hi, seed=seed + 3)
-    total = int(sizes.sum())
-    kinds = np.random.default_rng(seed + 4).choice(np.array([0, 1, 2], np.uint8), size=total,
-                                                   p=[0.6, 0.3, 0.1])
-    keys = inputs.zipf_keys_u64(total, ZIPF_N, 1.0, seed=seed + 5)
-    offs = np.concatenate([[0], np.cumsum(sizes)])
-    reqs = [(int(tabs[i]), keys[offs[i]:offs[i + 1]], kinds[offs[i]:offs[i + 1]]) for i in range(nreq)]
-    return caps, reqs, total
+    return inputs.serving_trace(nreq, seed=seed, median=median, lo=lo, hi=hi, universe=ZIPF_N)
 
 
-def _serve(caps, reqs, total, mode, slots, streams, budget, nclients):
+def _serve(caps, reqs, total, mode, slots, streams, budget, nclients, keep_results=False):
     from paper_1601_04017_amd import lpht
 
     srv = lpht.Server(caps, mode=mode, max_inflight=slots, streams=streams, hbm_budget=budget)
@@ -241,14 +271,66 @@ def _serve(caps, reqs, total, mode, slots, streams, budget, nclients):
     lat = np.array([d.done_us - d.submit_us for d in done])
     ok = sum(1 for d in done if d.status == 0)
     st = srv.stats()
+    results = [(o[0].numpy().copy(), o[1].numpy().copy()) for o in outs] if keep_results else None
     srv.close()
     del arr, outs, keep
-    return {"mops": round(total / wall_us, 1), "wall_ms": round(wall_us / 1e3, 2),
-            "p50_ms": round(float(np.percentile(lat, 50)) / 1e3, 3),
-            "p99_ms": round(float(np.percentile(lat, 99)) / 1e3, 3),
-            "completed_ok": ok, "launch_groups": st["waves"],
-            "admission_waits": st["admission_waits"], "hbm_budget": budget,
-            "peak_hbm_bytes": st["peak_hbm_bytes"]}
+    out = {"mops": round(total / wall_us, 1), "wall_ms": round(wall_us / 1e3, 2),
+           "p50_ms": round(float(np.percentile(lat, 50)) / 1e3, 3),
+           "p99_ms": round(float(np.percentile(lat, 99)) / 1e3, 3),
+           "completed_ok": ok, "launch_groups": st["waves"],
+           "admission_waits": st["admission_waits"], "hbm_budget": budget,
+           "peak_hbm_bytes": st["peak_hbm_bytes"]}
+    return (out, results) if keep_results else out
+
+
+def _first_true(keys, flags):
+    """Flags with each key's single true flag moved to its first occurrence
+    (which operation of equal keys wins is unspecified)."""
+    f = flags.copy()
+    t = f == 1
+    if not t.any():
+        return f
+    order = np.argsort(keys, kind="stable")
+    ks, ts = keys[order], t[order]
+    starts = np.flatnonzero(np.r_[True, ks[1:] != ks[:-1]])
+    has = np.add.reduceat(ts.astype(np.int64), starts)
+    f[t] = 0
+    f[order[starts][has > 0]] = 1
+    return f
+
+
+def serving_leg(nreq=300, nclients=256):
+    """Batched serving on the mixed trace, closed loop: the resident kernel and
+    continuous-batching waves against one launch per request, under a budget
+    of twice the initial tables.  p50 / p99 request latency (submit to
+    completion, host clock) and throughput.  The three runs must agree
+    request by request (values, and flags up to which of equal keys won)."""
+    from paper_1601_04017_amd import lpht
+
+    caps, reqs, total = serving_trace(nreq)
+    budget = 2 * sum(16 << c for c in caps)
+    res = {"trace": f"{nreq} requests, {total} ops, 64 tables of 2^12..2^26 cells, {nclients} clients, "
+                    "lognormal sizes median 16384 in [1024, 2^20], find/increment/erase 60/30/10, Zipf(1.0) "
+                    "keys over 1e8",
+           "requests": nreq, "ops": total}
+    outs = {}
+    for name, mode, streams in (("persistent", lpht.SERVE_PERSISTENT, 1), ("waves", lpht.SERVE_WAVES, 4),
+                                ("one_launch_per_request", lpht.SERVE_SINGLE, 4)):
+        log(f"serving leg: {name}")
+        res[name], outs[name] = _serve(caps, reqs, total, mode, 256, streams, budget, nclients,
+                                       keep_results=True)
+    ref = outs["one_launch_per_request"]
+    agree = True
+    for name in ("persistent", "waves"):
+        for (tab, keys, kinds), (va, fa), (vb, fb) in zip(reqs, outs[name], ref):
+            m0 = kinds == 0
+            if not (np.array_equal(va, vb) and np.array_equal(fa[m0], fb[m0])):
+                agree = False
+            for m in (kinds == 1, kinds == 2):
+                if not np.array_equal(_first_true(keys[m], fa[m]), _first_true(keys[m], fb[m])):
+                    agree = False
+    res["modes_agree"] = agree
+    return res
 
 
 def run_serving(nreq=2000, nclients=256):
@@ -611,12 +693,59 @@ def _suite_zipf(up, stream, reps):
     return zres
 
 
+def _stats(xs):
+    xs = [float(x) for x in xs]
+    return {"mean": round(float(np.mean(xs)), 3), "min": round(min(xs), 3), "max": round(max(xs), 3)}
+
+
+def control_zipf_scrambled(t2, d_zscr, reps, stream):
+    """The Zipf insert-or-increment with the keys renamed by a seeded
+    bijection: the same histogram, without the consecutive ranks that the CRC
+    pair spreads over distinct cells (the control for that artefact)."""
+    from paper_1601_04017_amd import lpht
+    ms = []
+    for r in range(reps + 1):
+        t2.clear()
+        x = _timed(lambda: t2.insert_or_update(d_zscr, None, op=lpht.ADD, flags=False), stream)
+        if r:
+            ms.append(x)
+    return ms
+
+
+def control_growing(d_keys, d_vals, reps):
+    """10^8 distinct keys inserted in batches of 2^20 into a table that starts
+    at 4096 cells and doubles by block-parallel migration when the fill would
+    pass 1/2: total and migration time (HIP events around each migration)."""
+    import torch
+    from paper_1601_04017_amd import lpht
+    b = 1 << 20
+    tot, mig = [], []
+    for r in range(reps + 1):
+        g = new_table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+        g.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lo in range(0, N_OPS, b):
+            g.insert(d_keys[lo:lo + b], d_vals[lo:lo + b], flags=False)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) * 1e3
+        st = g.stats()
+        assert g.count() == (N_OPS, N_OPS) and g.log2_capacity == 28
+        g.close()
+        if r:
+            tot.append(el)
+            mig.append(st["migrate_ms"])
+    return tot, mig, st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the controls, ceilings and the serving leg (profiling runs)")
     ap.add_argument("--group-width", type=int, default=None)
     ap.add_argument("--aggregate", type=int, default=None)
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads")
@@ -632,7 +761,7 @@ def main():
 
     import torch
 
-    from paper_1601_04017_amd import inputs, lpht
+    from paper_1601_04017_amd import inputs, lpht, roofline
 
     lpht.load()
     assert torch.cuda.is_available()
@@ -660,6 +789,7 @@ def main():
     perm = inputs.permutation(N_OPS, 203)
     hit = keys[perm]
     zipf = inputs.zipf_keys_u64(N_OPS, ZIPF_N, ZIPF_S, seed=402)
+    zscr = None if args.no_extras else inputs.scramble_keys_u64(zipf, 409)
     log("uploading")
 
     def up(a):
@@ -715,9 +845,9 @@ def main():
     assert bool((hv == torch.from_numpy(perm[:1 << 20].astype(np.int64)).to(dev)).all()), "values"
     mv, mf = t1.find(d_miss[:1 << 20])
     assert not bool(mf.any()), "absent keys found"
-    del perm
     used, live = t1.count()
     assert used == live == N_OPS, (used, live)
+    zipf_distinct = t2.count()[1]
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
     log(f"timed x{args.steps}")
@@ -728,8 +858,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall * 1000 / args.steps
-    ph_ms = {p: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
-             for i, p in enumerate(phases)}
+    ph_all = {p: [evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)] for i, p in enumerate(phases)}
+    ph_ms = {p: float(np.mean(v)) for p, v in ph_all.items()}
     ops_per_step = 4 * N_OPS
     value = ops_per_step / (wall / args.steps) / 1e6
 
@@ -746,7 +876,8 @@ def main():
     width = {"insert": phase_widths(tun, "insert", 0, N_OPS, 1 << LOG2C),
              "find_hit": phase_widths(tun, "find", N_OPS, 0, 1 << LOG2C),
              "find_miss": phase_widths(tun, "find", N_OPS, 0, 1 << LOG2C)}
-    roofline = {
+    traffic = measured_traffic(dominant, width[dominant])
+    roofline_out = {
         "bound": "hbm",
         "kernel": " + ".join(f"k_bulk<KV64,{dominant},G={g}>" for g in width[dominant]),
         "launches": len(width[dominant]),
@@ -754,11 +885,13 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(ach[dominant] / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(dominant, width[dominant]),
+        "traffic": traffic,
         # the phase's launches together (one per group width), timed with
         # HIP events on the stream they run on
         "algorithmic_bytes_per_phase": round(bpo[dominant] * N_OPS),
     }
+    if traffic:
+        roofline_out["traffic_GBs"] = round(traffic / (ph_ms[dominant] / 1e3) / 1e9, 1)
 
     out = {
         "metric": "Mops/s insert/find/Zipf-increment at 1e8 ops; % HBM roofline; batch p99",
@@ -786,19 +919,53 @@ def main():
         },
         "tuning": tune_info,
         "phases_ms": {k: round(v, 3) for k, v in ph_ms.items()},
+        "phases_ms_min_max": {k: [round(min(v), 3), round(max(v), 3)] for k, v in ph_all.items()},
         "phase_mops": {p: round(N_OPS / (ph_ms[p] / 1e3) / 1e6, 1)
                        for p in ("insert", "find_hit", "find_miss", "upsert_zipf")},
         "phase_gbs_algorithmic": {k: round(v, 1) for k, v in ach.items()},
-        "roofline": roofline,
+        "zipf_distinct_keys": int(zipf_distinct),
+        "roofline": roofline_out,
     }
+    if not args.no_extras:
+        # outside the timed steps: controls, measured ceilings, serving
+        log("control: scrambled Zipf keys")
+        d_zscr = up(zscr)
+        zs = control_zipf_scrambled(t2, d_zscr, max(3, min(args.steps, 10)), stream)
+        assert t2.count()[1] == zipf_distinct  # a bijection keeps the distinct count
+        out["control_zipf_scrambled"] = {
+            "ms": _stats(zs), "mops": round(N_OPS / (np.mean(zs) / 1e3) / 1e6, 1),
+            "keys": "the Zipf(1.0) keys mapped through a seeded 64-bit Feistel bijection (seed 409)"}
+        del d_zscr
+        log("control: growing from 4096 cells")
+        t1.close()
+        t2.close()
+        gt, gm, gst = control_growing(d_keys, d_vals, 3)
+        out["growing_from_4096"] = {
+            "total_ms": _stats(gt), "migrate_ms": _stats(gm),
+            "mops": round(N_OPS / (np.mean(gt) / 1e3) / 1e6, 1),
+            "data_migrations": int(gst["migrations"]), "final_log2_capacity": LOG2C,
+            "batches": -(-N_OPS // (1 << 20))}
+        del d_out, d_flags, d_found
+        log("ceilings")
+        ceil = roofline.measure()
+        out["ceilings"] = ceil
+        lines_s, lines_u = lines_per_op(alpha)
+        r_line = ceil["gather16_Gps"]  # every random access fetches one whole line
+        bound_mops = {"insert": min(r_line / (2 * lines_s), ceil["cas_Gps"]) * 1e3,
+                      "find_hit": r_line / lines_s * 1e3, "find_miss": r_line / lines_u * 1e3}
+        roofline_out["measured_random_access"] = {
+            "R_line_G_per_s": r_line, "R_cas_G_per_s": ceil["cas_Gps"],
+            "bound_mops": {k: round(v, 1) for k, v in bound_mops.items()},
+            "frac": {k: round(out["phase_mops"][k] / v, 4) for k, v in bound_mops.items()}}
+        out["serving"] = serving_leg()
     if args.suite:
-        del d_keys, d_vals, d_hit, d_miss, d_zipf, d_out, d_flags, d_found
+        del d_keys, d_vals, d_hit, d_miss, d_zipf
         t1.close()
         t2.close()
         out["suite"] = run_suite(dev, parts=tuple(args.parts.split(",")))
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, 1 thread)")
-        out["cpu_baseline"] = cpu_baseline(keys, hit, miss, zipf)
+        log("cpu baseline (oracle, 1 thread pinned)")
+        out["cpu_baseline"] = cpu_baseline(keys, miss, zipf)
     print(json.dumps(out), flush=True)
 
 

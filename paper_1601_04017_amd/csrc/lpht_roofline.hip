@@ -92,9 +92,26 @@ __global__ void __launch_bounds__(256) k_hot_add(u64 *word, int per) {
   for (int j = 0; j < per; ++j) __hip_atomic_fetch_add(word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Streaming copy: a workgroup copies tiles of 256 x COPY_PER 16-byte units;
+// each lane issues its COPY_PER loads (coalesced across the workgroup) before
+// any store, so many loads are in flight, and stores bypass the caches
+// (non-temporal), since nothing reads the destination again.
+constexpr int COPY_PER = 8;
 __global__ void __launch_bounds__(256) k_copy(const u64x2 *src, u64x2 *dst, u64 n16) {
-  const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+  const u64 tile = 256ull * COPY_PER;
+  const u64 ntiles = n16 / tile;
+  for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u64 b = t * tile + threadIdx.x;
+    u64x2 v[COPY_PER];
+#pragma unroll
+    for (int j = 0; j < COPY_PER; ++j) v[j] = __builtin_nontemporal_load(src + b + 256ull * j);
+#pragma unroll
+    for (int j = 0; j < COPY_PER; ++j) __builtin_nontemporal_store(v[j], dst + b + 256ull * j);
+  }
+  // the ragged end (fewer than one tile)
+  for (u64 i = ntiles * tile + (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (u64)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 }  // namespace

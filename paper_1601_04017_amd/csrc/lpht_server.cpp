@@ -467,9 +467,13 @@ bool persist_retire(lpht_server *S) {
   return any;
 }
 
+// Whether the growth rule may fire before the request's increments: an upper
+// bound of `used` (the exact count after the last completion plus insertions
+// made on the table outside the server since, `pending`); grow_before_batch
+// then decides exactly.
 bool needs_growth(const lpht_server *S, const Req *q) {
   const lpht_table *t = S->tables[q->r.table];
-  return q->count[1] && !within_fill(t, t->known_used + q->count[1], 1ull << t->log2c);
+  return q->count[1] && !within_fill(t, t->known_used + t->pending + q->count[1], 1ull << t->log2c);
 }
 
 // One pass of the worker in persistent mode.

@@ -15,7 +15,8 @@ over the universe 1..N.
   32-bit finaliser, also a bijection.  Reserved keys 0 and 1 are removed.
 * Zipf ranks use the rejection-inversion sampler of Hoermann and Derflinger
   (ACM TOMACS 6(3), 1996), vectorised with numpy; keys are rank + 1 so that
-  the most frequent key is not the tombstone key 1.
+  the most frequent key is not the tombstone key 1.  The control stream maps
+  those keys through a seeded Feistel bijection (scramble_keys_u64).
 """
 from __future__ import annotations
 
@@ -177,6 +178,46 @@ def zipf_keys_u64(m: int, n_universe: int, s: float, seed: int) -> np.ndarray:
     return (ZipfSampler(n_universe, s).sample(m, seed) + 1).astype(np.uint64)
 
 
+def _feistel_round_keys(seed: int, rounds: int) -> np.ndarray:
+    return _splitmix64_out(np.arange(rounds, dtype=np.uint64) ^ _seed64(seed))
+
+
+def _feistel64(x: np.ndarray, rk: np.ndarray) -> np.ndarray:
+    """A balanced Feistel network on the two 32-bit halves of x: each round
+    (L, R) -> (R, L ^ F(R)), F = the low 32 bits of SplitMix64's output
+    function of R ^ round key.  A bijection of the 64-bit integers for any
+    round function."""
+    lo = (x & np.uint64(0xFFFFFFFF)).astype(np.uint64)
+    hi = (x >> np.uint64(32)).astype(np.uint64)
+    for k in rk:
+        f = _splitmix64_out(lo ^ k) & np.uint64(0xFFFFFFFF)
+        lo, hi = hi ^ f, lo
+    return (hi << np.uint64(32)) | lo
+
+
+def scramble_keys_u64(keys: np.ndarray, seed: int, rounds: int = 4, chunk: int = 1 << 23) -> np.ndarray:
+    """Maps keys through a seeded bijection g of [2, 2^64): a 4-round Feistel
+    network, cycle-walked (applied again while the result is 0 or 1) so that
+    reserved keys are neither produced nor needed.  Equal keys stay equal and
+    distinct keys stay distinct, so a Zipf stream keeps its histogram (up to
+    the renaming) while consecutive ranks lose their consecutive values: the
+    control for hashes that spread consecutive keys without collisions."""
+    keys = np.asarray(keys, dtype=np.uint64)
+    if np.any(keys < 2):
+        raise ValueError("keys must lie in [2, 2^64)")
+    rk = _feistel_round_keys(seed, rounds)
+    out = np.empty_like(keys)
+    with np.errstate(over="ignore"):
+        for lo in range(0, keys.size, chunk):
+            y = _feistel64(keys[lo:lo + chunk], rk)
+            bad = y < 2
+            while np.any(bad):
+                y[bad] = _feistel64(y[bad], rk)
+                bad = y < 2
+            out[lo:lo + chunk] = y
+    return out
+
+
 def zipf_pmf(n_universe: int, s: float, ranks) -> np.ndarray:
     """P(rank) = rank^-s / H_{N,s}; H summed in float64 in chunks."""
     H = 0.0
@@ -207,3 +248,25 @@ def lognormal_sizes(count: int, median: float, sigma: float, lo: int, hi: int, s
     rng = np.random.default_rng(seed)
     x = np.exp(rng.normal(math.log(median), sigma, size=count))
     return np.clip(np.rint(x), lo, hi).astype(np.int64)
+
+
+def serving_trace(nreq: int, seed: int = 500, median: int = 16384, lo: int = 1024, hi: int = 1 << 20,
+                  ntables: int = 64, e_lo: int = 12, e_hi: int = 26, universe: int = 10 ** 8,
+                  zipf_s: float = 1.0):
+    """The mixed serving workload: `ntables` tables of 2^e cells, e uniform in
+    e_lo..e_hi (seed + 1); each request goes to a uniformly random table
+    (seed + 2); request sizes lognormal with the given median and sigma 1.35,
+    rounded and clipped to [lo, hi] (seed + 3); operation kinds find /
+    insert-or-increment / erase with probabilities 0.6 / 0.3 / 0.1 (seed + 4);
+    keys Zipf(zipf_s) ranks over 1..universe, plus one (seed + 5).
+    Returns (log2 capacities, [(table, keys u64, kinds u8)], total ops)."""
+    caps = [int(e) for e in np.random.default_rng(seed + 1).integers(e_lo, e_hi + 1, size=ntables)]
+    tabs = np.random.default_rng(seed + 2).integers(0, ntables, size=nreq)
+    sizes = lognormal_sizes(nreq, median, 1.35, lo, hi, seed=seed + 3)
+    total = int(sizes.sum())
+    kinds = np.random.default_rng(seed + 4).choice(np.array([0, 1, 2], np.uint8), size=total,
+                                                   p=[0.6, 0.3, 0.1])
+    keys = zipf_keys_u64(total, universe, zipf_s, seed=seed + 5)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    reqs = [(int(tabs[i]), keys[offs[i]:offs[i + 1]], kinds[offs[i]:offs[i + 1]]) for i in range(nreq)]
+    return caps, reqs, total

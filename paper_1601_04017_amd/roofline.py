@@ -75,7 +75,10 @@ def measure(buf_bytes: int = 1 << 32, lanes: int = 1 << 24, reps: int = 3) -> di
     out["hot_add_Mps"] = round(hot_lanes * hot_per / t / 1e6, 2)
     half = buf_bytes // 2
     base = buf.data_ptr()
-    t = timed(lambda: L.rl_copy(ctypes.c_void_p(base), ctypes.c_void_p(base + half), half, 256 * 1024 * 4, sh))
+    # as many workgroups as there are tiles of 32 KiB, at most 65536 (the
+    # table's zero-fill uses the same shape)
+    tiles = min(65536, half // (16 * 256 * 8))
+    t = timed(lambda: L.rl_copy(ctypes.c_void_p(base), ctypes.c_void_p(base + half), half, 256 * tiles, sh))
     out["copy_GBs"] = round(2 * half / t / 1e9, 1)
     del buf
     return out

@@ -156,3 +156,40 @@ def test_zipf_presized_and_growing_full_size(tuned, s):
         assert bool((found == 1).all()), grow
         assert np.array_equal(to_host(v, np.uint64), cnt.astype(np.uint64)), grow
         t.close()
+
+
+def test_zipf_scrambled_keys_full_size(tuned):
+    # the control stream of the benchmark: the Zipf(1.0) keys renamed by the
+    # seeded Feistel bijection, so the CRC pair no longer spreads consecutive
+    # ranks over distinct cells; the presized table (and one growing from
+    # 4096 cells in batches of 2^20) must hold the exact histogram, and every
+    # stored key must be reachable from its home along non-empty cells
+    from paper_1601_04017_amd import lpht
+    z = inputs.scramble_keys_u64(inputs.zipf_keys_u64(N, N, 1.0, seed=402), 409)
+    uk, cnt = np.unique(z, return_counts=True)
+    print(f"full size: scrambled Zipf(1.0) increments, {uk.size} distinct keys", flush=True)
+    dz, du = to_dev(z), to_dev(uk)
+    del z
+    for grow in (False, True):
+        if grow:
+            t = lpht.Table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+            t.apply_tuning(tuned)
+            for lo in range(0, N, 1 << 20):
+                t.insert_or_update(dz[lo:lo + (1 << 20)], None, op=lpht.ADD, flags=False)
+        else:
+            t = _table(tuned)
+            t.insert_or_update(dz, None, op=lpht.ADD, flags=False)
+        assert t.count() == (uk.size, uk.size) and t.status() == 0, grow
+        v, found = t.find(du)
+        assert bool((found == 1).all()), grow
+        assert np.array_equal(to_host(v, np.uint64), cnt.astype(np.uint64)), grow
+        if not grow:
+            # reachability of every tenth stored key from its home
+            ks, _ = H.split_cells(cells_host(t), oracle.KV64)
+            occ = ks != H.EMPTY
+            q = np.flatnonzero(occ)[::10]
+            p = H.homes(ks[q], oracle.KV64, LOG2C)
+            rs = H.run_start(occ)[q]
+            assert np.all((q - p) % (1 << LOG2C) <= q - rs), "stored key not reachable from its home"
+            del ks, occ
+        t.close()

@@ -64,3 +64,53 @@ def test_lognormal_sizes_clip():
     x = inputs.lognormal_sizes(10000, 16384, 1.35, 1024, 1 << 20, seed=503)
     assert x.min() >= 1024 and x.max() <= 1 << 20
     assert 12000 < np.median(x) < 21000
+
+
+def test_scrambled_zipf_keeps_histogram_and_breaks_consecutive_spread():
+    z = inputs.zipf_keys_u64(500_000, 10 ** 6, 1.0, seed=402)
+    s1 = inputs.scramble_keys_u64(z, 7)
+    s2 = inputs.scramble_keys_u64(z, 7)
+    assert np.array_equal(s1, s2)
+    assert s1.min() >= 2
+    # a bijection: equal keys stay equal, distinct stay distinct, so the
+    # multiset of counts is unchanged and first occurrences stay in place
+    uz, iz, cz = np.unique(z, return_index=True, return_counts=True)
+    us, is_, cs = np.unique(s1, return_index=True, return_counts=True)
+    assert uz.size == us.size
+    assert np.array_equal(np.sort(iz), np.sort(is_))
+    assert np.array_equal(np.sort(cz), np.sort(cs))
+    # another seed gives another bijection
+    assert not np.array_equal(inputs.scramble_keys_u64(z[:1000], 8), s1[:1000])
+
+
+def test_scramble_is_injective_and_avoids_reserved_keys():
+    x = np.arange(2, 2 + (1 << 20), dtype=np.uint64)
+    y = inputs.scramble_keys_u64(x, 11)
+    assert np.unique(y).size == x.size and y.min() >= 2
+    # cycle walking: inputs the network maps to 0 or 1 still land in [2, 2^64)
+    rk = inputs._feistel_round_keys(11, 4)
+    pre = []
+    for target in (0, 1):
+        # the inverse network gives the preimage of a reserved value
+        lo, hi = np.uint64(target & 0xFFFFFFFF), np.uint64(target >> 32)
+        for k in rk[::-1]:
+            with np.errstate(over="ignore"):
+                f = inputs._splitmix64_out(np.array([hi ^ k], np.uint64))[0] & np.uint64(0xFFFFFFFF)
+            lo, hi = hi, lo ^ f
+        pre.append((int(hi) << 32) | int(lo))
+    p = np.array([v for v in pre if v >= 2], dtype=np.uint64)
+    if p.size:
+        q = inputs.scramble_keys_u64(p, 11)
+        assert q.min() >= 2
+
+
+def test_scrambled_consecutive_keys_collide_like_random_keys():
+    import oracle
+    from tests import helpers as H
+    keys = np.arange(2, 2 + (1 << 16), dtype=np.uint64)
+    c = 1 << 18
+    plain = np.unique(H.homes(keys, oracle.KV64, 18)).size
+    scr = np.unique(H.homes(inputs.scramble_keys_u64(keys, 3), oracle.KV64, 18)).size
+    assert plain == keys.size  # the CRC pair spreads consecutive keys without collision
+    expect = c * (1 - np.exp(-keys.size / c))  # distinct homes of random keys
+    assert abs(scr - expect) < 0.01 * expect
