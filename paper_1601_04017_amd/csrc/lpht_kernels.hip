@@ -1150,7 +1150,10 @@ __global__ void k_persist_init(PersistDev *dev, PersistState *st, u64 first_q) {
   if (e < kPersistRing) {
     // the entry serves the first request q >= first_q with q % ring == e
     u64 q = first_q + ((e + kPersistRing - (uint32_t)(first_q % kPersistRing)) % kPersistRing);
-    dev[e].done[0] = dev[e].done[1] = dev[e].done[2] = 0;  // generation 0: no request
+    // generation 0 (no request) in every phase counter: the array may hold a
+    // previous server's counters, whose tags would match the same request
+    // numbers here and make a phase look finished before it starts
+    for (uint32_t p = 0; p < kPersistPhases; ++p) dev[e].done[p] = 0;
     dev[e].claim = (q + 1) << 32;
   }
   if (e < kPersistGroups) {
