@@ -265,6 +265,25 @@ int lpht_insert_async(lpht_table *t, const void *keys, const void *vals, uint64_
  * about 2 x (live + n) x (2 x key width + 4) bytes for the call. */
 int lpht_build(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, void *stream);
 
+/* lpht_build for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same result, flags and errors as lpht_build, but no hipMalloc, hipFree or
+ * pool allocation.  The build's scratch is a fixed 64 MiB device array of
+ * the library (one per GPU, held until the process ends), and the result is
+ * written into the table's current cell array, so the capacity never
+ * changes: an auto-growing table that would have to grow (n > alpha *
+ * capacity) gets UNSUPPORTED.  Limits: the scratch the build needs for n
+ * keys at the table's capacity must fit 64 MiB (about (2 x key width + 4) x
+ * 2n bytes plus per-block counters: 2^20 keys into up to 2^26 cells, either
+ * layout); larger calls get LPHT_ERR_INVALID and change nothing.  All calls
+ * on one GPU share the array, which keeps the last call's contents (each
+ * call clears what it counts with): calls that overlap on one GPU race and
+ * must be ordered by the caller (one stream, or events).  On FULL the table
+ * is unchanged; after a device error its contents are undefined.
+ * Synchronises the stream (the distinct count is read back). */
+int lpht_build_noalloc(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op,
+                       void *stream);
+
 /* Sort-based batched merge (Sec. 5.5): as lpht_build over the table's live
  * elements followed by the batch, i.e. the batch applied to the table with
  * insertOrUpdate semantics in index order (LPHT_ASSIGN: the last occurrence

@@ -819,6 +819,61 @@ int lpht_build(lpht_table *t, const void *keys, const void *vals, uint64_t n, ui
   return bulk_merge(t, keys, vals, n, op, false, stream);
 }
 
+int lpht_build_noalloc(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op,
+                       void *stream) {
+  int rc = check_arrays(t, keys, vals, n);
+  if (rc) return rc;
+  if (op > LPHT_ADD) return LPHT_ERR_INVALID;
+  if (n >= (1ull << 32) - 1) return LPHT_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(t->device) != hipSuccess) return LPHT_ERR_DEVICE;
+  void *scratch = nullptr;
+  hipError_t e = noalloc_scratch(t->device, &scratch);
+  if (e != hipSuccess) return from_hip(e);
+  // the capacity cannot change (a new cell array would be an allocation)
+  if (t->log2c > kBulkMaxLog2) return LPHT_ERR_UNSUPPORTED;
+  if (t->cfg.auto_grow && !within_fill(t, n, 1ull << t->log2c)) return LPHT_ERR_UNSUPPORTED;
+  if (bulk_merge_scratch_bytes(n, n, t->log2c, t->cfg.layout) > kNoAllocScratchBytes) return LPHT_ERR_INVALID;
+  rc = sync_counts(t, s);
+  if (rc) return rc;
+  BulkMergeArgs a{};
+  a.layout = t->cfg.layout;
+  a.op = op;
+  a.keys = keys;
+  a.vals = vals;
+  a.n = n;
+  a.max_items = n;
+  // a build never reads the old cells, and when it does not fail for lack
+  // of room it writes every cell, so the result goes to the table's own array
+  a.new_cells = t->cells;
+  a.log2_new = t->log2c;
+  a.crc_hi = t->crc_hi;
+  a.crc_lo = t->crc_lo;
+  a.mul = t->mul;
+  a.status = t->status;
+  a.scratch = scratch;
+  a.num_cus = t->launch.num_cus;
+  BulkMergeCtl ctl{};
+  e = launch_set_status(t->status, 0, 0, 0, s);
+  if (e == hipSuccess) e = launch_bulk_merge(a, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&ctl, scratch, sizeof(ctl), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess || ctl.full) {
+    (void)launch_set_status(t->status, t->known_used, t->known_live, 0, s);
+    return e != hipSuccess ? from_hip(e) : ctl.full == 1 ? LPHT_ERR_FULL : LPHT_ERR_DEVICE;
+  }
+  t->known_used = t->known_live = ctl.distinct;
+  t->pending = 0;
+  t->mods_since_exact = 0;
+  t->stats.bulk_merges++;
+  if (t->special) {
+    e = launch_special(t->cfg.layout, OP_UPSERT, op, keys, vals, n, nullptr, nullptr, t->special,
+                       t->special_scratch, 1, s);
+    if (e != hipSuccess) return from_hip(e);
+  }
+  return LPHT_OK;
+}
+
 int lpht_merge(lpht_table *t, const void *keys, const void *vals, uint64_t n, uint32_t op, void *stream) {
   return bulk_merge(t, keys, vals, n, op, true, stream);
 }

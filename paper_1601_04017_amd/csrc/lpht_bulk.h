@@ -49,6 +49,13 @@ struct BulkMergeCtl {
 // `max_items` are elements.
 size_t bulk_merge_scratch_bytes(uint64_t inputs, uint64_t max_items, uint32_t log2_new, uint32_t layout);
 
+// Size of the fixed device scratch used by lpht_build_noalloc.
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+
+// The device address of that scratch on `device` (looked up once per device
+// with the device current, then cached).
+hipError_t noalloc_scratch(int device, void **out);
+
 // Enqueues the whole operation on `s`.  The result (when ctl->full == 0) is
 // the table obtained by inserting the distinct keys one by one in increasing
 // order of (hash, key) into an empty table of 2^log2_new cells.

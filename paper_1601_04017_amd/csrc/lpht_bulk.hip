@@ -48,6 +48,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <climits>
 #include <type_traits>
@@ -1130,6 +1132,39 @@ void carve_all(Carve &cv, uint64_t N, const Geometry &g, uint32_t layout, BmK &k
 }
 
 }  // namespace
+
+// The fixed scratch of the entry point that allocates nothing
+// (lpht_build_noalloc): one array per device, held until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device array:
+// its device address comes from hipGetSymbolAddress, once per device, with
+// that device current, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocDevices];
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void **out) {
+  *out = nullptr;
+  if (device < 0 || device >= kNoAllocDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = p;
+  }
+  *out = g_noalloc_ptr[device];
+  return hipSuccess;
+}
 
 size_t bulk_merge_scratch_bytes(uint64_t inputs, uint64_t max_items, uint32_t log2_new, uint32_t layout) {
   const Geometry g = geometry(inputs, log2_new);

@@ -136,6 +136,7 @@ _SIGS = {
     "lpht_erase": (ctypes.c_int, [_VP, _VP, _U64, _VP, _VP]),
     "lpht_grow": (ctypes.c_int, [_VP, _U32, _VP]),
     "lpht_build": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP]),
+    "lpht_build_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP]),
     "lpht_insert_async": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP, _VP]),
     "lpht_merge": (ctypes.c_int, [_VP, _VP, _VP, _U64, _U32, _VP]),
     "lpht_count": (ctypes.c_int, [_VP, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP]),
@@ -359,6 +360,12 @@ class Table:
         """Sort-based bulk build: the table's contents become the batch."""
         n = self._n(keys)
         _check(load().lpht_build(self._h, _ptr(keys), _ptr(vals), n, op, _stream_handle(stream)), "lpht_build")
+
+    def build_noalloc(self, keys, vals=None, op=ASSIGN, stream=None):
+        """lpht_build with the library's fixed scratch, in place: no device
+        allocation; returns the status code (no exception)."""
+        n = self._n(keys)
+        return load().lpht_build_noalloc(self._h, _ptr(keys), _ptr(vals), n, op, _stream_handle(stream))
 
     def merge(self, keys, vals=None, op=ASSIGN, stream=None):
         """Sort-based batched merge of the batch into the table."""
