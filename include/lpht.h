@@ -136,7 +136,13 @@ typedef struct lpht_tuning {
   uint32_t group_width;   /* lanes that probe one operation together: 1, 2, 4, 8 or 16 */
   uint32_t blocks_per_cu; /* resident workgroups per compute unit the grid is sized for, 1..32 */
   uint32_t migrate_block; /* old cells per migration workgroup, power of two 256..8192 */
-  uint32_t aggregate;     /* 1 (default): combine equal keys in LDS before LPHT_ADD upserts */
+  uint32_t aggregate;     /* LPHT_ADD upserts: 1 (default): combine equal keys in LDS; calls of
+                           * at least 2^22 operations on tables of at least 2^20 cells are first
+                           * partitioned by table region (top 12 hash bits), so that every
+                           * occurrence of a key is combined and each distinct key costs one
+                           * upsert (scratch: about (key width [+ value width] [+ 4 with flags])
+                           * bytes per operation, from the table's allocator); 2: LDS combining
+                           * of 2048-operation chunks only; 0: no combining */
   /* Group width by fill quarter, used / capacity in [0, 1/4], (1/4, 1/2],
    * (1/2, 3/4], (3/4, 1] (the host's bound on `used` after the operations):
    * for finds, and for the operations that modify the table.  0 =

@@ -15,6 +15,7 @@
 #include "lpht_host.h"
 #include "lpht_async.h"
 #include "lpht_bulk.h"
+#include "lpht_part.h"
 #include "lpht_shrink.h"
 #include "lpht_special.h"
 
@@ -149,7 +150,7 @@ bool tuning_ok(const lpht_tuning *u) {
   if (u->migrate_block < 256 || u->migrate_block > 8192 ||
       (u->migrate_block & (u->migrate_block - 1)))
     return false;
-  if (u->aggregate > 1) return false;
+  if (u->aggregate > 2) return false;
   for (int i = 0; i < 4; ++i)
     for (uint8_t g : {u->g_find[i], u->g_modify[i]})
       if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16) return false;
@@ -392,6 +393,22 @@ int run_bulk(lpht_table *t, OpKind op, const void *keys, const void *vals, uint6
                  t->known_used + t->pending <= (1ull << t->log2c))
                     ? 1u
                     : 0u;
+  if (a.aggregate && t->tuning.aggregate == 1 && part_applies(n, t->log2c)) {
+    // large insert-or-add on a large table: partition by table region first
+    const size_t sb = part_scratch_bytes(n, t->log2c, t->cfg.layout, vals != nullptr, flags != nullptr,
+                                         t->launch.num_cus);
+    void *scratch = dev_alloc(t, sb, s);
+    if (scratch) {
+      const hipError_t e = launch_upsert_add_part(a, scratch, t->launch.num_cus, s);
+      dev_free(t, scratch, sb, s);
+      if (e != hipSuccess) return from_hip(e);
+      if (t->special)
+        return from_hip(launch_special(t->cfg.layout, op, up, keys, vals, n, vals_out, flags, t->special,
+                                       t->special_scratch, false, s));
+      return LPHT_OK;
+    }
+    // no memory for the partition: combine chunk by chunk instead
+  }
   const bool inserting = op == OP_INSERT || op == OP_UPSERT;
   const uint64_t c = 1ull << t->log2c;
   // bound on used before this call (the growth rule already counted it)

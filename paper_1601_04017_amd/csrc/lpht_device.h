@@ -166,6 +166,54 @@ struct Cells<1> {
   }
 };
 
+// One insertOrUpdate(k, d, add) on the table by a single lane (Algorithm 1
+// with fetch-and-add as atomicUpdate).  Returns the flag.
+template <int LAYOUT>
+__device__ __forceinline__ uint8_t upsert_add_one(const BulkArgs &A, const uint32_t (*T)[256], u64 k,
+                                                  u64 d, long long &d_used, long long &d_live,
+                                                  uint32_t &err) {
+  const u64 cap = 1ull << A.log2c, mask = cap - 1;
+  u64 p = home_of<LAYOUT>(T, k, A.crc_hi, A.crc_lo, A.mul, A.log2c);
+  for (u64 probes = 0; probes < cap; ++probes, p = (p + 1) & mask) {
+    if (LAYOUT == 0) {
+      u64 *w = (u64 *)A.cells + p;
+      u64 ck = *w & 0xFFFFFFFFull;
+      if (ck == kEmpty) {
+        const u64 old = cas64(w, 0ull, (d << 32) | k);
+        if (old == 0) {
+          d_used += 1;
+          d_live += 1;
+          return 1;
+        }
+        ck = old & 0xFFFFFFFFull;
+      }
+      if (ck == k) {
+        add64(w, d << 32);
+        return 0;
+      }
+    } else {
+      u64 *kp = (u64 *)A.cells + 2 * p;
+      u64 ck = *kp;
+      if (ck == kEmpty) {
+        const u64 old = cas64(kp, kEmpty, k);
+        if (old == kEmpty) {
+          add64(kp + 1, d);
+          d_used += 1;
+          d_live += 1;
+          return 1;
+        }
+        ck = old;
+      }
+      if (ck == k) {
+        add64(kp + 1, d);
+        return 0;
+      }
+    }
+  }
+  err |= kErrFull;
+  return 0xFF;
+}
+
 // Orders LDS accesses of the lanes of one wavefront.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -194,10 +194,6 @@ def shutdown():
     _lib.lpht_release_pools()
 
 
-def _finalizing():
-    return sys.is_finalizing()
-
-
 def load(path: str = LIB_PATH):
     """Loads liblpht.so and declares its signatures.  Raises if it is absent."""
     global _lib
@@ -285,8 +281,10 @@ class Table:
             load().lpht_destroy(self._h, _stream_handle(stream if stream is not None else self._stream))
             self._h = None
 
-    def __del__(self):
-        if _finalizing():  # the exit hook closed it already; no HIP calls now
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: module globals may be gone during teardown,
+        # when the exit hook has closed everything and no HIP call may follow
+        if _finalizing():
             return
         try:
             self.close()
@@ -520,8 +518,10 @@ class Batch:
             load().lpht_batch_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        if _finalizing():  # the exit hook closed it already; no HIP calls now
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: module globals may be gone during teardown,
+        # when the exit hook has closed everything and no HIP call may follow
+        if _finalizing():
             return
         try:
             self.close()
@@ -625,8 +625,10 @@ class StrTable:
             _str_lib().lpht_str_destroy(self._h, _stream_handle(self._stream))
             self._h = None
 
-    def __del__(self):
-        if _finalizing():  # the exit hook closed it already; no HIP calls now
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: module globals may be gone during teardown,
+        # when the exit hook has closed everything and no HIP call may follow
+        if _finalizing():
             return
         try:
             self.close()
@@ -821,8 +823,10 @@ class Server:
             load().lpht_server_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        if _finalizing():  # the exit hook closed it already; no HIP calls now
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: module globals may be gone during teardown,
+        # when the exit hook has closed everything and no HIP call may follow
+        if _finalizing():
             return
         try:
             self.close()
