@@ -579,14 +579,15 @@ def _suite_async(up, reps, dkeys, dvals):
     out = {}
     for name, keys, vals, add in (("distinct", dkeys[:N_OPS], dvals[:N_OPS], False), ("zipf1_add", z, None, True)):
         row = {}
-        for mode in ("async", "host"):
+        for mode in ("async", "async_presized", "host"):
             res = []
             for r in range(reps + 1):
-                t = new_table(layout=lpht.KV64, log2_capacity=12, auto_grow=True)
+                t = new_table(layout=lpht.KV64, log2_capacity=28 if mode == "async_presized" else 12,
+                              auto_grow=True)
                 t.set_timing(True)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                if mode == "async":
+                if mode.startswith("async"):
                     t.insert_async(keys, vals, add=add, flags=False)
                 elif add:
                     t.insert_or_update(keys, None, op=lpht.ADD, flags=False)
@@ -594,11 +595,15 @@ def _suite_async(up, reps, dkeys, dvals):
                     t.insert(keys, vals, flags=False)
                 torch.cuda.synchronize()
                 el = (time.perf_counter() - t0) * 1e3
+                st = t.stats()
+                if not add:
+                    assert t.count() == (N_OPS, N_OPS), t.count()
                 if r:
-                    res.append((el, t.log2_capacity, t.stats()["async_growths"]))
+                    res.append((el, t.log2_capacity, st["async_growths"], st["async_fallbacks"]))
                 t.close()
-            el, lg, ng = np.mean(res, axis=0)
-            row[mode] = {"ms": round(el, 3), "final_log2_capacity": int(lg), "in_kernel_growths": int(ng)}
+            el, lg, ng, nf = np.mean(res, axis=0)
+            row[mode] = {"ms": round(el, 3), "final_log2_capacity": int(lg), "in_kernel_growths": int(ng),
+                         "fallback_growths": round(float(nf), 2)}
         out[name] = row
     del z
     return out

@@ -164,6 +164,8 @@ typedef struct lpht_stats {
   uint64_t shrinks;        /* data migrations to a smaller capacity */
   uint64_t bulk_merges;    /* completed lpht_build / lpht_merge calls */
   uint64_t async_growths;  /* migrations made inside lpht_insert_async kernels */
+  uint64_t async_fallbacks; /* of those, migrations that met a cluster longer than the block
+                             * migration's halo and re-inserted by compare-and-swap instead */
 } lpht_stats;
 
 typedef struct lpht_table lpht_table; /* opaque; owned by the library */

@@ -13,7 +13,7 @@ OUT = os.path.join(PKG, "liblpht.so")
 SOURCES = ["lpht_kernels.hip", "lpht_part.hip", "lpht_shrink.hip", "lpht_bulk.hip", "lpht_async.hip", "lpht_special.hip", "lpht_str.hip", "lpht_str_api.cpp", "lpht_api.cpp", "lpht_server.cpp", "lpht_tune.cpp"]
 ROOFLINE_OUT = os.path.join(PKG, "libroofline.so")
 ROOFLINE_SOURCES = ["lpht_roofline.hip"]
-HEADERS = ["lpht_internal.h", "lpht_host.h", "lpht_device.h", "lpht_part.h", "lpht_shrink.h", "lpht_bulk.h", "lpht_async.h", "lpht_special.h", "lpht_str.h", os.path.join("..", "..", "include", "lpht.h")]
+HEADERS = ["lpht_internal.h", "lpht_host.h", "lpht_device.h", "lpht_migrate.h", "lpht_part.h", "lpht_shrink.h", "lpht_bulk.h", "lpht_async.h", "lpht_special.h", "lpht_str.h", os.path.join("..", "..", "include", "lpht.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

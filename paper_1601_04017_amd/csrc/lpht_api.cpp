@@ -948,13 +948,8 @@ int lpht_insert_async(lpht_table *t, const void *keys, const void *vals, uint64_
       release(0);
       return LPHT_ERR_OOM;
     }
-    // the kernel migrates into zeroed tables: clearing them here, at the
-    // zero-fill kernel's rate, spares every growth a phase and a barrier
-    const hipError_t ze = launch_fill_zero(a.ladder[i], cb << (t->log2c + i), t->launch, s);
-    if (ze != hipSuccess) {
-      release(0);
-      return from_hip(ze);
-    }
+    // no clearing: the kernel's block migration writes every cell of the
+    // target (its rare fallback clears the target itself)
   }
   AsyncCtl *ctl = (AsyncCtl *)dev_alloc(t, sizeof(AsyncCtl), s);
   if (!ctl) {
@@ -986,6 +981,7 @@ int lpht_insert_async(lpht_table *t, const void *keys, const void *vals, uint64_
     t->log2c += fin;
   }
   t->stats.async_growths += fin;
+  t->stats.async_fallbacks += h.fallbacks;
   if (t->special) {
     e = launch_special(t->cfg.layout, add ? OP_UPSERT : OP_INSERT, add ? LPHT_ADD : LPHT_ASSIGN, keys, vals, n,
                        nullptr, flags, t->special, t->special_scratch, false, s);

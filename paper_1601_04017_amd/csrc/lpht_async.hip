@@ -3,34 +3,36 @@
 // protocol and the approximate size of Sec. 5.2).
 //
 // One cooperative launch (every workgroup resident) processes a batch of
-// insertions (or insert-or-add operations).  Wavefronts take chunks of 64 r
-// operations from a shared counter (r rounds, up to 64, fewer while the
-// table's free cells are few), one operation per lane per round (linear
-// probing with compare-and-swap, Alg. 1); equal keys of a chunk are combined
-// in LDS and applied once at the chunk's end.  Each wavefront counts its successful insertions locally
-// and adds the count to the global counter I after a randomised number
-// (1..64 r) of them; when the addition makes I reach alpha * c, it raises
-// the growing flag.
+// insertions (or insert-or-add operations).  Wavefront w of W owns the w-th
+// of W equal runs of the batch and works through it in chunks of 64 r
+// operations (r rounds, up to 64, fewer while the table's free cells are
+// few), one operation per lane per round (linear probing with
+// compare-and-swap, Alg. 1); equal keys of a chunk are combined in LDS and
+// applied once at the chunk's end.  Each wavefront counts its successful
+// insertions locally and adds the count to its shard of the global counter
+// after a randomised number (1..64 r) of them; when the addition makes the
+// shard reach its share of alpha * c, it raises the growing flag.
 //
 // The protocol of the synchronized variant: a wavefront looks at the flag
-// before taking each chunk (its "busy" period is one chunk); when it is
-// raised the wavefront drops its local count and arrives at the growth.  Once
-// every wavefront has arrived nobody touches the old table, and all of them
+// before each chunk (its "busy" period is one chunk); when it is raised the
+// wavefront drops its local count and arrives at the growth.  Once every
+// wavefront has arrived nobody touches the old table, and all of them
 // migrate it together (the dedicated helpers are the kernel's own
-// wavefronts) into the table of twice the size, which the host reserved and
-// zeroed before the launch: work items of old cells, read lane-consecutively,
-// each live element inserted into the target with compare-and-swap.  The
-// last to finish publishes the new table version, with I = the number of
-// moved elements, and clears the flag.
+// wavefronts) into the table of twice the size that the host reserved
+// before the launch, by the block-parallel cluster migration of Lemma 1.
+// The last to finish publishes the new table version, with the number of
+// moved elements as its base count, and clears the flag.
 //
 // The growing flag and the version share one word, gen = 2 * epoch + flag,
 // so a wavefront can never confuse a finished growth with a pending one.
 // Every wait is bounded by the device's constant-rate clock; passing the
 // bound sets an error and ends the wavefront (the others then time out too).
 //
-// Table cells are read with device-coherent loads and written with
-// device-coherent stores or atomics, since different wavefronts write the
-// target table and read it afterwards within the same launch.
+// While inserting, table cells are read with device-coherent loads and
+// written with device-coherent stores or atomics, since different
+// wavefronts write the target table and read it afterwards within the same
+// launch.  Counters that every wavefront updates are split over separate
+// lines (kAsyncShards).
 
 #include <hip/hip_runtime.h>
 
@@ -38,11 +40,14 @@
 
 #include "lpht_async.h"
 #include "lpht_device.h"
+#include "lpht_migrate.h"
 
 namespace lpht {
 
 namespace {
 
+constexpr int kMigQ = 8;                        // window cells per lane of the migration
+constexpr uint32_t kMigB = 64 * kMigQ - 2 * MIG_HALO;  // old cells per migration block (256)
 constexpr uint8_t kFlagReserved = 0xFE;
 constexpr uint8_t kFlagFull = 0xFF;
 
@@ -56,6 +61,11 @@ __device__ __forceinline__ void st64(u64 *p, u64 v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Waits until every memory operation this wavefront issued is acknowledged at
+// its point of coherence; the "memory" clobber keeps the compiler from moving
+// accesses across it.
+__device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // The key word of cell i (PACKED32: the whole cell word, key in the low half).
 template <int L>
@@ -127,74 +137,160 @@ __device__ __forceinline__ uint32_t lane0_add(uint32_t *p, uint32_t d) {
   return uni(r);
 }
 
-template <int L>
-__device__ __forceinline__ void put(void *cells, u64 p, u64 key, u64 val) {
-  if (L == 0) {
-    st64((u64 *)cells + p, (key & 0xFFFFFFFFull) | (val << 32));
-  } else {
-    st64((u64 *)cells + 2 * p + 1, val);
-    st64((u64 *)cells + 2 * p, key);
+// Shard of wavefront w, the number of wavefronts on shard `sh`, and the
+// number of shards in use.
+__device__ __forceinline__ uint32_t shard_size(uint32_t sh, uint32_t W) {
+  return W / kAsyncShards + (sh < W % kAsyncShards ? 1u : 0u);
+}
+__device__ __forceinline__ uint32_t shards_used(uint32_t W) { return W < kAsyncShards ? W : kAsyncShards; }
+
+// Counts the wavefront through barrier k (1, 2, ...) of the running growth:
+// after its own memory operations are acknowledged, it adds one to its
+// shard's line; the wavefront that completes a shard adds one to `arrived`,
+// which reaches k * shards_used(W) when everybody is through.  Returns true
+// for the wavefront that completed the barrier.
+__device__ bool arrive(AsyncCtl *ctl, uint32_t sh, uint32_t W, uint32_t k) {
+  wait_mem();
+  uint32_t last = 0;
+  if ((threadIdx.x & 63) == 0) {
+    const unsigned long long old =
+        __hip_atomic_fetch_add(&ctl->arrive[sh].v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == (unsigned long long)k * shard_size(sh, W) - 1) {
+      const uint32_t t = __hip_atomic_fetch_add(&ctl->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = t == k * shards_used(W) - 1;
+    }
   }
+  return uni(last) != 0;
 }
 
-// The migration of epoch e into e + 1 by all W wavefronts.  Returns false
-// on timeout.  gen is 2e + 1 on entry; the last wavefront through sets it
-// to 2(e + 1).
+// The migration of epoch e into e + 1 by all W wavefronts (this one is
+// wavefront `wid`).  Returns false on timeout.  gen is 2e + 1 on entry; the
+// last wavefront through sets it to 2(e + 1).
+//
+//   1. arrival: every wavefront has left the old table;
+//   2. block-parallel cluster migration (Sec. 5.3.1, Lemma 1), the same
+//      per-block work as the migration kernel: wavefront w takes the w-th
+//      of W equal runs of consecutive blocks of kMigB old cells (no shared
+//      claim counter), builds each block's owned new range in its LDS region
+//      (`wlds`, free between chunks) from the window of old cells around the
+//      block and writes it once, empty cells included, so the target needs
+//      no zeroing; the next block's window is loaded while the current one is
+//      worked on;
+//   3. arrival; if some block saw a cluster longer than the halo, every
+//      wavefront zeroes the target, arrives once more, and the old table's
+//      live elements are inserted into it with compare-and-swap instead;
+//   4. the last wavefront through publishes the new version.
+// Outside the migration every access to the tables is device-coherent by
+// itself (agent-scope relaxed atomic loads, stores and read-modify-writes).
+// The block migration uses plain loads and stores, bracketed by two
+// agent-scope fences per wavefront: one after the first arrival (this XCD's
+// L2 may hold lines of the old table older than the inserters' atomics) and
+// one before the second (the new cells sit in this XCD's L2 until written
+// back).
 template <int L>
-__device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e, uint32_t W, u64 ticks) {
+__device__ bool migrate(const AsyncArgs &a, const uint32_t (*T)[256], uint32_t e, uint32_t W, uint32_t wid,
+                        u64 ticks, unsigned char *wlds) {
   AsyncCtl *ctl = a.ctl;
   const uint32_t lane = threadIdx.x & 63;
+  const uint32_t sh = wid % kAsyncShards, S = shards_used(W);
   const View o = view_of(a, e, W), nv = view_of(a, e + 1, W);
-  // 1. every wavefront has left the old table
+  // 1.
+  arrive(ctl, sh, W, 1);
+  if (!wait_ge(&ctl->arrived, S, ticks)) return false;
   __threadfence();
-  lane0_add(&ctl->arrived, 1);
-  if (!wait_ge(&ctl->arrived, W, ticks)) return false;
-  __threadfence();
-  // 2. every live element of the old table, read lane-consecutively, is
-  //    inserted into the target with compare-and-swap (the target is a valid
-  //    table of the same keys; the order inside clusters is that of the
-  //    insertions)
+  // 2. (the capacity is at least 2^19 cells, a whole number of blocks)
   const u64 oc = 1ull << o.log2c;
-  u64 moved = 0;
-  for (;;) {
-    const u64 item = lane0_add(&ctl->mig_next, 1);
-    const u64 b0 = item * kAsyncMigBlock;
-    if (b0 >= oc) break;
-    const u64 b1 = std::min<u64>(oc, b0 + kAsyncMigBlock);
-    for (u64 i = b0 + lane; i < b1; i += 64) {
-      const u64 k = key_at<L>(o.cells, i);
-      if (k == kEmpty || k == kTomb) continue;
-      const u64 v = L == 0 ? (ld64((const u64 *)o.cells + i) >> 32) : ld64((const u64 *)o.cells + 2 * i + 1);
-      u64 p = home_of<L>(T, k, a.crc_hi, a.crc_lo, a.mul, nv.log2c);
-      for (u64 step = 0; step <= nv.mask; ++step, p = (p + 1) & nv.mask) {
-        if (L == 0) {
-          if (cas64((u64 *)nv.cells + p, kEmpty, k | (v << 32)) == kEmpty) break;
-        } else if (cas64((u64 *)nv.cells + 2 * p, kEmpty, k) == kEmpty) {
-          st64((u64 *)nv.cells + 2 * p + 1, v);
-          break;
-        }
+  const uint32_t nblocks = (uint32_t)(oc / kMigB);
+  long long moved = 0;
+  bool overflow = false;
+  {
+    const uint32_t b0 = (uint32_t)((u64)nblocks * wid / W), b1 = (uint32_t)((u64)nblocks * (wid + 1) / W);
+    u64 nk[kMigQ], nvv[kMigQ];
+    if (b0 < b1) mig_load_window<L, kMigQ>(nk, nvv, o.cells, o.mask, b0);
+    for (uint32_t b = b0; b < b1; ++b) {
+      u64 k[kMigQ], v[kMigQ];
+#pragma unroll
+      for (int q = 0; q < kMigQ; ++q) {
+        k[q] = nk[q];
+        v[q] = nvv[q];
       }
-      ++moved;
+      if (b + 1 < b1) mig_load_window<L, kMigQ>(nk, nvv, o.cells, o.mask, b + 1);
+      moved += mig_block<L, kMigQ>(k, v, b, o.log2c, 1, T, a.crc_hi, a.crc_lo, a.mul, wlds, nv.cells, overflow);
     }
   }
-  const long long ms = wave_sum((long long)moved);
-  if (lane == 0 && ms) __hip_atomic_fetch_add(&ctl->moved, (unsigned long long)ms, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-  // 3. the last to arrive publishes the new version
+  if (__any(overflow) && lane == 0)
+    __hip_atomic_store(&ctl->mig_overflow, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // 3.
   __threadfence();
-  const uint32_t before = lane0_add(&ctl->arrived, 1);
-  if (before == 2 * W - 1) {
+  arrive(ctl, sh, W, 2);
+  if (!wait_ge(&ctl->arrived, 2 * S, ticks)) return false;
+  const bool fallback = uni(ld32(&ctl->mig_overflow)) != 0;
+  uint32_t last = 3;  // the barrier after which everything is written
+  if (fallback) {
+    // zero the target, then re-insert every live element by compare-and-swap
+    const u64 nc16 = (L == 0 ? (1ull << nv.log2c) / 2 : (1ull << nv.log2c));  // 16-byte units
+    for (;;) {
+      const uint32_t item = lane0_add(&ctl->mig_next2, 1);
+      const u64 z0 = (u64)item * 4096;
+      if (z0 >= nc16) break;
+      const u64 z1 = std::min<u64>(nc16, z0 + 4096);
+      for (u64 x = z0 + lane; x < z1; x += 64) {
+        st64((u64 *)nv.cells + 2 * x, 0ull);
+        st64((u64 *)nv.cells + 2 * x + 1, 0ull);
+      }
+    }
+    arrive(ctl, sh, W, 3);
+    if (!wait_ge(&ctl->arrived, 3 * S, ticks)) return false;
+    last = 4;
+    moved = 0;
+    for (;;) {
+      const uint32_t item = lane0_add(&ctl->mig_next3, 1);
+      const u64 b0 = (u64)item * kAsyncMigBlock;
+      if (b0 >= oc) break;
+      const u64 b1 = std::min<u64>(oc, b0 + kAsyncMigBlock);
+      for (u64 i = b0 + lane; i < b1; i += 64) {
+        const u64 k = key_at<L>(o.cells, i);
+        if (k == kEmpty || k == kTomb) continue;
+        const u64 v = L == 0 ? (ld64((const u64 *)o.cells + i) >> 32) : ld64((const u64 *)o.cells + 2 * i + 1);
+        u64 p = home_of<L>(T, k, a.crc_hi, a.crc_lo, a.mul, nv.log2c);
+        for (u64 step = 0; step <= nv.mask; ++step, p = (p + 1) & nv.mask) {
+          if (L == 0) {
+            if (cas64((u64 *)nv.cells + p, kEmpty, k | (v << 32)) == kEmpty) break;
+          } else if (cas64((u64 *)nv.cells + 2 * p, kEmpty, k) == kEmpty) {
+            st64((u64 *)nv.cells + 2 * p + 1, v);
+            break;
+          }
+        }
+        ++moved;
+      }
+    }
+  }
+  const long long ms = wave_sum(moved);
+  if (lane == 0 && ms)
+    __hip_atomic_fetch_add(&ctl->moved[sh].v, (unsigned long long)ms, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // 4.
+  if (arrive(ctl, sh, W, last)) {
+    // the last one through: the new version begins with base = the moved
+    // elements and empty shards
+    unsigned long long mv = 0;
+    if (lane < S) mv = __hip_atomic_load(&ctl->moved[lane].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mv = (unsigned long long)wave_sum((long long)mv);
+    if (lane < S) {
+      st64(&ctl->moved[lane].v, 0ull);
+      st64(&ctl->count[lane].v, 0ull);
+      st64(&ctl->arrive[lane].v, 0ull);
+    }
     if (lane == 0) {
-      __threadfence();
-      const unsigned long long mv = __hip_atomic_load(&ctl->moved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->I, mv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->moved, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->mig_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st64(&ctl->base, mv);
+      __hip_atomic_store(&ctl->mig_next2, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->mig_next3, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->mig_overflow, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (fallback) __hip_atomic_fetch_add(&ctl->fallbacks, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->epoch, e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      __hip_atomic_store(&ctl->gen, 2 * (e + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+    wait_mem();  // the counters before the new version
+    if (lane == 0) __hip_atomic_store(&ctl->gen, 2 * (e + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   return true;
 }
@@ -219,12 +315,17 @@ struct ChunkLds {
   u64 rep[kChunkSlots];
 };
 
+// A wavefront's LDS: its combining table between growths, the migration's
+// window and image during one (the table is empty then and cleared after).
+constexpr size_t kWaveLds = sizeof(ChunkLds) > mig_wave_lds(kMigB, 1, 2) ? sizeof(ChunkLds) : mig_wave_lds(kMigB, 1, 2);
+
 template <int L>
 __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, uint32_t W) {
   __shared__ uint32_t T[8][256];
-  __shared__ ChunkLds cl[4];
+  __shared__ __attribute__((aligned(16))) unsigned char wl[4][kWaveLds];
   crc_tables_build(T);
-  ChunkLds &C = cl[threadIdx.x >> 6];
+  unsigned char *wlds = wl[threadIdx.x >> 6];
+  ChunkLds &C = *reinterpret_cast<ChunkLds *>(wlds);
   AsyncCtl *ctl = a.ctl;
   const uint32_t lane = threadIdx.x & 63;
   for (uint32_t q = lane; q < kChunkSlots; q += 64) {
@@ -233,9 +334,19 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
   }
   wave_sync();
   uint32_t *gen = &ctl->gen;
+  const uint32_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t sh = wid % kAsyncShards, S = shards_used(W);
+  // this wavefront's operations [pos, end): the wid-th of W equal runs
+  u64 pos = (u64)(((unsigned __int128)a.n * wid) / W);
+  const u64 end = (u64)(((unsigned __int128)a.n * (wid + 1)) / W);
   uint32_t my = 0;
   View v = view_of(a, 0, W);
-  uint32_t rng = 0x9E3779B9u ^ (blockIdx.x * 4 + (threadIdx.x >> 6)) * 0x85EBCA6Bu;
+  // a shard's share of the insertions that take the table to alpha c: the
+  // growth starts when one shard has it, so while none has, the flushed
+  // total is below the threshold
+  auto share = [&](u64 base) -> u64 { return v.thr > base ? (v.thr - base) / S : 0; };
+  u64 tshare = share(a.used0);
+  uint32_t rng = 0x9E3779B9u ^ wid * 0x85EBCA6Bu;
   auto next_flush = [&]() {
     rng ^= rng << 13;
     rng ^= rng >> 17;
@@ -251,15 +362,21 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
     const uint32_t g = uni(ld32(gen));
     if (g / 2 > my) {  // a growth finished (this wavefront took part in it)
       my = g / 2;
-      v = view_of(a, my, W);
-      __threadfence();
+      v = view_of(a, my, W);  // its cells' addresses depend on the load of gen
+      tshare = share(ld64(&ctl->base));
     }
     if (g & 1u) {  // a growth of version `my` is pending: arrive and help
       local = 0;  // the migration recounts what was inserted
-      if (!migrate<L>(a, T, my, W, ticks)) {
+      if (!migrate<L>(a, T, my, W, wid, ticks, wlds)) {
         err = 1;
         break;
       }
+      // the migration used the combining table's LDS
+      for (uint32_t q = lane; q < kChunkSlots; q += 64) {
+        C.key[q] = 0;
+        C.acc[q] = 0;
+      }
+      wave_sync();
       const uint32_t g2 = wait_gen_past(gen, g, ticks);
       if (g2 == ~0u) {
         err = 1;
@@ -278,17 +395,14 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
       __builtin_amdgcn_s_sleep(4);
       continue;
     }
-    const u64 span = 64ull * v.rounds;
-    u64 base = 0;
-    if (lane == 0) base = __hip_atomic_fetch_add(&ctl->next, (unsigned long long)span, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    base = ((u64)uni((uint32_t)(base >> 32)) << 32) | uni((uint32_t)base);
-    if (base >= a.n) {
+    if (pos >= end) {
       finished = true;
       idle_since = wall_clock64();
       lane0_add(&ctl->finished, 1);
       continue;
     }
+    const u64 base = pos, lim = std::min<u64>(end, pos + 64ull * v.rounds);
+    pos = lim;
     // the table operation for key with value d in the current table: 1
     // inserted, 0 present (d added in add mode), kFlagFull no empty cell
     auto apply_op = [&](u64 key, u64 d) -> uint8_t {
@@ -327,15 +441,16 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
       return kFlagFull;
     };
     // adds the wavefront's new insertions to its local count, flushing it to
-    // I (and raising the growing flag) when it reaches the random bound
+    // its shard of the counter (and raising the growing flag) when it
+    // reaches the random bound
     auto account = [&](uint32_t ins) {
       local += ins;
       if (local >= flush_at) {
         uint32_t trig = 0;
         if (lane == 0) {
-          const unsigned long long before =
-              __hip_atomic_fetch_add(&ctl->I, (unsigned long long)local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          trig = before + local >= v.thr && my + 1 < a.nladder;
+          const unsigned long long before = __hip_atomic_fetch_add(
+              &ctl->count[sh].v, (unsigned long long)local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          trig = before + local >= tshare && my + 1 < a.nladder;
         }
         local = 0;
         flush_at = next_flush();
@@ -353,7 +468,7 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
       const bool claim = taken < kChunkSlots / 4 * 3;
       uint32_t inserted = 0;
       bool lead = false;
-      if (i < a.n) {
+      if (i < lim) {
         const u64 key = L == 0 ? (u64)((const uint32_t *)a.keys)[i] : ((const u64 *)a.keys)[i];
         const u64 d = a.vals ? (L == 0 ? (u64)((const uint32_t *)a.vals)[i] : ((const u64 *)a.vals)[i]) : 1;
         if (key <= kTomb) {
@@ -428,7 +543,7 @@ __global__ void __launch_bounds__(256) k_async_insert(AsyncArgs a, u64 ticks, ui
 __global__ void k_async_init(AsyncCtl *ctl, u64 used0) {
   for (uint32_t i = threadIdx.x; i < sizeof(AsyncCtl) / 8; i += blockDim.x) ((unsigned long long *)ctl)[i] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) ctl->I = used0;
+  if (threadIdx.x == 0) ctl->base = used0;
 }
 
 }  // namespace

@@ -39,6 +39,7 @@
 #include <stdint.h>
 
 #include "lpht_device.h"
+#include "lpht_migrate.h"
 #include "lpht_internal.h"
 
 namespace lpht {
@@ -824,22 +825,6 @@ __global__ void __launch_bounds__(256) k_migrate_simple(const void *old_cells, u
 // Positions are kept unwrapped (old cell x may be negative for block 0).  A
 // cluster longer than the halo (or a table without empty cells) sets the
 // overflow flag; the guarded simple migration then redoes the whole move.
-constexpr int MIG_HALO = 128;
-constexpr uint16_t kImgEmpty = 0xFFFF;
-
-__host__ __device__ constexpr uint32_t mig_window(uint32_t mb) { return mb + 2 * MIG_HALO; }
-
-// LDS of one wavefront: window keys and values (u64 each; PACKED32 keeps the
-// word in the key array), each window cell's state (i32: the new home's image
-// slot, or one of the negative codes below), the image (u16 per new cell) and
-// the list of cluster starts (u16 per start, at most half the window).
-__host__ __device__ constexpr size_t mig_wave_lds(uint32_t mb, uint32_t layout, uint32_t gamma) {
-  return ((size_t)mig_window(mb) * ((layout == 0 ? 8u : 16u) + 4u + 1u) + (size_t)gamma * mig_window(mb) * 2u +
-          15) &
-         ~(size_t)15;
-}
-constexpr int32_t kCellEmpty = -1, kCellTomb = -2, kCellFar = -3;  // window cell states
-
 // Q = window cells per lane; the block is B = 64 Q - 2 MIG_HALO old cells.
 // A workgroup is 1..4 wavefronts, each with its own LDS region.
 template <int LAYOUT, int Q>
@@ -851,167 +836,30 @@ __global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint
   __shared__ uint32_t s_err;
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn_lds[];
   crc_tables_build(T);
-
-  constexpr int H = MIG_HALO;
-  constexpr uint32_t W = 64 * Q;  // window cells
-  constexpr uint32_t mb = W - 2 * H;
-  static_assert(H % 64 == 0 && mb % 64 == 0, "window of whole lane rows");
+  constexpr uint32_t mb = 64 * Q - 2 * MIG_HALO;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t gamma = 1u << g;  // 1 or 2
-  const uint32_t IW = gamma * W;   // image slots
-  unsigned char *base = dyn_lds + wave * mig_wave_lds(mb, LAYOUT, gamma);
-  u64 *wkey = (u64 *)base;
-  u64 *wval = wkey + W;                                   // KV64 only
-  int32_t *wnh = (int32_t *)(wkey + (LAYOUT == 0 ? W : 2 * W));
-  uint16_t *img = (uint16_t *)(wnh + W);
-  uint16_t *starts = img + IW;  // cluster starts of [lo, hi)
-
+  unsigned char *base = dyn_lds + wave * mig_wave_lds(mb, LAYOUT, 1u << g);
   const u64 cap = 1ull << log2_old, mask = cap - 1;
-  const uint32_t log2_new = log2_old + g;
   const u64 nblocks = cap >> (31 - __builtin_clz(mb));  // cap / mb, both powers of two
   const uint32_t nwb = blockDim.x >> 6;
   const u64 nw = (u64)gridDim.x * nwb;
   long long moved = 0;
   bool overflow = false;
-
-  // window cells t = lane + 64 q of block b, loaded into registers; the next
-  // block's loads are issued before the current block is worked on, so their
-  // latency overlaps the work
+  // the next block's window is loaded before the current block is worked
+  // on, so its latency overlaps the work
   u64 nk[Q], nv[Q];
-  auto load_window = [&](u64 b) {
-    const long long wb = (long long)(b * mb) - H;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const u64 x = (u64)(wb + (long long)(lane + 64 * q)) & mask;
-      if (LAYOUT == 0) {
-        nk[q] = ((const u64 *)old_cells)[x];
-        nv[q] = 0;
-      } else {
-        const u64x2 c = ((const u64x2 *)old_cells)[x];
-        nk[q] = c.x;
-        nv[q] = c.y;
-      }
-    }
-  };
   u64 blk = (u64)blockIdx.x * nwb + wave;
-  if (blk < nblocks) load_window(blk);
+  if (blk < nblocks) mig_load_window<LAYOUT, Q>(nk, nv, old_cells, mask, blk);
   for (; blk < nblocks; blk += nw) {
-    const long long d = (long long)(blk * mb);
-    const long long wbase = d - H;  // unwrapped old index of window cell 0
     u64 k[Q], v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       k[q] = nk[q];
       v[q] = nv[q];
     }
-    if (blk + nw < nblocks) load_window(blk + nw);
-    u64 emp[Q];  // ballot of empty window cells, 64 per word
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const uint32_t t = lane + 64 * q;
-      const u64 key = LAYOUT == 0 ? (k[q] & 0xFFFFFFFFull) : k[q];
-      wkey[t] = k[q];
-      if (LAYOUT == 1) wval[t] = v[q];
-      int32_t rel = key == kEmpty ? kCellEmpty : kCellTomb;
-      if (key != kEmpty && key != kTomb) {
-        // new home, unwrapped consistently with this cell's old position
-        const u64 hn = home_of<LAYOUT>(T, key, crc_hi, crc_lo, mul, log2_new);
-        const u64 oh = hn >> g;
-        const long long x = wbase + (long long)t;
-        const u64 delta = ((u64)x - oh) & mask;
-        const long long nh = (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
-        const long long r = nh - (long long)gamma * wbase;  // image slot of the home
-        rel = (r < 0 || r >= (long long)IW) ? kCellFar : (int32_t)r;
-      }
-      wnh[t] = rel;
-      emp[q] = __ballot(key == kEmpty);
-    }
-    for (uint32_t t = lane; t < IW / 2; t += 64) ((uint32_t *)img)[t] = 0xFFFFFFFFu;
-    // the window range [lo, hi) of the clusters overlapping the block
-    // (cell H - 1 and cell H both non-empty: a cluster comes in from before);
-    // every index into emp[] is a constant, so it stays in registers
-    int lo = H, hi = H + (int)mb;
-    bool skip = false;
-    if (!((emp[H / 64 - 1] >> 63) & 1ull) && !(emp[H / 64] & 1ull)) {
-      int last = -1;
-#pragma unroll
-      for (int q = 0; q < H / 64; ++q)
-        if (emp[q]) last = 64 * q + 63 - __builtin_clzll(emp[q]);
-      if (last < 0) skip = true;
-      lo = last + 1;
-    }
-    if (!((emp[(H + mb) / 64 - 1] >> 63) & 1ull)) {
-      int first = -1;
-#pragma unroll
-      for (int q = Q - 1; q >= 0; --q) {
-        if (64 * q < H + (int)mb) break;
-        if (emp[q]) first = 64 * q + __builtin_ctzll(emp[q]);
-      }
-      if (first < 0) skip = true;
-      hi = first;
-    }
-    wave_sync();
-    if (skip) {
-      overflow = true;
-    } else {
-      // the cluster starts in [lo, hi) (non-empty cells after an empty one),
-      // listed in LDS; lanes then take them round-robin, each walking its
-      // clusters in old-array order
-      uint32_t nstarts = 0;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int t = (int)lane + 64 * q;
-        const bool here_empty = (emp[q] >> lane) & 1ull;
-        const bool prev_empty =
-            lane ? (bool)((emp[q] >> (lane - 1)) & 1ull) : (q == 0 ? true : (bool)(emp[q > 0 ? q - 1 : 0] >> 63));
-        const bool st0 = t >= lo && t < hi && !here_empty && prev_empty;
-        const u64 m = __ballot(st0);
-        if (st0) starts[nstarts + __builtin_popcountll(m & ((1ull << lane) - 1))] = (uint16_t)t;
-        nstarts += (uint32_t)__builtin_popcountll(m);
-      }
-      wave_sync();
-      bool bad = false;
-      for (uint32_t i = lane; i < nstarts && !bad; i += 64) {
-        for (int u = starts[i]; u < hi; ++u) {
-          int p = wnh[u];
-          if (p == kCellEmpty) break;
-          if (p == kCellTomb) continue;
-          if (p < 0) {
-            bad = true;
-            break;
-          }
-          while (p < (int)IW && img[p] != kImgEmpty) ++p;
-          if (p >= (int)IW) {
-            bad = true;
-            break;
-          }
-          img[p] = (uint16_t)u;
-        }
-      }
-      if (bad) overflow = true;
-      wave_sync();
-      // the owned new cells [g*d, g*(d+B)) = image slots [g*H, g*(H+B))
-      const u64 dst0 = (u64)d * gamma;
-      const uint32_t n_out = gamma * mb;
-      for (uint32_t t = lane; t < n_out; t += 64) {
-        const uint16_t ix = img[gamma * H + t];
-        if (LAYOUT == 0) {
-          const u64 w = ix == kImgEmpty ? 0ull : wkey[ix];
-          ((u64 *)new_cells)[dst0 + t] = w;
-          moved += (ix != kImgEmpty);
-        } else {
-          u64x2 c = {0ull, 0ull};
-          if (ix != kImgEmpty) {
-            c.x = wkey[ix];
-            c.y = wval[ix];
-          }
-          ((u64x2 *)new_cells)[dst0 + t] = c;
-          moved += (ix != kImgEmpty);
-        }
-      }
-    }
-    wave_sync();
+    if (blk + nw < nblocks) mig_load_window<LAYOUT, Q>(nk, nv, old_cells, mask, blk + nw);
+    moved += mig_block<LAYOUT, Q>(k, v, blk, log2_old, g, T, crc_hi, crc_lo, mul, base, new_cells, overflow);
   }
   if (__any(overflow) && lane == 0) atomicOr(&st->overflow, 1ull);
   flush_counts(st, moved, moved, 0, s_acc, &s_err);

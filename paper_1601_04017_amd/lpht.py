@@ -99,6 +99,7 @@ class lpht_stats(ctypes.Structure):
         ("shrinks", ctypes.c_uint64),
         ("bulk_merges", ctypes.c_uint64),
         ("async_growths", ctypes.c_uint64),
+        ("async_fallbacks", ctypes.c_uint64),
     ]
 
 

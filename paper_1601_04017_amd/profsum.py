@@ -23,12 +23,13 @@ import os
 from collections import OrderedDict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_kernels.hip", "lpht_device.h", "lpht_internal.h")]
+KERNEL_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_kernels.hip", "lpht_migrate.h", "lpht_device.h", "lpht_internal.h")]
 SHRINK_SRCS = [os.path.join(PKG, "csrc", f)
                for f in ("lpht_shrink.hip", "lpht_shrink.h", "lpht_device.h", "lpht_internal.h")]
 STR_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_str.hip", "lpht_str.h", "lpht_device.h", "lpht_internal.h")]
 ASYNC_SRCS = [os.path.join(PKG, "csrc", f)
-              for f in ("lpht_async.hip", "lpht_async.h", "lpht_device.h", "lpht_internal.h")]
+              for f in ("lpht_async.hip", "lpht_async.h", "lpht_migrate.h", "lpht_device.h", "lpht_internal.h")]
+PART_SRCS = [os.path.join(PKG, "csrc", f) for f in ("lpht_part.hip", "lpht_part.h", "lpht_device.h", "lpht_internal.h")]
 
 
 def kernel_source_sha(srcs=None) -> str:
@@ -101,7 +102,8 @@ def main():
     lines += ["```", "", f"Kernel source sha256[:16]: `{kernel_source_sha()}` "
               f"(shrink kernels: `{kernel_source_sha(SHRINK_SRCS)}`, "
               f"string-key kernels: `{kernel_source_sha(STR_SRCS)}`, "
-              f"in-kernel growth: `{kernel_source_sha(ASYNC_SRCS)}`)", "",
+              f"in-kernel growth: `{kernel_source_sha(ASYNC_SRCS)}`, "
+              f"partitioned insert-or-add: `{kernel_source_sha(PART_SRCS)}`)", "",
               "## Kernel durations (--kernel-trace --stats)", "",
               "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
     for s in stats[:a.rows]:

@@ -109,3 +109,41 @@ def test_duplicates_existing_contents_and_reserved_keys(layout):
     assert t.count() == (len(live), len(live))
     assert t.status() == lpht.ERR_RESERVED_KEY
     _oracle_same_cells(t, layout, live)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_growths_use_the_block_migration(layout):
+    # ordinary growths inside the kernel move clusters block by block (no
+    # fallback), and the result is the oracle's
+    n = 2_000_000
+    keys = _keys(layout, n, 21)
+    vals = (np.arange(n) + 5).astype(keys_dtype(layout))
+    t = make_table(layout, 12, auto_grow=True)
+    t.insert_async(to_dev(keys), to_dev(vals), flags=False)
+    st = t.stats()
+    assert st["async_growths"] >= 1 and st["async_fallbacks"] == 0
+    _oracle_same_cells(t, layout, dict(zip(keys.tolist(), vals.tolist())))
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_cluster_longer_than_halo_takes_the_fallback(layout):
+    # 300 keys whose homes in a 2^22-cell table lie in 256 cells form a
+    # cluster far longer than the block migration's 128-cell halo (it stays
+    # that long at 2^21 and 2^23 cells: positions nest); the growths that see
+    # it re-insert by compare-and-swap, and the contents still match
+    import oracle as O
+    kb = 4 if layout == oracle.PACKED32 else 8
+    cand = np.arange(2, 6_000_002, dtype=np.uint64)
+    hm = (O.hash_bulk(cand.astype(keys_dtype(layout)), kb) >> np.uint64(64 - 22)).astype(np.int64)
+    crowd = cand[(hm >= 70_000) & (hm < 70_256)][:300].astype(keys_dtype(layout))
+    assert crowd.size == 300  # 6e6 candidates give about 366
+    rest = _keys(layout, 1_200_000, 23)
+    rest = rest[~np.isin(rest, crowd)]
+    keys = np.concatenate([crowd, rest])
+    keys = keys[inputs.permutation(keys.size, 24)]
+    vals = (np.arange(keys.size) * 3 + 1).astype(keys_dtype(layout))
+    t = make_table(layout, 12, auto_grow=True)
+    t.insert_async(to_dev(keys), to_dev(vals), flags=False)
+    st = t.stats()
+    assert st["async_growths"] >= 1 and st["async_fallbacks"] >= 1
+    _oracle_same_cells(t, layout, dict(zip(keys.tolist(), vals.tolist())))
