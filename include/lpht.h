@@ -445,8 +445,18 @@ int lpht_batch_run(lpht_batch *b, const lpht_batch_op *ops, uint32_t nops, void 
  *                       publish the completion in host memory.  No HIP call
  *                       is made per request.  The kernel's launch is captured
  *                       once as a HIP graph and replayed: it exits when idle
- *                       and is relaunched on new work; for table growth it is
- *                       stopped, the table migrates, and it is relaunched.
+ *                       and is relaunched on new work.  Growth happens inside
+ *                       it (hiding the migration, Sec. 5.3.2): when the
+ *                       growth rule asks for one doubling of a table of at
+ *                       least 2^10 cells, the worker posts a migration entry,
+ *                       whose rounds are blocks of the block-parallel cluster
+ *                       migration (Sec. 5.3.1) that the serving wavefronts
+ *                       run while requests on other tables go on; the
+ *                       waiting request is posted once the table has its new
+ *                       cells.  Other growth (several doublings, cleanups,
+ *                       shrinks, small or empty tables) and a migration that
+ *                       meets a cluster longer than its halo stop the
+ *                       kernel, migrate on the host and relaunch it.
  *                       Request arrays must be pinned host memory (or device
  *                       memory); submit rejects others with
  *                       LPHT_ERR_INVALID.
@@ -507,6 +517,9 @@ typedef struct lpht_server_stats {
   uint64_t peak_hbm_bytes;   /* peak of tables + staging as accounted by admission */
   uint64_t admission_waits;  /* times the head request waited for budget */
   double busy_us;            /* time with at least one request on the device */
+  uint64_t kernel_growths;   /* resident mode: doublings migrated by the running kernel */
+  uint64_t kernel_growth_fallbacks; /* of those, moves redone by the host (a cluster longer
+                                     * than the migration's halo) */
 } lpht_server_stats;
 
 typedef struct lpht_server lpht_server;

@@ -63,6 +63,41 @@ hipMemPool_t g_pools[kMaxDevices];
 // blocks handed out by pool_alloc and not yet given back to pool_free
 std::atomic<long long> g_pool_blocks{0};
 
+// Frees the pool has not been told of yet.  A block freed on stream s is
+// often still to be read by work queued on s (the old table of a migration
+// just enqueued); handed to another stream's allocation at once, it was seen
+// overwritten before that work ran, although the stream-ordered allocator
+// should have kept it back.  So pool_free records an event on s and returns
+// the block to the pool only once the event has completed; allocations and
+// frees reap the completed ones.
+struct PendingFree {
+  void *p;
+  hipEvent_t ev;
+  int device;
+};
+std::mutex g_pending_mu;
+std::vector<PendingFree> g_pending;
+std::vector<hipEvent_t> g_spare_events;
+
+// Returns to the pool every pending block of `device` whose event has
+// completed (all of them, waiting, when `wait`), ordered on stream s.
+void reap_pending(int device, hipStream_t s, bool wait) {
+  std::lock_guard<std::mutex> lk(g_pending_mu);
+  size_t k = 0;
+  for (size_t i = 0; i < g_pending.size(); ++i) {
+    PendingFree &f = g_pending[i];
+    const bool done = f.device == device &&
+                      (wait ? hipEventSynchronize(f.ev) == hipSuccess : hipEventQuery(f.ev) == hipSuccess);
+    if (done) {
+      (void)hipFreeAsync(f.p, s);
+      g_spare_events.push_back(f.ev);
+    } else {
+      g_pending[k++] = f;
+    }
+  }
+  g_pending.resize(k);
+}
+
 hipMemPool_t device_pool(int dev) {
   if (dev < 0 || dev >= kMaxDevices) return nullptr;
   std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -84,6 +119,7 @@ hipMemPool_t device_pool(int dev) {
 void *pool_alloc(int device, size_t bytes, hipStream_t s) {
   hipMemPool_t pool = device_pool(device);
   if (!pool) return nullptr;
+  reap_pending(device, s, false);
   void *p = nullptr;
   if (hipMallocFromPoolAsync(&p, bytes, pool, s) != hipSuccess) return nullptr;
   g_pool_blocks.fetch_add(1);
@@ -92,8 +128,34 @@ void *pool_alloc(int device, size_t bytes, hipStream_t s) {
 
 void pool_free(void *p, hipStream_t s) {
   if (!p) return;
-  (void)hipFreeAsync(p, s);
+  int device = 0;
+  hipEvent_t ev = nullptr;
+  bool queued = false;
+  if (hipGetDevice(&device) == hipSuccess) {
+    {
+      std::lock_guard<std::mutex> lk(g_pending_mu);
+      if (!g_spare_events.empty()) {
+        ev = g_spare_events.back();
+        g_spare_events.pop_back();
+      }
+    }
+    if (ev || hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+      if (hipEventRecord(ev, s) == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_pending_mu);
+        g_pending.push_back({p, ev, device});
+        queued = true;
+      } else {
+        (void)hipEventDestroy(ev);
+      }
+    }
+  }
+  if (!queued) {
+    // no event: wait for the stream, then free
+    (void)hipStreamSynchronize(s);
+    (void)hipFreeAsync(p, s);
+  }
   g_pool_blocks.fetch_sub(1);
+  reap_pending(device, s, false);
 }
 
 int release_pools() {
@@ -109,10 +171,18 @@ int release_pools() {
       have_cur = true;
     }
     // the frees of destroyed tables complete in stream order: wait for them
+    if (hipSetDevice(d) == hipSuccess) {
+      reap_pending(d, nullptr, true);
+    }
     if (hipSetDevice(d) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
         hipMemPoolTrimTo(g_pools[d], 0) != hipSuccess || hipMemPoolDestroy(g_pools[d]) != hipSuccess)
       rc = LPHT_ERR_DEVICE;
     g_pools[d] = nullptr;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_pending_mu);
+    for (hipEvent_t ev : g_spare_events) (void)hipEventDestroy(ev);
+    g_spare_events.clear();
   }
   if (have_cur) (void)hipSetDevice(cur);
   return rc;
@@ -341,6 +411,16 @@ int grow_before_batch(lpht_table *t, uint64_t b, hipStream_t s) {
   if (rc) return rc;
   t->pending = b;
   return LPHT_OK;
+}
+
+int growth_kind(const lpht_table *t, uint64_t b) {
+  const uint64_t c = 1ull << t->log2c;
+  if (b == 0 || !t->cfg.auto_grow || within_fill(t, t->known_used + b, c)) return 0;
+  if ((unsigned __int128)(t->known_live + b) * 2 * t->cfg.max_fill_den <=
+      (unsigned __int128)c * t->cfg.max_fill_num)
+    return 2;  // cleanup or shrink
+  if (t->known_live == 0 || t->log2c >= 34) return 2;
+  return within_fill(t, t->known_live + b, 2 * c) ? 1 : 2;
 }
 
 BulkArgs make_args(lpht_table *t) {

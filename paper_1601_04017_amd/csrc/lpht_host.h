@@ -73,6 +73,12 @@ int sync_counts(lpht_table *t, hipStream_t s);
 int resize_empty(lpht_table *t, uint32_t log2_new, hipStream_t s, uint32_t steps = 1);
 int migrate_once(lpht_table *t, uint32_t log2_new, hipStream_t s);
 int grow_before_batch(lpht_table *t, uint64_t b, hipStream_t s);
+// What grow_before_batch would do before b insertions, on the host's counts
+// (which must be exact: nothing pending, no modification since the last
+// exact count): 0 nothing, 1 exactly one doubling of a non-empty table,
+// 2 anything else (several doublings, a cleanup or shrink, the resize of an
+// empty table).
+int growth_kind(const lpht_table *t, uint64_t b);
 BulkArgs make_args(lpht_table *t);
 bool aligned(const void *p, size_t a);
 int check_arrays(lpht_table *t, const void *keys, const void *vals, uint64_t n);

@@ -12,6 +12,7 @@ constexpr uint64_t kTomb = 1;   // del_key
 
 constexpr uint32_t kErrFull = 1u;
 constexpr uint32_t kErrReserved = 2u;
+constexpr uint32_t kErrMigrate = 4u;  // a block migration saw a cluster longer than its halo
 
 // Per-table device status block: exact counts and sticky error bits.  The
 // counts are spread over kCountSlots slots, one 128-byte line each, so that
@@ -119,8 +120,16 @@ struct alignas(64) PersistReq {   // host memory, one per ring entry
   void *hvals;                    // may be null
   uint8_t *hflags;                // may be null
   unsigned long long rounds[kPersistPhases];  // rounds per phase (0 for a phase without operations)
+  // A migration entry (mig_cells non-null) moves the table a.cells of 2^a.log2c
+  // cells into mig_cells of 2^mig_log2c cells (twice as many): its phase-0
+  // rounds are blocks of kPersistMigBlock old cells (Sec. 5.3.1, Lemma 1),
+  // its one copy-out round only completes it; a.n is 0 and there are no
+  // host arrays.
+  void *mig_cells;
+  unsigned long long mig_log2c;
   unsigned long long seq;         // q + 1 once the entry holds request q (written last)
 };
+constexpr uint32_t kPersistMigBlock = 256;
 
 struct alignas(64) PersistDone {  // host memory, written by the device
   unsigned long long seq;         // q + 1 when request q has completed (written last)

@@ -901,7 +901,11 @@ __global__ void __launch_bounds__(256) k_migrate_lds(const void *old_cells, uint
 // staging are read with agent-scope relaxed atomic loads and written with
 // agent-scope atomics, descriptors and counters likewise, host arrays are read
 // with volatile (uncached) loads, and results go to host memory as
-// system-scope (written-through) stores.  What orders one wavefront's accesses before a
+// system-scope (written-through) stores.  Table cells are only ever written
+// by read-modify-write atomics, which act at the device's point of
+// coherence; a request's staging is written and read within its group, that
+// is, within one XCD.  Migration entries are the exception: their blocks run
+// between two fences (persist_migrate).  What orders one wavefront's accesses before a
 // counter update that another wavefront waits for is then only their
 // completion: `wait_mem` (all of the wavefront's memory operations
 // acknowledged) comes before each counter update and each publication, and a
@@ -1147,6 +1151,48 @@ __device__ __attribute__((noinline)) void persist_copy_out(const u64 *req, u64 r
   }
 }
 
+// Each serving wavefront's LDS: its round buffers (values, staged keys,
+// flags, kinds) or, while it runs migration blocks, the block migration's
+// state (the scattering form, which keeps keys and values in registers, so
+// that four workgroups still fit a compute unit).
+constexpr uint32_t kPersistMigQ = 8;  // window rows: kPersistMigBlock + 2 MIG_HALO cells
+static_assert(64 * kPersistMigQ - 2 * MIG_HALO == kPersistMigBlock, "migration block of the resident kernel");
+constexpr size_t kPersistWaveLds =
+    std::max<size_t>((size_t)ROUND * 18, mig_wave_lds_scatter(kPersistMigBlock, 2));
+
+// Blocks [b, b + nb) of the migration entry at `req` (Sec. 5.3.1, Lemma 1):
+// the same per-block work as the migration kernel, with plain loads and
+// stores between two agent-scope fences.  The first drops this XCD's L2 lines
+// of the old table, which may predate the atomics of earlier requests; the
+// second writes the new cells back from this XCD's L2 before the rounds are
+// counted as finished, so that requests served on other XCDs read them.
+// (A device-scope relaxed store is no substitute: it reaches the XCD's L2,
+// not memory, and a request on another XCD then reads the cell as it was.)
+// A cluster longer than the halo sets kErrMigrate in the table's status; the
+// host then migrates the table itself.
+template <int LAYOUT>
+__device__ __attribute__((noinline)) void persist_migrate(const uint32_t (*T)[256], unsigned char *mlds,
+                                                          const u64 *req, u64 b, u64 nb) {
+  constexpr uint32_t Q = kPersistMigQ;
+  const uint32_t lane = threadIdx.x & 63;
+  BulkArgs A;
+  load_args(A, req);
+  void *nc = (void *)uni(req[offsetof(PersistReq, mig_cells) / sizeof(u64)]);
+  const uint32_t g = (uint32_t)uni(req[offsetof(PersistReq, mig_log2c) / sizeof(u64)]) - A.log2c;
+  const u64 mask = (1ull << A.log2c) - 1;
+  b = uni(b);
+  nb = uni(nb);
+  bool overflow = false;
+  __threadfence();
+  for (u64 i = b; i < b + nb; ++i) {
+    u64 k[Q], v[Q];  // no prefetch of the next window: the registers would spill here
+    mig_load_window<LAYOUT, Q>(k, v, A.cells, mask, i);
+    (void)mig_block<LAYOUT, Q, true>(k, v, i, A.log2c, g, T, A.crc_hi, A.crc_lo, A.mul, mlds, nc, overflow);
+  }
+  __threadfence();
+  if (__any(overflow) && lane == 0) atomicOr(&A.status->err, kErrMigrate);
+}
+
 __device__ __forceinline__ u64 pick(int p, u64 a, u64 b, u64 c, u64 d, u64 e) {
   return p == 0 ? a : p == 1 ? b : p == 2 ? c : p == 3 ? d : e;
 }
@@ -1155,7 +1201,8 @@ __device__ __forceinline__ u64 pick(int p, u64 a, u64 b, u64 c, u64 d, u64 e) {
 // claim or the stop flag is seen.  Returns whether any round was run.
 template <int LAYOUT>
 __device__ bool persist_serve(const uint32_t (*T)[256], uint8_t *wflag, u64 *wout, u64 *skeys,
-                              uint8_t *skinds, const u64 *req, PersistDev *dev, PersistDone *done_ring,
+                              uint8_t *skinds, unsigned char *mlds, const u64 *req, PersistDev *dev,
+                              PersistDone *done_ring,
                               PersistState *st, const u64 *stop_word, u64 q, uint32_t e, u64 gw,
                               uint32_t &rounds_since_check, bool &stop_seen) {
   const uint32_t lane = threadIdx.x & 63;
@@ -1164,6 +1211,7 @@ __device__ bool persist_serve(const uint32_t (*T)[256], uint8_t *wflag, u64 *wou
             R4 = uni(req[w + 4]);
   const u64 total = R0 + R1 + R2 + R3 + R4;
   DevStatus *status = (DevStatus *)uni(req[offsetof(BulkArgs, status) / sizeof(u64)]);
+  const bool mig = uni(req[offsetof(PersistReq, mig_cells) / sizeof(u64)]) != 0;
   const u64 tag = (q + 1) << 32;
   bool worked = false;
   while (true) {
@@ -1184,8 +1232,10 @@ __device__ bool persist_serve(const uint32_t (*T)[256], uint8_t *wflag, u64 *wou
       for (int tries = 0; tries < 4; ++tries) {
         const u64 cnt = c & 0xFFFFFFFFull;
         if ((c >> 32) != q + 1 || cnt >= total) break;
+        // (migration blocks in runs of up to 16: each run pays two fences)
+        const u64 most = mig ? 16 : 4;
         u64 want = (total - cnt) >> 5;
-        want = want < 1 ? 1 : (want > 4 ? 4 : want);
+        want = want < 1 ? 1 : (want > most ? most : want);
         if (__hip_atomic_compare_exchange_strong(&dev[e].claim, &c, c + want, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
           t0 = cnt;
@@ -1233,7 +1283,9 @@ __device__ bool persist_serve(const uint32_t (*T)[256], uint8_t *wflag, u64 *wou
       // (their writes completed before their counters moved; the loads below
       // are issued after that was seen)
       wave_sync();
-      if (p == 0) {
+      if (p == 0 && mig) {
+        persist_migrate<LAYOUT>(T, mlds, req, r, seg);
+      } else if (p == 0) {
         for (u64 rr = r; rr < r + seg; ++rr) persist_copy_in<LAYOUT>(req, rr);
       } else if (p == 4) {
         for (u64 rr = r; rr < r + seg; ++rr) persist_copy_out<LAYOUT>(req, rr, R1 != 0);
@@ -1265,6 +1317,13 @@ __device__ bool persist_serve(const uint32_t (*T)[256], uint8_t *wflag, u64 *wou
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if ((nv & 0xFFFFFFFFull) == rp && p == kPersistPhases - 1) {
           // the last copy-out round: the request is complete
+          if (mig && !(__hip_atomic_load(&status->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrMigrate)) {
+            // the new table holds the live elements without tombstones (after
+            // an overflow the host migrates the old table, whose counts stay)
+            for (int kk = 0; kk < kCountSlots; ++kk)
+              dev_store(&status->slot[kk].used, dev_relaxed(&status->slot[kk].live));
+            wait_mem();
+          }
           u64 used = 0, live = 0;
           for (int kk = 0; kk < kCountSlots; ++kk) {
             used += dev_relaxed(&status->slot[kk].used);
@@ -1302,11 +1361,13 @@ __global__ void __launch_bounds__(256, 4) k_persist(const PersistCtl *ctl, const
     return;
   }
   const uint32_t nwb = blockDim.x >> 6;
-  // per wave: values (ROUND u64), staged keys (ROUND u64), flags, kinds (ROUND bytes each)
-  u64 *wout = (u64 *)dyn_lds + wave * ROUND;
-  u64 *skeys = (u64 *)dyn_lds + (nwb + wave) * ROUND;
-  uint8_t *wflag = dyn_lds + 2 * nwb * ROUND * 8 + wave * ROUND;
-  uint8_t *skinds = dyn_lds + 2 * nwb * ROUND * 8 + (nwb + wave) * ROUND;
+  // per wave (kPersistWaveLds bytes): values (ROUND u64), staged keys (ROUND
+  // u64), flags, kinds (ROUND bytes each); or the migration's state
+  unsigned char *mlds = dyn_lds + wave * kPersistWaveLds;
+  u64 *wout = (u64 *)mlds;
+  u64 *skeys = wout + ROUND;
+  uint8_t *wflag = (uint8_t *)(skeys + ROUND);
+  uint8_t *skinds = wflag + ROUND;
   const u64 gw = (u64)blockIdx.x * nwb + wave;
   const uint32_t g = blockIdx.x % kPersistGroups;
   const u64 *posted_word = &st->group[g].posted;
@@ -1366,7 +1427,7 @@ __global__ void __launch_bounds__(256, 4) k_persist(const PersistCtl *ctl, const
             if (lane == 0) s_q[wave] = q;
             wave_sync();
           }
-          worked |= persist_serve<LAYOUT>(T, wflag, wout, skeys, skinds, &s_req[wave][0], dev, done_ring, st, stop_word,
+          worked |= persist_serve<LAYOUT>(T, wflag, wout, skeys, skinds, mlds, &s_req[wave][0], dev, done_ring, st, stop_word,
                                           q, e, gw, rounds_since_check, stop_seen);
         }
       }
@@ -1580,7 +1641,7 @@ hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistR
                           PersistDone *done, PersistDev *dev, PersistState *st, uint64_t idle_ticks,
                           uint32_t grid, hipStream_t s) {
   if (grid < kPersistGroups || grid % kPersistGroups) return hipErrorInvalidValue;
-  const size_t lds = 4 * (size_t)ROUND * 18;
+  const size_t lds = 4 * kPersistWaveLds;
   hipLaunchKernelGGL(k_persist_arm, dim3(1), dim3(64), 0, s, st, ctl, (u64)grid * 4 - 1);
   hipError_t rc = hipGetLastError();
   if (rc != hipSuccess) return rc;

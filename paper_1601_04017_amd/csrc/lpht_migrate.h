@@ -46,12 +46,19 @@ __host__ __device__ constexpr size_t mig_wave_lds(uint32_t mb, uint32_t layout, 
           15) &
          ~(size_t)15;
 }
+// The scattering form keeps keys and values in registers: cell states, the
+// image, the cluster starts and each window cell's new slot (u16).
+__host__ __device__ constexpr size_t mig_wave_lds_scatter(uint32_t mb, uint32_t gamma) {
+  return ((size_t)mig_window(mb) * (4u + 1u + 2u) + (size_t)gamma * mig_window(mb) * 2u + 15) & ~(size_t)15;
+}
 constexpr int32_t kCellEmpty = -1, kCellTomb = -2, kCellFar = -3;  // window cell states
 
 
 // The window of block b (cells t = lane + 64 q, q < Q, of [b B - H, ...)),
-// wrapped modulo the old capacity (mask = capacity - 1).
-template <int LAYOUT, int Q>
+// wrapped modulo the old capacity (mask = capacity - 1).  COH: device-coherent
+// loads (agent-scope relaxed atomics), for a table that other wavefronts of
+// the same launch wrote.
+template <int LAYOUT, int Q, bool COH = false>
 __device__ __forceinline__ void mig_load_window(u64 (&nk)[Q], u64 (&nv)[Q], const void *old_cells, u64 mask,
                                                 u64 b) {
   constexpr uint32_t mb = 64 * Q - 2 * MIG_HALO;
@@ -61,10 +68,10 @@ __device__ __forceinline__ void mig_load_window(u64 (&nk)[Q], u64 (&nv)[Q], cons
   for (int q = 0; q < Q; ++q) {
     const u64 x = (u64)(wb + (long long)(lane + 64 * q)) & mask;
     if (LAYOUT == 0) {
-      nk[q] = ((const u64 *)old_cells)[x];
+      nk[q] = Cells<0>::word<COH>(old_cells, x);
       nv[q] = 0;
     } else {
-      const u64x2 c = ((const u64x2 *)old_cells)[x];
+      const u64x2 c = Cells<1>::cell<COH>(old_cells, x);
       nk[q] = c.x;
       nv[q] = c.y;
     }
@@ -73,8 +80,15 @@ __device__ __forceinline__ void mig_load_window(u64 (&nk)[Q], u64 (&nv)[Q], cons
 
 // Migrates block `blk` from its window (k, v) into the new table of
 // 2^(log2_old + g) cells; `base` is the wavefront's mig_wave_lds(B, LAYOUT,
-// 2^g) bytes of LDS.  Returns the number of elements written.
-template <int LAYOUT, int Q>
+// 2^g) bytes of LDS (SCATTER: mig_wave_lds_scatter(B, 2^g)).  Returns the
+// number of elements written.
+//   SCATTER: instead of gathering the owned image from keys and values kept
+//     in LDS, each lane stores its own elements that landed in the owned range
+//     from its registers and the empty owned cells are zeroed (less LDS, more
+//     wavefronts where LDS is short); nothing is written after an overflow.
+//   COH: the new cells are written with device-coherent stores (agent-scope
+//     relaxed atomics), for readers in the same launch.
+template <int LAYOUT, int Q, bool SCATTER = false, bool COH = false>
 __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)[Q], u64 blk, uint32_t log2_old,
                                                uint32_t g, const uint32_t (*T)[256], uint32_t crc_hi, uint32_t crc_lo,
                                                u64 mul, unsigned char *base, void *new_cells, bool &overflow) {
@@ -85,23 +99,27 @@ __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t gamma = 1u << g;  // 1 or 2
   const uint32_t IW = gamma * W;   // image slots
-  u64 *wkey = (u64 *)base;
-  u64 *wval = wkey + W;  // KV64 only
-  int32_t *wnh = (int32_t *)(wkey + (LAYOUT == 0 ? W : 2 * W));
+  u64 *wkey = (u64 *)base;  // gather only
+  u64 *wval = wkey + W;     // gather, KV64 only
+  int32_t *wnh = (int32_t *)(SCATTER ? base : (unsigned char *)(wkey + (LAYOUT == 0 ? W : 2 * W)));
   uint16_t *img = (uint16_t *)(wnh + W);
-  uint16_t *starts = img + IW;  // cluster starts of [lo, hi)
+  uint16_t *starts = img + IW;        // cluster starts of [lo, hi)
+  uint16_t *newpos = starts + W / 2;  // scatter only: image slot each element went to
   const u64 cap = 1ull << log2_old, mask = cap - 1;
   const uint32_t log2_new = log2_old + g;
   long long moved = 0;
   const long long d = (long long)(blk * mb);
   const long long wbase = d - H;  // unwrapped old index of window cell 0
-  u64 emp[Q];  // ballot of empty window cells, 64 per word
+  u64 emp[Q];         // ballot of empty window cells, 64 per word
+  uint32_t elem = 0;  // bit q: this lane's cell of row q holds an element
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const uint32_t t = lane + 64 * q;
     const u64 key = LAYOUT == 0 ? (k[q] & 0xFFFFFFFFull) : k[q];
-    wkey[t] = k[q];
-    if (LAYOUT == 1) wval[t] = v[q];
+    if (!SCATTER) {
+      wkey[t] = k[q];
+      if (LAYOUT == 1) wval[t] = v[q];
+    }
     int32_t rel = key == kEmpty ? kCellEmpty : kCellTomb;
     if (key != kEmpty && key != kTomb) {
       // new home, unwrapped consistently with this cell's old position
@@ -112,6 +130,7 @@ __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)
       const long long nh = (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
       const long long r = nh - (long long)gamma * wbase;  // image slot of the home
       rel = (r < 0 || r >= (long long)IW) ? kCellFar : (int32_t)r;
+      elem |= 1u << q;
     }
     wnh[t] = rel;
     emp[q] = __ballot(key == kEmpty);
@@ -183,6 +202,7 @@ __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)
         if (p >= (int)IW) return 2;
         if (p - tb < 64) taken |= 1ull << (p - tb);
         img[p] = (uint16_t)u;
+        if (SCATTER) newpos[u] = (uint16_t)p;
         return 0;
       };
       // the cells' states are loaded four ahead of their placement
@@ -204,24 +224,52 @@ __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)
         c3 = n3;
       }
     }
-    if (bad) overflow = true;
-    wave_sync();
-    // the owned new cells [g*d, g*(d+B)) = image slots [g*H, g*(H+B))
     const u64 dst0 = (u64)d * gamma;
-    const uint32_t n_out = gamma * mb;
-    for (uint32_t t = lane; t < n_out; t += 64) {
-      const uint16_t ix = img[gamma * H + t];
+    const uint32_t o0 = gamma * H, n_out = gamma * mb;  // the owned image slots [o0, o0 + n_out)
+    auto put = [&](u64 x, u64 kw, u64 vw) {
       if (LAYOUT == 0) {
-        ((u64 *)new_cells)[dst0 + t] = ix == kImgEmpty ? 0ull : wkey[ix];
+        if (COH)
+          __hip_atomic_store((u64 *)new_cells + x, kw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          ((u64 *)new_cells)[x] = kw;
+      } else if (COH) {
+        __hip_atomic_store((u64 *)new_cells + 2 * x, kw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store((u64 *)new_cells + 2 * x + 1, vw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
-        u64x2 c = {0ull, 0ull};
-        if (ix != kImgEmpty) {
-          c.x = wkey[ix];
-          c.y = wval[ix];
-        }
-        ((u64x2 *)new_cells)[dst0 + t] = c;
+        ((u64x2 *)new_cells)[x] = u64x2{kw, vw};
       }
-      moved += (ix != kImgEmpty);
+    };
+    if (SCATTER) {
+      if (__any(bad)) {
+        overflow = true;  // the caller redoes the move; nothing is written
+      } else {
+        wave_sync();
+        // the lane's own elements placed in the owned range, then zeros in
+        // the owned cells left empty
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int t = (int)lane + 64 * q;
+          if (!((elem >> q) & 1u) || t < lo || t >= hi) continue;
+          const uint32_t o = (uint32_t)newpos[t] - o0;  // wraps when below the owned range
+          if (o >= n_out) continue;
+          put(dst0 + o, k[q], v[q]);
+          ++moved;
+        }
+        for (uint32_t t = lane; t < n_out; t += 64)
+          if (img[o0 + t] == kImgEmpty) put(dst0 + t, 0ull, 0ull);
+      }
+    } else {
+      if (bad) overflow = true;
+      wave_sync();
+      // the owned new cells [g*d, g*(d+B)) = image slots [g*H, g*(H+B))
+      for (uint32_t t = lane; t < n_out; t += 64) {
+        const uint16_t ix = img[o0 + t];
+        const bool e = ix == kImgEmpty;
+        const uint32_t j = e ? 0u : ix;
+        const u64 kw = wkey[j], vw = LAYOUT == 1 ? wval[j] : 0ull;
+        put(dst0 + t, e ? 0ull : kw, e ? 0ull : vw);
+        moved += !e;
+      }
     }
   }
   wave_sync();

@@ -60,6 +60,11 @@ struct Req {
   bool done = false;
   uint64_t need = 0;  // bytes accounted by admission (staging and growth)
   uint64_t arena_off = ~0ull;  // resident mode: the request's staging in the arena
+  // resident mode, a migration entry of the server's own: its table grows
+  // into mig_cells before `waiting` is posted
+  bool mig = false;
+  Req *waiting = nullptr;
+  void *mig_cells = nullptr;
 };
 
 struct Group {
@@ -123,6 +128,7 @@ struct lpht_server {
   uint64_t idle_ticks = 0;         // kIdleExitMs in ticks of the device's constant clock
   uint64_t persist_launches = 0;
   bool persist_failed = false;     // a bounded wait in the kernel expired
+
 };
 
 namespace {
@@ -422,6 +428,8 @@ void persist_post(lpht_server *S, Req *q) {
   R.rounds[0] = copy_rounds;
   for (int k = 0; k < 3; ++k) R.rounds[k + 1] = q->count[k] ? (n + kRound - 1) / kRound : 0;
   R.rounds[4] = copy_rounds;
+  R.mig_cells = nullptr;
+  R.mig_log2c = 0;
   __atomic_store_n(&R.seq, qn + 1, __ATOMIC_RELEASE);
   t->mods_since_exact++;
   S->pentry[e] = q;
@@ -430,6 +438,105 @@ void persist_post(lpht_server *S, Req *q) {
   S->next_q = qn + 1;
   if (S->inflight_reqs++ == 0) S->busy_since = now_us();
   __atomic_store_n(&S->pctl->posted, qn + 1, __ATOMIC_RELEASE);
+}
+
+// Smallest capacity the resident kernel migrates itself (its migration
+// window spans 512 old cells).
+constexpr uint32_t kPersistMigMinLog2 = 10;
+
+// Posts a migration entry that doubles table `ti` inside the running resident
+// kernel (Sec. 5.3.2: the serving wavefronts are the helpers, and requests on
+// other tables keep being served meanwhile); `q` is posted once it is done.
+// False when the new table cannot be allocated.
+bool persist_post_migration(lpht_server *S, uint32_t ti, Req *q) {
+  lpht_table *t = S->tables[ti];
+  const size_t nb = (size_t)cell_bytes(t->cfg.layout) << (t->log2c + 1);
+  void *nc = dev_alloc(t, nb, S->streams[0]);
+  if (!nc) return false;
+  Req *m = new (std::nothrow) Req();
+  if (!m) {
+    dev_free(t, nc, nb, S->streams[0]);
+    return false;
+  }
+  m->mig = true;
+  m->waiting = q;
+  m->mig_cells = nc;
+  m->r.table = ti;
+  const uint64_t qn = S->next_q;
+  const uint32_t e = (uint32_t)(qn % kPersistRing);
+  PersistReq &R = S->pring[e];
+  BulkArgs a = make_args(t);
+  a.n = 0;
+  R.a = a;
+  R.hkeys = nullptr;
+  R.hkinds = nullptr;
+  R.hvals = nullptr;
+  R.hflags = nullptr;
+  R.rounds[0] = (1ull << t->log2c) / kPersistMigBlock;
+  R.rounds[1] = R.rounds[2] = R.rounds[3] = 0;
+  R.rounds[4] = 1;
+  R.mig_cells = nc;
+  R.mig_log2c = t->log2c + 1;
+  __atomic_store_n(&R.seq, qn + 1, __ATOMIC_RELEASE);
+  t->mods_since_exact++;
+  S->pentry[e] = m;
+  S->next_q = qn + 1;
+  if (S->inflight_reqs++ == 0) S->busy_since = now_us();
+  __atomic_store_n(&S->pctl->posted, qn + 1, __ATOMIC_RELEASE);
+  return true;
+}
+
+// Whether the growth rule may fire before the request's increments: an upper
+// bound of `used` (the exact count after the last completion plus insertions
+// made on the table outside the server since, `pending`); grow_before_batch
+// then decides exactly.
+bool needs_growth(const lpht_server *S, const Req *q) {
+  const lpht_table *t = S->tables[q->r.table];
+  return q->count[1] && !within_fill(t, t->known_used + t->pending + q->count[1], 1ull << t->log2c);
+}
+
+// A request whose table may have to grow first: a single doubling of a large
+// enough table whose counts are exact becomes a migration entry for the
+// running kernel; every other case waits for the host path (stop the kernel,
+// migrate, relaunch).
+void persist_grow_then_post(lpht_server *S, Req *q) {
+  lpht_table *t = S->tables[q->r.table];
+  if (!S->persist_failed && t->pending == 0 && t->mods_since_exact == 0 && t->log2c >= kPersistMigMinLog2) {
+    const int kind = growth_kind(t, q->count[1]);
+    if (kind == 0) {
+      persist_post(S, q);
+      return;
+    }
+    if (kind == 1 && persist_post_migration(S, q->r.table, q)) return;
+  }
+  S->grow_wait.push_back(q);
+}
+
+// A completed migration entry: the table takes the new cells (or, after an
+// overflow, the host migrates it), then the waiting request goes on.
+void persist_migration_done(lpht_server *S, Req *m, uint32_t e) {
+  lpht_table *t = S->tables[m->r.table];
+  const size_t cb = cell_bytes(t->cfg.layout);
+  const uint64_t err = S->pdone[e].err;
+  Req *q = m->waiting;
+  // (frees on streams[0] reach the pool only once the resident kernel,
+  // queued before them, has exited)
+  if ((err & kErrMigrate) || S->persist_failed) {
+    dev_free(t, m->mig_cells, cb << (t->log2c + 1), S->streams[0]);
+    S->st.kernel_growth_fallbacks++;
+    S->grow_wait.push_back(q);
+  } else {
+    // the old table is no longer read: its last reader was this entry
+    dev_free(t, t->cells, cb << t->log2c, S->streams[0]);
+    t->cells = m->mig_cells;
+    t->stats.migrations++;
+    t->stats.resizes++;
+    t->stats.cells_migrated += 1ull << t->log2c;
+    t->log2c += 1;
+    S->st.kernel_growths++;
+    persist_grow_then_post(S, q);
+  }
+  delete m;
 }
 
 // Retires requests whose completion the kernel has published.
@@ -442,6 +549,17 @@ bool persist_retire(lpht_server *S) {
     if (!q) continue;
     if (__atomic_load_n(&S->pdone[e].seq, __ATOMIC_ACQUIRE) != qn + 1) continue;
     lpht_table *T = S->tables[q->r.table];
+    if (q->mig) {
+      T->known_used = S->pdone[e].used;
+      T->known_live = S->pdone[e].live;
+      T->pending = 0;
+      T->mods_since_exact = 0;
+      S->pentry[e] = nullptr;
+      if (--S->inflight_reqs == 0) S->st.busy_us += now_us() - S->busy_since;
+      persist_migration_done(S, q, e);
+      any = true;
+      continue;
+    }
     if (S->persist_failed && q->c.status == LPHT_OK) q->c.status = LPHT_ERR_DEVICE;
     T->known_used = S->pdone[e].used;
     T->known_live = S->pdone[e].live;
@@ -465,15 +583,6 @@ bool persist_retire(lpht_server *S) {
     S->cv_done.notify_all();
   }
   return any;
-}
-
-// Whether the growth rule may fire before the request's increments: an upper
-// bound of `used` (the exact count after the last completion plus insertions
-// made on the table outside the server since, `pending`); grow_before_batch
-// then decides exactly.
-bool needs_growth(const lpht_server *S, const Req *q) {
-  const lpht_table *t = S->tables[q->r.table];
-  return q->count[1] && !within_fill(t, t->known_used + t->pending + q->count[1], 1ull << t->log2c);
 }
 
 // One pass of the worker in persistent mode.
@@ -515,11 +624,10 @@ bool persist_step(lpht_server *S, std::vector<Req *> &admitted) {
   admitted.clear();
   admit(S, admitted);
   for (Req *q : admitted) {
-    if (needs_growth(S, q)) {
-      S->grow_wait.push_back(q);
-    } else {
+    if (needs_growth(S, q))
+      persist_grow_then_post(S, q);
+    else
       persist_post(S, q);
-    }
     progressed = true;
   }
   if (!S->running && S->oldest_q < S->next_q && S->grow_wait.empty()) {

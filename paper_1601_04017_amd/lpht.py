@@ -767,6 +767,8 @@ class lpht_server_stats(ctypes.Structure):
         ("peak_hbm_bytes", ctypes.c_uint64),
         ("admission_waits", ctypes.c_uint64),
         ("busy_us", ctypes.c_double),
+        ("kernel_growths", ctypes.c_uint64),
+        ("kernel_growth_fallbacks", ctypes.c_uint64),
     ]
 
 

@@ -198,3 +198,52 @@ def test_serving_persistent_rejects_pageable_buffers():
     rc = lpht.load().lpht_server_submit(srv._h, ctypes.byref(req), ctypes.byref(t))
     srv.close()
     assert rc == lpht.ERR_INVALID
+
+
+@pytest.mark.parametrize("layout_name", ["KV64", "PACKED32"])
+def test_serving_persistent_grows_inside_the_kernel(layout_name):
+    # increments over a wide key range make tables of 2^10..2^13 cells double
+    # several times while the resident kernel keeps serving: single doublings
+    # become migration entries run by the kernel's own wavefronts (block
+    # migration, Lemma 1); results, counts, capacities and every table's
+    # occupancy and run key sets must equal the oracle's replay
+    from paper_1601_04017_amd import lpht
+    layout = getattr(oracle, layout_name)
+    caps = [10, 11, 12, 13]
+    reqs = _trace(len(caps), 90, seed=31, lo=256, hi=6000, universe=400000, mix=(0.2, 0.7, 0.1))
+    if layout == oracle.PACKED32:
+        reqs = [(t, k.astype(np.uint32) | np.uint32(2), kd) for t, k, kd in reqs]
+    srv = lpht.Server(caps, layout=getattr(lpht, layout_name), mode=lpht.SERVE_PERSISTENT, max_inflight=32,
+                      streams=1)
+    arr, outs, keep = srv.make_requests(reqs)
+    done, _ = srv.run_closed_loop(arr, 16)
+    kdt = np.uint32 if layout == oracle.PACKED32 else np.uint64
+    res = [(o[0].numpy().view(kdt).astype(np.uint64), o[1].numpy().copy()) for o in outs]
+    cells = [cells_host(srv.table(i)) for i in range(len(caps))]
+    counts = [srv.table(i).count() for i in range(len(caps))]
+    capsz = [srv.table(i).capacity for i in range(len(caps))]
+    stats = srv.stats()
+    srv.close()
+    assert all(d.status == 0 for d in done)
+    orcs = [oracle.OracleTable(layout, c, auto_grow=True) for c in caps]
+    ref = []
+    for tab, keys, kinds in reqs:
+        o = orcs[tab]
+        m0, m1, m2 = kinds == 0, kinds == 1, kinds == 2
+        vals = np.zeros(keys.size, np.uint64)
+        flags = np.zeros(keys.size, np.uint8)
+        v, f = o.find(keys[m0])
+        vals[m0], flags[m0] = v, f
+        flags[m1] = o.insert_or_update(keys[m1], None, oracle.ADD)
+        flags[m2] = o.erase(keys[m2])
+        ref.append((vals, flags))
+    _check_same(reqs, res, ref)
+    doublings = 0
+    for i, o in enumerate(orcs):
+        assert counts[i] == o.counts()
+        assert capsz[i] == o.capacity
+        H.assert_same_table_modulo_run_order(cells[i], o.cells(), layout)
+        doublings += (capsz[i].bit_length() - 1) - caps[i]
+    assert stats["kernel_growth_fallbacks"] == 0, stats
+    assert stats["kernel_growths"] >= 4, (stats, doublings)
+    assert stats["kernel_growths"] <= doublings, (stats, doublings)
