@@ -203,7 +203,7 @@ SUITE_PARTS = ("ceilings", "packed32", "fill_sweep", "growing", "deletion", "bul
                "serving")
 
 
-def run_suite(dev, reps=3, parts=SUITE_PARTS):
+def run_suite(dev, reps=3, parts=SUITE_PARTS, serving_requests=2000):
     """The other workloads, each timed on the GPU (mean of `reps` after one
     warm-up): packed 2^21 table; the fill sweep of the 2^28 table; growing
     from 4096 cells in batches of 2^20; the deletion test (sliding window of
@@ -249,7 +249,7 @@ def run_suite(dev, reps=3, parts=SUITE_PARTS):
     if "zipf" in parts:
         out["zipf_increment"] = _suite_zipf(up, stream, reps)
     if "serving" in parts:
-        out["serving"] = run_serving()
+        out["serving"] = run_serving(nreq=serving_requests)
     return out
 
 
@@ -756,6 +756,8 @@ def main():
     ap.add_argument("--suite", action="store_true", help="also measure the other workloads")
     ap.add_argument("--parts", default=",".join(SUITE_PARTS), help="suite parts to run")
     ap.add_argument("--suite-only", action="store_true", help="skip the headline step")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests of the suite's serving trace (fewer under a tracing profiler)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape instead of the autotuner's")
     args = ap.parse_args()
@@ -785,7 +787,8 @@ def main():
                      "seconds": round(time.perf_counter() - t0, 2)}
     if args.suite_only:
         print(json.dumps({"tuning": tune_info,
-                          "suite": run_suite(dev, parts=tuple(args.parts.split(",")))}), flush=True)
+                          "suite": run_suite(dev, parts=tuple(args.parts.split(",")),
+                                                           serving_requests=args.serving_requests)}), flush=True)
         return
 
     log("generating inputs")
@@ -967,7 +970,8 @@ def main():
         del d_keys, d_vals, d_hit, d_miss, d_zipf
         t1.close()
         t2.close()
-        out["suite"] = run_suite(dev, parts=tuple(args.parts.split(",")))
+        out["suite"] = run_suite(dev, parts=tuple(args.parts.split(",")),
+                                                           serving_requests=args.serving_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 thread pinned)")
         out["cpu_baseline"] = cpu_baseline(keys, miss, zipf)
