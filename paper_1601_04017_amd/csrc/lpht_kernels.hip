@@ -252,6 +252,69 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
     start();
   };
 
+  // Single-table finds one lane per operation: a lane probes both of its
+  // operations of the round together, so two random loads are in flight per
+  // lane instead of one after the other.
+  constexpr bool kPairFind = OP == OP_FIND && G == 1 && !RESIDENT;
+  const bool pair = kPairFind && shome && !A.kinds;
+  if (pair) {
+    static_assert(ROUND == 128, "two operations per lane");
+    u64 key[2], pos[2], val[2] = {0, 0}, steps[2] = {0, 0};
+    bool act[2];
+    uint8_t fl[2] = {0, 0};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t loc = lane + 64 * q;
+      act[q] = loc < cnt;
+      key[q] = act[q] ? skeys[loc] : 0;
+      pos[q] = act[q] ? shome[loc] : 0;
+      if (act[q] && (key[q] == kEmpty || key[q] == kTomb)) {
+        err |= kErrReserved;
+        fl[q] = 0xFE;
+        act[q] = false;
+      }
+    }
+    while (act[0] || act[1]) {
+      u64 ck[2], cv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        ck[q] = kEmpty;
+        cv[q] = 0;
+        if (act[q]) {
+          if (LAYOUT == 0) {
+            const u64 w = Cells<0>::word<false>(A.cells, pos[q]);
+            ck[q] = Cells<0>::key_of(w);
+            cv[q] = Cells<0>::val_of(w);
+          } else {
+            const u64x2 c = Cells<1>::cell<false>(A.cells, pos[q]);
+            ck[q] = c.x;
+            cv[q] = c.y;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (!act[q]) continue;
+        if (ck[q] == key[q]) {
+          fl[q] = 1;
+          val[q] = cv[q];
+          act[q] = false;
+        } else if (ck[q] == kEmpty || ++steps[q] > mask) {
+          act[q] = false;  // absent (or every cell probed)
+        } else {
+          pos[q] = (pos[q] + 1) & mask;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t loc = lane + 64 * q;
+      if (loc < cnt) {
+        wflag[loc] = fl[q];
+        wout[loc] = val[q];
+      }
+    }
+  } else {
   start();
   while (__any(active)) {
     if (active) {
@@ -419,6 +482,7 @@ __device__ __forceinline__ void bulk_round(const BulkArgs &A, const uint32_t (*T
         }
       }
     }
+  }
   }
   // write the round's results as whole lines
   wave_sync();
