@@ -120,19 +120,6 @@ __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)
       wkey[t] = k[q];
       if (LAYOUT == 1) wval[t] = v[q];
     }
-    int32_t rel = key == kEmpty ? kCellEmpty : kCellTomb;
-    if (key != kEmpty && key != kTomb) {
-      // new home, unwrapped consistently with this cell's old position
-      const u64 hn = home_of<LAYOUT>(T, key, crc_hi, crc_lo, mul, log2_new);
-      const u64 oh = hn >> g;
-      const long long x = wbase + (long long)t;
-      const u64 delta = ((u64)x - oh) & mask;
-      const long long nh = (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
-      const long long r = nh - (long long)gamma * wbase;  // image slot of the home
-      rel = (r < 0 || r >= (long long)IW) ? kCellFar : (int32_t)r;
-      elem |= 1u << q;
-    }
-    wnh[t] = rel;
     emp[q] = __ballot(key == kEmpty);
   }
   for (uint32_t t = lane; t < IW / 2; t += 64) ((uint32_t *)img)[t] = 0xFFFFFFFFu;
@@ -158,6 +145,29 @@ __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)
     }
     if (first < 0) skip = true;
     hi = first;
+  }
+  // each cell's state; only the cells of [lo, hi) are walked, so only their
+  // keys are hashed (the halo rows outside it are mostly skipped whole)
+  if (!skip) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (64 * q + 63 < lo || 64 * q >= hi) continue;  // the row lies outside [lo, hi)
+      const int t = (int)lane + 64 * q;
+      const u64 key = LAYOUT == 0 ? (k[q] & 0xFFFFFFFFull) : k[q];
+      int32_t rel = key == kEmpty ? kCellEmpty : kCellTomb;
+      if (key != kEmpty && key != kTomb && t >= lo && t < hi) {
+        // new home, unwrapped consistently with this cell's old position
+        const u64 hn = home_of<LAYOUT>(T, key, crc_hi, crc_lo, mul, log2_new);
+        const u64 oh = hn >> g;
+        const long long x = wbase + (long long)t;
+        const u64 delta = ((u64)x - oh) & mask;
+        const long long nh = (long long)gamma * (x - (long long)delta) + (long long)(hn & (gamma - 1));
+        const long long r = nh - (long long)gamma * wbase;  // image slot of the home
+        rel = (r < 0 || r >= (long long)IW) ? kCellFar : (int32_t)r;
+        elem |= 1u << q;
+      }
+      wnh[t] = rel;
+    }
   }
   wave_sync();
   if (skip) {
