@@ -1738,11 +1738,24 @@ hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_ce
   const uint32_t g = log2_new - log2_old;
   const uint32_t mb = cfg.migrate_block;
   // static LDS of the kernel (CRC tables and counters) plus one region per
-  // wavefront; as many wavefronts (up to 4) as fit the 64 KiB a workgroup may
-  // allocate
+  // wavefront
   const size_t per_wave = g <= 1 ? mig_wave_lds(mb, layout, 1u << g) : ~(size_t)0 / 8;
   const size_t fixed = 8192 + 64;
-  const uint32_t wpb = per_wave > 65536 - fixed ? 0u : (uint32_t)std::min<size_t>(4, (65536 - fixed) / per_wave);
+  // wavefronts per workgroup (up to 4, within the 64 KiB a workgroup may
+  // allocate) that put the most wavefronts on a compute unit's 160 KiB: the
+  // migration is bound by the latency of each block's cluster walk
+  uint32_t wpb = 0;
+  {
+    size_t best = 0;
+    for (uint32_t w = 1; w <= 4; ++w) {
+      if (per_wave > (65536 - fixed) / w) break;
+      const size_t resident = w * ((160 * 1024) / (w * per_wave + fixed));
+      if (resident > best) {
+        best = resident;
+        wpb = w;
+      }
+    }
+  }
   const bool lds_path = !old_is_full && g <= 1 && (mb == 256 || mb == 512 || mb == 1024) && cap >= mb &&
                         wpb >= 1;
   const uint32_t sgrid = grid_for(cap, LaunchCfg{256, 1, cfg.blocks_per_cu, cfg.num_cus, mb, 0});

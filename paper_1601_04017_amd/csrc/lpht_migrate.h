@@ -38,18 +38,19 @@ constexpr uint16_t kImgEmpty = 0xFFFF;
 __host__ __device__ constexpr uint32_t mig_window(uint32_t mb) { return mb + 2 * MIG_HALO; }
 
 // LDS of one wavefront: window keys and values (u64 each; PACKED32 keeps the
-// word in the key array), each window cell's state (i32: the new home's image
-// slot, or one of the negative codes below), the image (u16 per new cell) and
-// the list of cluster starts (u16 per start, at most half the window).
+// word in the key array), each window cell's state (i16: the new home's image
+// slot, below 2 * 1280, or one of the negative codes below), the image (u16
+// per new cell) and the list of cluster starts (u16 per start, at most half
+// the window).
 __host__ __device__ constexpr size_t mig_wave_lds(uint32_t mb, uint32_t layout, uint32_t gamma) {
-  return ((size_t)mig_window(mb) * ((layout == 0 ? 8u : 16u) + 4u + 1u) + (size_t)gamma * mig_window(mb) * 2u +
+  return ((size_t)mig_window(mb) * ((layout == 0 ? 8u : 16u) + 2u + 1u) + (size_t)gamma * mig_window(mb) * 2u +
           15) &
          ~(size_t)15;
 }
 // The scattering form keeps keys and values in registers: cell states, the
 // image, the cluster starts and each window cell's new slot (u16).
 __host__ __device__ constexpr size_t mig_wave_lds_scatter(uint32_t mb, uint32_t gamma) {
-  return ((size_t)mig_window(mb) * (4u + 1u + 2u) + (size_t)gamma * mig_window(mb) * 2u + 15) & ~(size_t)15;
+  return ((size_t)mig_window(mb) * (2u + 1u + 2u) + (size_t)gamma * mig_window(mb) * 2u + 15) & ~(size_t)15;
 }
 constexpr int32_t kCellEmpty = -1, kCellTomb = -2, kCellFar = -3;  // window cell states
 
@@ -101,7 +102,8 @@ __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)
   const uint32_t IW = gamma * W;   // image slots
   u64 *wkey = (u64 *)base;  // gather only
   u64 *wval = wkey + W;     // gather, KV64 only
-  int32_t *wnh = (int32_t *)(SCATTER ? base : (unsigned char *)(wkey + (LAYOUT == 0 ? W : 2 * W)));
+  static_assert(2 * 64 * Q < 32768, "image slots fit the 16-bit cell states");
+  int16_t *wnh = (int16_t *)(SCATTER ? base : (unsigned char *)(wkey + (LAYOUT == 0 ? W : 2 * W)));
   uint16_t *img = (uint16_t *)(wnh + W);
   uint16_t *starts = img + IW;        // cluster starts of [lo, hi)
   uint16_t *newpos = starts + W / 2;  // scatter only: image slot each element went to
@@ -166,7 +168,7 @@ __device__ __forceinline__ long long mig_block(const u64 (&k)[Q], const u64 (&v)
         rel = (r < 0 || r >= (long long)IW) ? kCellFar : (int32_t)r;
         elem |= 1u << q;
       }
-      wnh[t] = rel;
+      wnh[t] = (int16_t)rel;
     }
   }
   wave_sync();
