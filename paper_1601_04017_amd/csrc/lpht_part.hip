@@ -52,7 +52,7 @@ namespace lpht {
 namespace {
 
 constexpr uint32_t kBits1 = 8;          // first-level buckets: 256
-constexpr uint32_t kMaxBits = 12;       // at most 4096 buckets in all
+constexpr uint32_t kMaxBits = 12;       // at most 4096 buckets in all (a bucket fits in 12 bits)
 constexpr uint32_t kCountWG = 512;      // workgroups of the count and scatter passes
 constexpr uint32_t kCountThreads = 512;
 constexpr uint32_t kApplyThreads = 1024;
@@ -76,6 +76,9 @@ struct Level {
   uint64_t *btot;        // [nb + 1]: totals (zeroed), then bucket starts; btot[nb] = elements
   uint32_t *hist;        // [nwg][nb]: this workgroup's offset inside each bucket
   uint32_t *items;       // [nb + 1] (second level only): first work item of each bucket
+  // (second level only) [items + 1]: first element of each work item, bit 63
+  // set when the item is its bucket's only one; the last entry is the total
+  uint64_t *istart;
 };
 
 struct PartK {
@@ -93,6 +96,12 @@ size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 template <int L>
 __device__ __forceinline__ u64 part_key(const void *p, u64 i) {
   return L == 0 ? (u64)((const uint32_t *)p)[i] : ((const u64 *)p)[i];
+}
+
+template <int L>
+__device__ __forceinline__ u64 part_key_nt(const void *p, u64 i) {
+  return L == 0 ? (u64)__builtin_nontemporal_load((const uint32_t *)p + i)
+                : __builtin_nontemporal_load((const u64 *)p + i);
 }
 
 template <int L>
@@ -171,21 +180,30 @@ __global__ void __launch_bounds__(kCountThreads) k_part_count(PartK k, uint32_t 
   const u64 lo = (u64)blockIdx.x * k.chunk;
   const u64 hi = lo + k.chunk < n ? lo + k.chunk : n;
   uint32_t err = 0;
-  // kUnroll independent loads per lane before any is used: enough bytes in
-  // flight to cover the memory latency
-  for (u64 base = lo; base < hi; base += (u64)blockDim.x * kUnroll) {
-    u64 key[kUnroll];
+  // kUnroll independent loads per lane before any is used, and the next
+  // tile's loads issued before this tile is counted: enough bytes in flight
+  // to cover the memory latency
+  const u64 step = (u64)blockDim.x * kUnroll;
+  u64 key[kUnroll];
+  auto load = [&](u64 base) {
 #pragma unroll
     for (uint32_t j = 0; j < kUnroll; ++j) {
       const u64 i = base + (u64)j * blockDim.x + threadIdx.x;
       key[j] = i < hi ? part_key<L>(V.skeys, i) : 0;
     }
+  };
+  if (lo < hi) load(lo);
+  for (u64 base = lo; base < hi; base += step) {
+    u64 ck[kUnroll];
+#pragma unroll
+    for (uint32_t j = 0; j < kUnroll; ++j) ck[j] = key[j];
+    if (base + step < hi) load(base + step);
 #pragma unroll
     for (uint32_t j = 0; j < kUnroll; ++j) {
       const u64 i = base + (u64)j * blockDim.x + threadIdx.x;
       bool act = i < hi;
       if (act && lv == 0) {
-        if (key[j] == kEmpty || key[j] == kTomb) {
+        if (ck[j] == kEmpty || ck[j] == kTomb) {
           err |= kErrReserved;
           if (A.flags) A.flags[i] = 0xFE;
           act = false;
@@ -193,7 +211,7 @@ __global__ void __launch_bounds__(kCountThreads) k_part_count(PartK k, uint32_t 
           A.flags[i] = 0;
         }
       }
-      const uint32_t b = act ? (uint32_t)(hash_of<L>(T, key[j], A.crc_hi, A.crc_lo, A.mul) >> (64 - V.bits)) : 0;
+      const uint32_t b = act ? (uint32_t)(hash_of<L>(T, ck[j], A.crc_hi, A.crc_lo, A.mul) >> (64 - V.bits)) : 0;
       for (int r = 0; r < kAggRounds; ++r) {
         u64 lt = 0;
         uint32_t ll = 0;
@@ -238,7 +256,8 @@ __device__ __forceinline__ u64 block_scan_1024(u64 v, u64 *s_w, u64 *total) {
 }
 
 // One workgroup of 1024 threads, up to eight buckets per thread: bucket starts
-// and (with V.items) the first work item of each bucket.
+// and (with V.items) the first work item of each bucket and each item's
+// range.
 __global__ void __launch_bounds__(1024) k_part_scan(PartK k, uint32_t lv) {
   __shared__ u64 s_w[16];
   __shared__ u64 s_tot;
@@ -265,69 +284,156 @@ __global__ void __launch_bounds__(1024) k_part_scan(PartK k, uint32_t lv) {
     const uint32_t b = b0 + j;
     if (b < V.nb) {
       V.btot[b] = e;
-      if (V.items) V.items[b] = (uint32_t)it;
+      const u64 ni = (tot[j] + kItemOps - 1) / kItemOps;
+      if (V.items) {
+        V.items[b] = (uint32_t)it;
+        for (u64 q = 0; q < ni; ++q) V.istart[it + q] = (e + q * kItemOps) | (ni == 1 ? 1ull << 63 : 0);
+      }
       e += tot[j];
-      it += (tot[j] + kItemOps - 1) / kItemOps;
+      it += ni;
     }
   }
   if (threadIdx.x == 0) {
     V.btot[V.nb] = etotal;
-    if (V.items) V.items[V.nb] = (uint32_t)itotal;
+    if (V.items) {
+      V.items[V.nb] = (uint32_t)itotal;
+      V.istart[itotal] = etotal;
+    }
   }
 }
 
-template <int L>
-__global__ void __launch_bounds__(kCountThreads) k_part_scatter(PartK k, uint32_t lv) {
+// Scatter pass of level LV.  VALS, IDX: the level moves values and operation
+// indices along with the keys.  Keys are read once, by non-temporal loads, so
+// that L2 keeps the lines the stores are still filling.
+template <int L, bool VALS, bool IDX, int LV>
+__global__ void __launch_bounds__(kCountThreads) k_part_scatter(PartK k) {
   __shared__ uint32_t T[8][256];
-  __shared__ u64 cur[1u << kMaxBits];
+  // next free position of each bucket in this share (positions are below
+  // 2^32: calls of 2^32 - 1 or more operations are not partitioned)
+  __shared__ uint32_t cur[1u << kMaxBits];
   crc_tables_build(T);
-  const Level &V = k.L[lv];
+  const Level &V = k.L[LV];
   const BulkArgs &A = k.A;
-  const u64 n = lv == 0 ? A.n : k.L[0].btot[k.L[0].nb];
+  const u64 n = LV == 0 ? A.n : k.L[0].btot[k.L[0].nb];
   const u64 lo = (u64)blockIdx.x * k.chunk;
   const u64 hi = lo + k.chunk < n ? lo + k.chunk : n;
+  const uint32_t lane = threadIdx.x & 63;
+  // elements per lane and tile: where two tiles' loads are held with values
+  // or indices moved too, half as many keep the occupancy
+  constexpr uint32_t U = (LV == 1 && (VALS || IDX)) ? kUnroll / 2 : kUnroll;
   // only the buckets this share touched hold a valid reservation; the others
   // are never used below
-  for (uint32_t b = threadIdx.x; b < V.nb; b += blockDim.x) cur[b] = V.btot[b] + V.hist[(u64)blockIdx.x * V.nb + b];
+  for (uint32_t b = threadIdx.x; b < V.nb; b += blockDim.x)
+    cur[b] = (uint32_t)(V.btot[b] + V.hist[(u64)blockIdx.x * V.nb + b]);
   __syncthreads();
-  for (u64 base = lo; base < hi; base += (u64)blockDim.x * kUnroll) {
-    u64 key[kUnroll], val[kUnroll];
-    uint32_t idx[kUnroll];
+  const u64 step = (u64)blockDim.x * U;
+  u64 key[U], val[U];
+  uint32_t idx[U];
+  auto load = [&](u64 base) {
 #pragma unroll
-    for (uint32_t j = 0; j < kUnroll; ++j) {
+    for (uint32_t j = 0; j < U; ++j) {
       const u64 i = base + (u64)j * blockDim.x + threadIdx.x;
       const bool in = i < hi;
-      key[j] = in ? part_key<L>(V.skeys, i) : 0;
-      val[j] = in && V.dvals ? part_key<L>(V.svals, i) : 0;
-      idx[j] = in && V.didx ? (V.sidx ? V.sidx[i] : (uint32_t)i) : 0;
+      key[j] = in ? part_key_nt<L>(V.skeys, i) : 0;
+      val[j] = VALS && in ? part_key_nt<L>(V.svals, i) : 0;
+      idx[j] = IDX && in ? (V.sidx ? __builtin_nontemporal_load(V.sidx + i) : (uint32_t)i) : 0;
     }
+  };
+  // The second level loads the next tile while it places this one.  The
+  // first level does not: its stores go to 256 open runs per workgroup, and
+  // with twice the reads in flight L2 wrote more of those lines back
+  // part-filled.
+  if (LV == 1 && lo < hi) load(lo);
+  for (u64 base = lo; base < hi; base += step) {
+    if (LV == 0) load(base);
+    u64 ck[U], cv[U];
+    uint32_t ci[U];
 #pragma unroll
-    for (uint32_t j = 0; j < kUnroll; ++j) {
+    for (uint32_t j = 0; j < U; ++j) {
+      ck[j] = key[j];
+      cv[j] = val[j];
+      ci[j] = idx[j];
+    }
+    if (LV == 1 && base + step < hi) load(base + step);
+    // per element: bucket (bits 0-11), its lane's share to reserve (bits
+    // 12-18), the lane holding the reservation (bits 19-24), the place in the
+    // group (bits 25-30) and validity (bit 31)
+    uint32_t w[U];
+#pragma unroll
+    for (uint32_t j = 0; j < U; ++j) {
       const u64 i = base + (u64)j * blockDim.x + threadIdx.x;
-      const bool valid = i < hi && !(lv == 0 && (key[j] == kEmpty || key[j] == kTomb));
-      const uint32_t b = valid ? (uint32_t)(hash_of<L>(T, key[j], A.crc_hi, A.crc_lo, A.mul) >> (64 - V.bits)) : 0;
-      bool act = valid;
-      u64 pos = 0;
+      const bool valid = i < hi && !(LV == 0 && (ck[j] == kEmpty || ck[j] == kTomb));
+      const uint32_t b = valid ? (uint32_t)(hash_of<L>(T, ck[j], A.crc_hi, A.crc_lo, A.mul) >> (64 - V.bits)) : 0;
+      w[j] = b | (valid ? (1u << 12) | (1u << 31) : 0u) | (lane << 19);
+    }
+    // Lanes that share the leading lane's bucket reserve their places with
+    // one atomic by the leading lane (decided by ballots alone).
+#pragma unroll
+    for (uint32_t j = 0; j < U; ++j) {
+      bool open = (w[j] >> 31) != 0;
+      const uint32_t b = w[j] & 0xFFFu;
       for (int r = 0; r < kAggRounds; ++r) {
         u64 lt = 0;
         uint32_t ll = 0;
-        const u64 m = match_first(act, b, lt, ll);
+        const u64 m = match_first(open, b, lt, ll);
         if (__popcll(m) < 2) break;
-        u64 at = 0;
-        if ((threadIdx.x & 63) == ll) at = atomicAdd((unsigned long long *)&cur[(uint32_t)lt], (u64)__popcll(m));
-        at = __shfl(at, (int)ll, 64);
-        if ((m >> (threadIdx.x & 63)) & 1) {
-          pos = at + lanes_below(m);
-          act = false;
+        if ((m >> lane) & 1) {
+          open = false;
+          const uint32_t add = lane == ll ? (uint32_t)__popcll(m) : 0u;
+          w[j] = b | (add << 12) | (ll << 19) | (lanes_below(m) << 25) | (1u << 31);
         }
       }
-      if (act) pos = atomicAdd((unsigned long long *)&cur[b], 1ull);
-      if (!valid) continue;
-      part_store<L>(V.dkeys, pos, key[j]);
-      if (V.dvals) part_store<L>(V.dvals, pos, val[j]);
-      if (V.didx) V.didx[pos] = idx[j];
+    }
+    auto put = [&](uint32_t j, uint32_t at) {
+      const u64 pos = (u64)(uint32_t)__shfl((int)at, (int)((w[j] >> 19) & 63u), 64) + ((w[j] >> 25) & 63u);
+      if (!(w[j] >> 31)) return;
+      part_store<L>(V.dkeys, pos, ck[j]);
+      if (VALS) part_store<L>(V.dvals, pos, cv[j]);
+      if (IDX) V.didx[pos] = ci[j];
+    };
+    if (LV == 0) {
+      // one element's reservation and stores at a time
+#pragma unroll
+      for (uint32_t j = 0; j < U; ++j) {
+        const uint32_t add = (w[j] >> 12) & 0x7Fu;
+        put(j, add ? atomicAdd(&cur[w[j] & 0xFFFu], add) : 0u);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      // all of the tile's LDS atomics issued before any result is awaited
+      uint32_t at[U];
+#pragma unroll
+      for (uint32_t j = 0; j < U; ++j) {
+        const uint32_t add = (w[j] >> 12) & 0x7Fu;
+        at[j] = add ? atomicAdd(&cur[w[j] & 0xFFFu], add) : 0u;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < U; ++j) put(j, at[j]);
     }
   }
+}
+
+// Open output runs: a first-level workgroup fills one run per bucket, 256
+// at once, and an XCD's L2 holds the partly written last line of every run of
+// the workgroups resident on its 32 CUs.  With two workgroups per CU (the
+// occupancy their registers allow) those lines were written back part-filled:
+// 1.38 GB written to HBM for 0.8 GB of keys and 920 us per 10^8 Zipf(1.0)
+// keys.  The first level therefore reserves LDS it does not use so that one
+// workgroup runs per CU: 0.92 GB and 775 us.  The second level has at most a
+// few dozen runs per workgroup and keeps the full occupancy.
+constexpr size_t kScatter1LdsPad = 64 * 1024;
+
+template <int L, int LV>
+void launch_scatter(const PartK &k, bool vals, bool idx, hipStream_t s) {
+  const size_t pad = LV == 0 ? kScatter1LdsPad : 0;
+  if (vals && idx)
+    hipLaunchKernelGGL((k_part_scatter<L, true, true, LV>), dim3(k.nwg), dim3(kCountThreads), pad, s, k);
+  else if (vals)
+    hipLaunchKernelGGL((k_part_scatter<L, true, false, LV>), dim3(k.nwg), dim3(kCountThreads), pad, s, k);
+  else if (idx)
+    hipLaunchKernelGGL((k_part_scatter<L, false, true, LV>), dim3(k.nwg), dim3(kCountThreads), pad, s, k);
+  else
+    hipLaunchKernelGGL((k_part_scatter<L, false, false, LV>), dim3(k.nwg), dim3(kCountThreads), pad, s, k);
 }
 
 // insertOrUpdate(k, d, add) by the only lane that updates k in this call
@@ -371,7 +477,6 @@ __global__ void __launch_bounds__(kApplyThreads) k_part_apply(PartK k) {
   __shared__ u64 s_sum[S];
   __shared__ uint32_t s_rep[FL ? S : 1];
   __shared__ uint32_t s_claims;
-  __shared__ uint32_t s_item[2];
   __shared__ long long s_acc[2];
   __shared__ uint32_t s_err;
   crc_tables_build(T);
@@ -380,51 +485,63 @@ __global__ void __launch_bounds__(kApplyThreads) k_part_apply(PartK k) {
     s_sum[q] = 0;
     if (FL) s_rep[q] = ~0u;
   }
+  if (threadIdx.x == 0) s_claims = 0;
+  __syncthreads();
   const BulkArgs &A = k.A;
   const Level &V = k.L[1];
   long long d_used = 0, d_live = 0;
   uint32_t err = 0;
   const uint32_t nitems = V.items[V.nb];
-  for (uint32_t j = blockIdx.x; j < nitems; j += gridDim.x) {
-    if (threadIdx.x == 0) {
-      // the bucket of item j: the last b with items[b] <= j
-      uint32_t a = 0, z = V.nb;  // items[a] <= j < items[z]
-      while (z - a > 1) {
-        const uint32_t m = (a + z) / 2;
-        if (V.items[m] <= j)
-          a = m;
-        else
-          z = m;
-      }
-      s_item[0] = a;
-      s_item[1] = V.items[a + 1] - V.items[a] == 1;
-      s_claims = 0;
-    }
-    __syncthreads();
-    const uint32_t b = s_item[0];
-    const bool alone = s_item[1] != 0;
-    const u64 lo = V.btot[b] + (u64)(j - V.items[b]) * kItemOps;
-    const u64 end = V.btot[b + 1];
-    const u64 hi = lo + kItemOps < end ? lo + kItemOps : end;
-    for (u64 pb = lo; pb < hi; pb += (u64)blockDim.x * kUnroll) {
-     u64 keys[kUnroll], ds[kUnroll];
-     uint32_t idxs[kUnroll];
+  const u64 step = (u64)blockDim.x * kUnroll;
+  constexpr u64 kAlone = 1ull << 63;
+  u64 keys[kUnroll], ds[kUnroll];
+  uint32_t idxs[kUnroll];
+  auto load = [&](u64 pb, u64 hi) {
 #pragma unroll
-     for (uint32_t j = 0; j < kUnroll; ++j) {
-       const u64 p = pb + (u64)j * blockDim.x + threadIdx.x;
-       const bool in = p < hi;
-       keys[j] = in ? part_key<L>(V.dkeys, p) : 0;
-       ds[j] = in ? (V.dvals ? part_key<L>(V.dvals, p) : 1) : 0;
-       idxs[j] = in && FL ? V.didx[p] : 0;
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+      const u64 p = pb + (u64)u * blockDim.x + threadIdx.x;
+      const bool in = p < hi;
+      keys[u] = in ? part_key<L>(V.dkeys, p) : 0;
+      ds[u] = in ? (V.dvals ? part_key<L>(V.dvals, p) : 1) : 0;
+      idxs[u] = in && FL ? V.didx[p] : 0;
+    }
+  };
+  // item j covers [istart[j], istart[j + 1]) without the flag bit
+  u64 lo = 0, hi = 0;
+  bool alone = false;
+  if (blockIdx.x < nitems) {
+    const u64 s0 = V.istart[blockIdx.x];
+    lo = s0 & ~kAlone;
+    hi = V.istart[blockIdx.x + 1] & ~kAlone;
+    alone = (s0 & kAlone) != 0;
+    load(lo, hi);
+  }
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const uint32_t nx = it + gridDim.x;
+    for (u64 pb = lo; pb < hi; pb += step) {
+     u64 ck[kUnroll], cd[kUnroll];
+     uint32_t ci[kUnroll];
+#pragma unroll
+     for (uint32_t u = 0; u < kUnroll; ++u) {
+       ck[u] = keys[u];
+       cd[u] = ds[u];
+       ci[u] = idxs[u];
      }
-     for (uint32_t j = 0; j < kUnroll; ++j) {
+     // the next tile's loads (this item's, else the next item's first) are
+     // in flight while this one is combined
+     if (pb + step < hi) {
+       load(pb + step, hi);
+     } else if (nx < nitems) {
+       load(V.istart[nx] & ~kAlone, V.istart[nx + 1] & ~kAlone);
+     }
+     for (uint32_t u = 0; u < kUnroll; ++u) {
       // equal keys on the lanes of this step first (a batch key is never 0
       // here, so 0 marks lanes past the end)
-      bool act = keys[j] != 0;
+      bool act = ck[u] != 0;
       bool open = act;  // not yet in a group
-      const u64 key = keys[j];
-      u64 d = ds[j];
-      uint32_t idx = idxs[j];
+      const u64 key = ck[u];
+      u64 d = cd[u];
+      uint32_t idx = ci[u];
       // every lane runs every round (the shuffles read all lanes)
       for (int r = 0; r < kAggRounds; ++r) {
         u64 lk = 0;
@@ -479,6 +596,8 @@ __global__ void __launch_bounds__(kApplyThreads) k_part_apply(PartK k) {
      }
     }
     __syncthreads();
+    // nothing reads the claim count again before the barrier that ends the item
+    if (threadIdx.x == 0) s_claims = 0;
     // one upsert per distinct key of the item
     for (uint32_t q = threadIdx.x; q < S; q += blockDim.x) {
       const u64 key = s_key[q];
@@ -493,12 +612,18 @@ __global__ void __launch_bounds__(kApplyThreads) k_part_apply(PartK k) {
       s_sum[q] = 0;
     }
     __syncthreads();
+    if (nx < nitems) {
+      const u64 s0 = V.istart[nx];
+      lo = s0 & ~kAlone;
+      hi = V.istart[nx + 1] & ~kAlone;
+      alone = (s0 & kAlone) != 0;
+    }
   }
   flush_counts(A.status, d_used, d_live, err, s_acc, &s_err);
 }
 
 struct Carved {
-  size_t btot[2], hist[2], items, keys[2], vals[2], idx[2], total;
+  size_t btot[2], hist[2], items, istart, keys[2], vals[2], idx[2], total;
 };
 
 Carved carve(uint64_t n, uint32_t log2c, uint32_t layout, bool with_vals, bool with_flags, uint32_t nwg) {
@@ -514,6 +639,9 @@ Carved carve(uint64_t n, uint32_t log2c, uint32_t layout, bool with_vals, bool w
   }
   o.items = at;
   at += round256(((size_t)nb[1] + 1) * 4);
+  // a bucket of c elements has ceil(c / kItemOps) items
+  o.istart = at;
+  at += round256((n / kItemOps + nb[1] + 2) * 8);
   for (int lv = 0; lv < 2; ++lv) {
     o.keys[lv] = at;
     at += round256(n * kb);
@@ -559,6 +687,7 @@ hipError_t launch_upsert_add_part(const BulkArgs &a, void *scratch, uint32_t num
     V.btot = (uint64_t *)(base + o.btot[lv]);
     V.hist = (uint32_t *)(base + o.hist[lv]);
     V.items = lv == 1 ? (uint32_t *)(base + o.items) : nullptr;
+    V.istart = lv == 1 ? (uint64_t *)(base + o.istart) : nullptr;
     V.dkeys = base + o.keys[lv];
     V.dvals = a.vals ? (void *)(base + o.vals[lv]) : nullptr;
     V.didx = a.flags ? (uint32_t *)(base + o.idx[lv]) : nullptr;
@@ -585,7 +714,14 @@ hipError_t launch_upsert_add_part(const BulkArgs &a, void *scratch, uint32_t num
     LPHT_PART(k_part_count, k.nwg, kCountThreads, k, lv);
     hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(1024), 0, s, k, lv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    LPHT_PART(k_part_scatter, k.nwg, kCountThreads, k, lv);
+    {
+      const bool vals = a.vals != nullptr, idx = a.flags != nullptr;
+      if (a.layout == 0)
+        lv == 0 ? launch_scatter<0, 0>(k, vals, idx, s) : launch_scatter<0, 1>(k, vals, idx, s);
+      else
+        lv == 0 ? launch_scatter<1, 0>(k, vals, idx, s) : launch_scatter<1, 1>(k, vals, idx, s);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
 #undef LPHT_PART
   }
   if (a.flags) {
