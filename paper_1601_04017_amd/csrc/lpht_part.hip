@@ -17,12 +17,13 @@
 // on the order.
 //
 // Passes: the partition runs in two levels, 256 buckets of the top 8 hash
-// bits and then 16 sub-buckets of the next 4 bits inside each, so that a
-// workgroup's scatter has few open output runs at a time and its writes
-// complete whole lines in L2 (one level of 4096 buckets left each XCD's L2
-// with far more partly written lines than it holds).  Skewed streams put one
-// key on most lanes of a wavefront, so the LDS atomics of all passes first
-// combine the lanes that share the leading lane's bucket or key.  Each level is a count
+// bits and then 32 sub-buckets of the next 5 bits inside each (on tables of
+// 2^21 cells or more), so that a workgroup's scatter has few open output runs
+// at a time and its writes complete whole lines in L2 (one level of 4096
+// buckets left each XCD's L2 with far more partly written lines than it
+// holds).  Skewed streams put one key on most lanes of a wavefront, so the
+// LDS atomics of the first level and of the apply first combine the lanes
+// that share the leading lane's bucket or key.  Each level is a count
 // (per-workgroup histograms of a contiguous share; each workgroup reserves
 // its share of every bucket with one atomic on the bucket's total), a scan of
 // the bucket totals by one workgroup (bucket starts; after the second level
@@ -52,15 +53,18 @@ namespace lpht {
 namespace {
 
 constexpr uint32_t kBits1 = 8;          // first-level buckets: 256
-constexpr uint32_t kMaxBits = 12;       // at most 4096 buckets in all (a bucket fits in 12 bits)
+constexpr uint32_t kMaxBits = 13;       // at most 8192 buckets in all (a bucket fits in 13 bits)
 constexpr uint32_t kCountWG = 512;      // workgroups of the count and scatter passes
 constexpr uint32_t kCountThreads = 512;
-constexpr uint32_t kApplyThreads = 1024;
+// apply workgroups: without flags two of 512 threads per CU (one combines
+// while the other makes its upserts), with flags one of 1024
+template <bool FL>
+constexpr uint32_t apply_threads() { return FL ? 1024 : 512; }
 constexpr uint32_t kItemOps = 32768;    // operations per apply work item
-// LDS combining slots: 8192 of 16 B (128 KiB, one workgroup per CU) hold the
-// ~4.4k distinct keys of a bucket of a 10^8-key Zipf(1) batch; with flags
-// each slot also keeps its representative's index, and 4096 slots fit
-constexpr uint32_t kSlotsNoFlags = 8192;
+// LDS combining slots: 4096 of 16 B (64 KiB, two workgroups per CU; with
+// flags each slot also keeps its representative's index) hold the ~2.2k
+// distinct keys of a bucket of a 10^8-key Zipf(1) batch in 8192 buckets
+constexpr uint32_t kSlotsNoFlags = 4096;
 constexpr uint32_t kSlotsFlags = 4096;
 constexpr uint32_t kProbe = 32;
 constexpr uint32_t kUnroll = 8;         // loads in flight per lane in the streaming passes
@@ -355,24 +359,30 @@ __global__ void __launch_bounds__(kCountThreads) k_part_scatter(PartK k) {
       ci[j] = idx[j];
     }
     if (LV == 1 && base + step < hi) load(base + step);
-    // per element: bucket (bits 0-11), its lane's share to reserve (bits
-    // 12-18), the lane holding the reservation (bits 19-24), the place in the
-    // group (bits 25-30) and validity (bit 31)
+    // per element: bucket (bits 0-12), its lane's share to reserve (bits
+    // 13-19), the lane holding the reservation (bits 20-25) and the place in
+    // the group (bits 26-31)
     uint32_t w[U];
+    bool valid[U];
 #pragma unroll
     for (uint32_t j = 0; j < U; ++j) {
       const u64 i = base + (u64)j * blockDim.x + threadIdx.x;
-      const bool valid = i < hi && !(LV == 0 && (ck[j] == kEmpty || ck[j] == kTomb));
-      const uint32_t b = valid ? (uint32_t)(hash_of<L>(T, ck[j], A.crc_hi, A.crc_lo, A.mul) >> (64 - V.bits)) : 0;
-      w[j] = b | (valid ? (1u << 12) | (1u << 31) : 0u) | (lane << 19);
+      valid[j] = i < hi && !(LV == 0 && (ck[j] == kEmpty || ck[j] == kTomb));
+      const uint32_t b = valid[j] ? (uint32_t)(hash_of<L>(T, ck[j], A.crc_hi, A.crc_lo, A.mul) >> (64 - V.bits)) : 0;
+      w[j] = b | (valid[j] ? 1u << 13 : 0u) | (lane << 20);
     }
     // Lanes that share the leading lane's bucket reserve their places with
-    // one atomic by the leading lane (decided by ballots alone).
+    // one atomic by the leading lane (decided by ballots alone).  Only the
+    // first level: its hot buckets hold the stream's most frequent keys,
+    // while the second level's lanes spread over the 32 sub-buckets of one
+    // or two first-level buckets, rarely more than two or three to one, and
+    // the ballot rounds cost more than the LDS atomics they save.
+    constexpr int kRounds = LV == 0 ? kAggRounds : 0;
 #pragma unroll
     for (uint32_t j = 0; j < U; ++j) {
-      bool open = (w[j] >> 31) != 0;
-      const uint32_t b = w[j] & 0xFFFu;
-      for (int r = 0; r < kAggRounds; ++r) {
+      bool open = valid[j];
+      const uint32_t b = w[j] & 0x1FFFu;
+      for (int r = 0; r < kRounds; ++r) {
         u64 lt = 0;
         uint32_t ll = 0;
         const u64 m = match_first(open, b, lt, ll);
@@ -380,13 +390,13 @@ __global__ void __launch_bounds__(kCountThreads) k_part_scatter(PartK k) {
         if ((m >> lane) & 1) {
           open = false;
           const uint32_t add = lane == ll ? (uint32_t)__popcll(m) : 0u;
-          w[j] = b | (add << 12) | (ll << 19) | (lanes_below(m) << 25) | (1u << 31);
+          w[j] = b | (add << 13) | (ll << 20) | (lanes_below(m) << 26);
         }
       }
     }
     auto put = [&](uint32_t j, uint32_t at) {
-      const u64 pos = (u64)(uint32_t)__shfl((int)at, (int)((w[j] >> 19) & 63u), 64) + ((w[j] >> 25) & 63u);
-      if (!(w[j] >> 31)) return;
+      const u64 pos = (u64)(uint32_t)__shfl((int)at, (int)((w[j] >> 20) & 63u), 64) + (w[j] >> 26);
+      if (!valid[j]) return;
       part_store<L>(V.dkeys, pos, ck[j]);
       if (VALS) part_store<L>(V.dvals, pos, cv[j]);
       if (IDX) V.didx[pos] = ci[j];
@@ -395,8 +405,8 @@ __global__ void __launch_bounds__(kCountThreads) k_part_scatter(PartK k) {
       // one element's reservation and stores at a time
 #pragma unroll
       for (uint32_t j = 0; j < U; ++j) {
-        const uint32_t add = (w[j] >> 12) & 0x7Fu;
-        put(j, add ? atomicAdd(&cur[w[j] & 0xFFFu], add) : 0u);
+        const uint32_t add = (w[j] >> 13) & 0x7Fu;
+        put(j, add ? atomicAdd(&cur[w[j] & 0x1FFFu], add) : 0u);
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
@@ -404,8 +414,8 @@ __global__ void __launch_bounds__(kCountThreads) k_part_scatter(PartK k) {
       uint32_t at[U];
 #pragma unroll
       for (uint32_t j = 0; j < U; ++j) {
-        const uint32_t add = (w[j] >> 12) & 0x7Fu;
-        at[j] = add ? atomicAdd(&cur[w[j] & 0xFFFu], add) : 0u;
+        const uint32_t add = (w[j] >> 13) & 0x7Fu;
+        at[j] = add ? atomicAdd(&cur[w[j] & 0x1FFFu], add) : 0u;
       }
 #pragma unroll
       for (uint32_t j = 0; j < U; ++j) put(j, at[j]);
@@ -468,9 +478,9 @@ __device__ __forceinline__ uint8_t upsert_add_excl_kv64(const BulkArgs &A, const
 }
 
 template <int L, bool FL>
-__global__ void __launch_bounds__(kApplyThreads) k_part_apply(PartK k) {
+__global__ void __launch_bounds__(apply_threads<FL>()) k_part_apply(PartK k) {
   constexpr uint32_t S = FL ? kSlotsFlags : kSlotsNoFlags;
-  constexpr uint32_t SB = FL ? 12 : 13;
+  constexpr uint32_t SB = 12;
   static_assert((1u << SB) == S, "slot bits");
   __shared__ uint32_t T[8][256];
   __shared__ u64 s_key[S];
@@ -549,7 +559,8 @@ __global__ void __launch_bounds__(kApplyThreads) k_part_apply(PartK k) {
         const u64 m = match_first(open, key, lk, ll);
         if (__popcll(m) < 2) break;
         const bool in = (m >> (threadIdx.x & 63)) & 1;
-        const u64 sum = (u64)wave_sum(in ? (long long)d : 0);
+        // without values every operation adds 1
+        const u64 sum = V.dvals ? (u64)wave_sum(in ? (long long)d : 0) : (u64)__popcll(m);
         const uint32_t imin = FL ? wave_min_u32(in ? idx : ~0u) : 0;
         if (in) {
           open = false;
@@ -698,7 +709,7 @@ hipError_t launch_upsert_add_part(const BulkArgs &a, void *scratch, uint32_t num
   k.L[1].skeys = k.L[0].dkeys;
   k.L[1].svals = k.L[0].dvals;
   k.L[1].sidx = k.L[0].didx;
-  const uint32_t apply_grid = std::max<uint32_t>(1, num_cus);  // one workgroup per CU (LDS)
+  const uint32_t cus = std::max<uint32_t>(1, num_cus);
   hipError_t e;
   hipLaunchKernelGGL(k_part_zero, dim3(1), dim3(1024), 0, s, k);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -724,16 +735,17 @@ hipError_t launch_upsert_add_part(const BulkArgs &a, void *scratch, uint32_t num
     }
 #undef LPHT_PART
   }
+  // as many apply workgroups as fit at once (LDS bounds them)
   if (a.flags) {
     if (a.layout == 0)
-      hipLaunchKernelGGL((k_part_apply<0, true>), dim3(apply_grid), dim3(kApplyThreads), 0, s, k);
+      hipLaunchKernelGGL((k_part_apply<0, true>), dim3(cus), dim3(apply_threads<true>()), 0, s, k);
     else
-      hipLaunchKernelGGL((k_part_apply<1, true>), dim3(apply_grid), dim3(kApplyThreads), 0, s, k);
+      hipLaunchKernelGGL((k_part_apply<1, true>), dim3(cus), dim3(apply_threads<true>()), 0, s, k);
   } else {
     if (a.layout == 0)
-      hipLaunchKernelGGL((k_part_apply<0, false>), dim3(apply_grid), dim3(kApplyThreads), 0, s, k);
+      hipLaunchKernelGGL((k_part_apply<0, false>), dim3(2 * cus), dim3(apply_threads<false>()), 0, s, k);
     else
-      hipLaunchKernelGGL((k_part_apply<1, false>), dim3(apply_grid), dim3(kApplyThreads), 0, s, k);
+      hipLaunchKernelGGL((k_part_apply<1, false>), dim3(2 * cus), dim3(apply_threads<false>()), 0, s, k);
   }
   return hipGetLastError();
 }
