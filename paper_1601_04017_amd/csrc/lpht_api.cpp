@@ -78,6 +78,8 @@ struct PendingFree {
 std::mutex g_pending_mu;
 std::vector<PendingFree> g_pending;
 std::vector<hipEvent_t> g_spare_events;
+// blocks whose event cannot be waited on: returned when the pools are released
+std::vector<PendingFree> g_stuck;
 
 // Returns to the pool every pending block of `device` whose event has
 // completed (all of them, waiting, when `wait`), ordered on stream s.
@@ -86,10 +88,22 @@ void reap_pending(int device, hipStream_t s, bool wait) {
   size_t k = 0;
   for (size_t i = 0; i < g_pending.size(); ++i) {
     PendingFree &f = g_pending[i];
-    const bool done = f.device == device &&
-                      (wait ? hipEventSynchronize(f.ev) == hipSuccess : hipEventQuery(f.ev) == hipSuccess);
+    hipError_t q = hipErrorNotReady;
+    if (f.device == device) q = wait ? hipEventSynchronize(f.ev) : hipEventQuery(f.ev);
+    const bool done = q == hipSuccess;
+    if (q != hipSuccess && q != hipErrorNotReady) {
+      // The event cannot be waited on (HIP has reported events recorded into
+      // a stream capture this way): the error is the pool's, not the
+      // caller's, and the block stays out of the pool until the pools are
+      // released after a device synchronisation.
+      (void)hipGetLastError();
+      g_stuck.push_back(f);
+      continue;
+    }
     if (done) {
-      (void)hipFreeAsync(f.p, s);
+      // a failed free leaves the block to the pool; its error is not the
+      // caller's to read
+      if (hipFreeAsync(f.p, s) != hipSuccess) (void)hipGetLastError();
       g_spare_events.push_back(f.ev);
     } else {
       g_pending[k++] = f;
@@ -145,14 +159,15 @@ void pool_free(void *p, hipStream_t s) {
         g_pending.push_back({p, ev, device});
         queued = true;
       } else {
+        (void)hipGetLastError();  // handled below: the free waits for the stream instead
         (void)hipEventDestroy(ev);
       }
     }
   }
   if (!queued) {
     // no event: wait for the stream, then free
-    (void)hipStreamSynchronize(s);
-    (void)hipFreeAsync(p, s);
+    if (hipStreamSynchronize(s) != hipSuccess) (void)hipGetLastError();
+    if (hipFreeAsync(p, s) != hipSuccess) (void)hipGetLastError();
   }
   g_pool_blocks.fetch_sub(1);
   reap_pending(device, s, false);
@@ -173,6 +188,19 @@ int release_pools() {
     // the frees of destroyed tables complete in stream order: wait for them
     if (hipSetDevice(d) == hipSuccess) {
       reap_pending(d, nullptr, true);
+      if (hipDeviceSynchronize() == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_pending_mu);
+        size_t k = 0;
+        for (const PendingFree &f : g_stuck) {
+          if (f.device == d) {
+            if (hipFreeAsync(f.p, nullptr) != hipSuccess) (void)hipGetLastError();
+            if (hipEventDestroy(f.ev) != hipSuccess) (void)hipGetLastError();
+          } else {
+            g_stuck[k++] = f;
+          }
+        }
+        g_stuck.resize(k);
+      }
     }
     if (hipSetDevice(d) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
         hipMemPoolTrimTo(g_pools[d], 0) != hipSuccess || hipMemPoolDestroy(g_pools[d]) != hipSuccess)

@@ -572,6 +572,7 @@ uint32_t async_min_log2(uint32_t grid, uint32_t alpha_num, uint32_t alpha_den) {
 }
 
 hipError_t launch_async_insert(const AsyncArgs &a, hipStream_t s) {
+  drop_stale_error();
   if (a.layout > 1 || !a.ctl || !a.grid || a.nladder < 1 || a.nladder > kAsyncLadder + 1) return hipErrorInvalidValue;
   int dev = 0, khz = 0;
   hipError_t e = hipGetDevice(&dev);

@@ -1175,6 +1175,7 @@ size_t bulk_merge_scratch_bytes(uint64_t inputs, uint64_t max_items, uint32_t lo
 }
 
 hipError_t launch_bulk_merge(const BulkMergeArgs &a, hipStream_t s) {
+  drop_stale_error();
   if (a.layout > 1 || a.op > 1 || a.log2_new < 6 || a.log2_new > kBulkMaxLog2 || !a.new_cells || !a.scratch ||
       !a.status)
     return hipErrorInvalidValue;

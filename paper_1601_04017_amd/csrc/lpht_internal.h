@@ -66,6 +66,14 @@ struct LaunchCfg {
   uint32_t aggregate;
 };
 
+// A launch wrapper reports its launches through hipGetLastError.  HIP keeps
+// the error of a failed call for the calling thread until hipGetLastError
+// reads it, and later successful calls leave it in place, so a wrapper first
+// drops whatever an earlier call of the thread left there (another
+// library's, or a failure the caller already handled): otherwise its own
+// successful launch would report that error.
+inline void drop_stale_error() { (void)hipGetLastError(); }
+
 // Kernel launchers (lpht_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_bulk(OpKind op, const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s);
 // One launch over `ndesc` descriptors of the same layout, operation and

@@ -1568,6 +1568,7 @@ static inline uint32_t grid_for(u64 work_items, const LaunchCfg &cfg) {
 
 template <int LAYOUT, int OP, int UP, int G>
 static hipError_t launch_g(const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  drop_stale_error();
   const u64 nrounds = (a.n + ROUND - 1) / ROUND;
   const uint32_t grid = grid_for(nrounds * 64, cfg);
   const size_t lds = (size_t)(cfg.block_threads / 64) * (bulk_lds_bytes_per_wave(OP) + kStageBytesPerWave);
@@ -1578,6 +1579,7 @@ static hipError_t launch_g(const BulkArgs &a, const LaunchCfg &cfg, hipStream_t 
 template <int LAYOUT, int OP, int UP, int G>
 static hipError_t launch_mg(const BulkArgs *descs, const u64 *rs, uint32_t ndesc, u64 total,
                             const LaunchCfg &cfg, hipStream_t s) {
+  drop_stale_error();
   const uint32_t grid = grid_for(total * 64, cfg);
   const size_t lds = (size_t)(cfg.block_threads / 64) * bulk_lds_bytes_per_wave(OP);
   hipLaunchKernelGGL((k_bulk_multi<LAYOUT, OP, UP, G>), dim3(grid), dim3(cfg.block_threads), lds, s,
@@ -1651,6 +1653,7 @@ static hipError_t launch_layout(OpKind op, const BulkArgs &a, const LaunchCfg &c
 }
 
 hipError_t launch_bulk(OpKind op, const BulkArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  drop_stale_error();
   if (a.n == 0) return hipSuccess;
   if (op == OP_UPSERT && a.up == 1 && a.aggregate) {
     const u64 nchunks = (a.n + AGG_CHUNK - 1) / AGG_CHUNK;
@@ -1666,6 +1669,7 @@ hipError_t launch_bulk(OpKind op, const BulkArgs &a, const LaunchCfg &cfg, hipSt
 }
 
 hipError_t launch_fill_zero(void *ptr, uint64_t bytes, const LaunchCfg &cfg, hipStream_t s) {
+  drop_stale_error();
   (void)cfg;
   u64 n16 = bytes / 16;
   if (n16 == 0) return hipSuccess;
@@ -1680,16 +1684,19 @@ hipError_t launch_fill_zero(void *ptr, uint64_t bytes, const LaunchCfg &cfg, hip
 
 hipError_t launch_set_status(DevStatus *st, uint64_t used, uint64_t live, int clear_err,
                              hipStream_t s) {
+  drop_stale_error();
   hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, st, (u64)used, (u64)live, clear_err);
   return hipGetLastError();
 }
 
 hipError_t launch_count_totals(const DevStatus *st, uint64_t *out, hipStream_t s) {
+  drop_stale_error();
   hipLaunchKernelGGL(k_count_totals, dim3(1), dim3(64), 0, s, st, (u64 *)out);
   return hipGetLastError();
 }
 
 hipError_t launch_gen_keys(void *out, uint64_t n, uint32_t layout, uint64_t seed, hipStream_t s) {
+  drop_stale_error();
   if (n == 0) return hipSuccess;
   const u64 blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
   hipLaunchKernelGGL(k_gen_keys, dim3((uint32_t)blocks), dim3(256), 0, s, out, (u64)n, layout, (u64)seed);
@@ -1697,6 +1704,7 @@ hipError_t launch_gen_keys(void *out, uint64_t n, uint32_t layout, uint64_t seed
 }
 
 hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first_q, hipStream_t s) {
+  drop_stale_error();
   hipLaunchKernelGGL(k_persist_init, dim3(1), dim3(kPersistRing), 0, s, dev, st, (u64)first_q);
   return hipGetLastError();
 }
@@ -1704,6 +1712,7 @@ hipError_t launch_persist_init(PersistDev *dev, PersistState *st, uint64_t first
 hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistReq *ring, PersistReq *dring,
                           PersistDone *done, PersistDev *dev, PersistState *st, uint64_t idle_ticks,
                           uint32_t grid, hipStream_t s) {
+  drop_stale_error();
   if (grid < kPersistGroups || grid % kPersistGroups) return hipErrorInvalidValue;
   const size_t lds = 4 * kPersistWaveLds;
   hipLaunchKernelGGL(k_persist_arm, dim3(1), dim3(64), 0, s, st, ctl, (u64)grid * 4 - 1);
@@ -1720,6 +1729,7 @@ hipError_t launch_persist(uint32_t layout, const PersistCtl *ctl, const PersistR
 
 hipError_t launch_recount(const void *cells, uint32_t log2c, uint32_t layout, DevStatus *st,
                           const LaunchCfg &cfg, hipStream_t s) {
+  drop_stale_error();
   u64 cap = 1ull << log2c;
   uint32_t grid = grid_for(cap, cfg);
   if (layout == 0)
@@ -1733,6 +1743,7 @@ hipError_t launch_migrate(const void *old_cells, uint32_t log2_old, void *new_ce
                           uint32_t log2_new, uint32_t layout, uint32_t crc_hi, uint32_t crc_lo,
                           uint64_t mul, int old_is_full, DevStatus *st, const LaunchCfg &cfg,
                           hipStream_t s) {
+  drop_stale_error();
   const u64 cap = 1ull << log2_old;
   const u64 new_bytes = (1ull << log2_new) * (layout == 0 ? 8ull : 16ull);
   const uint32_t g = log2_new - log2_old;

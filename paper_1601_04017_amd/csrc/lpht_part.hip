@@ -683,6 +683,7 @@ size_t part_scratch_bytes(uint64_t n, uint32_t log2c, uint32_t layout, bool with
 }
 
 hipError_t launch_upsert_add_part(const BulkArgs &a, void *scratch, uint32_t num_cus, hipStream_t s) {
+  drop_stale_error();
   if (a.n == 0) return hipSuccess;
   if (!part_applies(a.n, a.log2c) || a.layout > 1 || !scratch || a.kinds) return hipErrorInvalidValue;
   PartK k{};

@@ -59,6 +59,7 @@ struct Req {
   lpht_completion c;
   bool done = false;
   uint64_t need = 0;  // bytes accounted by admission (staging and growth)
+  uint64_t grow = 0;  // the growth part of `need`
   uint64_t arena_off = ~0ull;  // resident mode: the request's staging in the arena
   // resident mode, a migration entry of the server's own: its table grows
   // into mig_cells before `waiting` is posted
@@ -133,22 +134,39 @@ struct lpht_server {
 
 namespace {
 
+uint64_t table_bytes_of(const lpht_table *t) { return cell_bytes(t->cfg.layout) << t->log2c; }
+
 uint64_t table_bytes(const lpht_server *S) {
   uint64_t b = 0;
   for (auto *t : S->tables) b += cell_bytes(t->cfg.layout) << t->log2c;
   return b;
 }
 
-// Bytes a growth before `b` insertions would allocate for the new table.
+// A table that grew for request q is counted at its new size from then on;
+// until q retires, its reservation stands for the old cells instead (freed
+// once the work queued before the growth is done), not for the new ones a
+// second time.
+void growth_done(lpht_server *S, Req *q, uint64_t before) {
+  if (!q->grow || table_bytes_of(S->tables[q->r.table]) == before) return;
+  const uint64_t keep = std::min<uint64_t>(q->grow, before);
+  S->staging_bytes -= q->grow - keep;
+  q->need -= q->grow - keep;
+  q->grow = keep;
+}
+
+// Bytes a growth before `b` insertions would allocate for the new table: an
+// upper bound, as the growth rule decides on exact counts, and insertions
+// made on the table since its counts were last exact (`pending`) may each
+// have added a live key.
 uint64_t growth_bytes(const lpht_table *t, uint64_t b) {
   const uint64_t c = 1ull << t->log2c;
   if (b == 0 || within_fill(t, t->known_used + t->pending + b, c)) return 0;
+  const uint64_t live = t->known_live + t->pending + b;
   uint32_t target = t->log2c;
-  if ((unsigned __int128)(t->known_live + b) * 2 * t->cfg.max_fill_den >
-      (unsigned __int128)c * t->cfg.max_fill_num) {
+  if ((unsigned __int128)live * 2 * t->cfg.max_fill_den > (unsigned __int128)c * t->cfg.max_fill_num) {
     do {
       ++target;
-    } while (target < 34 && !within_fill(t, t->known_live + b, 1ull << target));
+    } while (target < 34 && !within_fill(t, live, 1ull << target));
   }
   // the old and the new table coexist during a migration; a chain of
   // doublings peaks at the last one
@@ -248,6 +266,8 @@ void launch_group(lpht_server *S, std::vector<Req *> &group) {
       ops.push_back(o);
     }
   }
+  std::vector<uint64_t> before(group.size());
+  for (size_t i = 0; i < group.size(); ++i) before[i] = table_bytes_of(S->tables[group[i]->r.table]);
   if (!ops.empty()) {
     const int rc = lpht_batch_run(S->batches[si], ops.data(), (uint32_t)ops.size(), (void *)s);
     S->st.launches_phases += 1;
@@ -255,6 +275,7 @@ void launch_group(lpht_server *S, std::vector<Req *> &group) {
       for (Req *q : group)
         if (q->c.status == LPHT_OK) q->c.status = rc;
   }
+  for (size_t i = 0; i < group.size(); ++i) growth_done(S, group[i], before[i]);
   const size_t area = 4 * S->tables.size();
   for (uint32_t ti : g.tables)
     (void)launch_count_totals(S->tables[ti]->status, S->d_totals + si * area + 4 * ti, s);
@@ -327,7 +348,8 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
     Req *q = S->fifo[t].front();
     // the staging comes from the arena; the budget counts it while in use
     const uint64_t staging = staging_size(S, q);
-    const uint64_t need = round256(staging) + growth_bytes(S->tables[t], q->count[1]);
+    const uint64_t grow = growth_bytes(S->tables[t], q->count[1]);
+    const uint64_t need = round256(staging) + grow;
     uint64_t off = ~0ull;
     const bool over = S->cfg.hbm_budget && hbm + need > S->cfg.hbm_budget;
     if (over || (off = arena_alloc(S, staging)) == ~0ull) {
@@ -349,6 +371,7 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
     S->fifo[t].pop_front();
     S->busy[t] = 1;
     q->need = need;
+    q->grow = grow;
     q->arena_off = off;
     hbm += need;
     S->staging_bytes += need;
@@ -527,6 +550,7 @@ void persist_migration_done(lpht_server *S, Req *m, uint32_t e) {
     S->grow_wait.push_back(q);
   } else {
     // the old table is no longer read: its last reader was this entry
+    const uint64_t before = table_bytes_of(t);
     dev_free(t, t->cells, cb << t->log2c, S->streams[0]);
     t->cells = m->mig_cells;
     t->stats.migrations++;
@@ -534,6 +558,7 @@ void persist_migration_done(lpht_server *S, Req *m, uint32_t e) {
     t->stats.cells_migrated += 1ull << t->log2c;
     t->log2c += 1;
     S->st.kernel_growths++;
+    growth_done(S, q, before);
     persist_grow_then_post(S, q);
   }
   delete m;
@@ -597,8 +622,10 @@ bool persist_step(lpht_server *S, std::vector<Req *> &admitted) {
       hipStream_t s = S->streams[0];
       for (Req *q : S->grow_wait) {
         lpht_table *t = S->tables[q->r.table];
+        const uint64_t before = table_bytes_of(t);
         const int rc = grow_before_batch(t, q->count[1], s);
         t->pending = 0;  // the posted request accounts for its insertions itself
+        growth_done(S, q, before);
         if (rc) {
           // the table could not grow: the request fails as a whole
           q->c.status = rc;

@@ -241,6 +241,7 @@ size_t shrink_scratch_bytes(uint32_t log2_old, uint32_t log2_new) {
 hipError_t launch_shrink(void *old_cells, uint32_t log2_old, void *new_cells, uint32_t log2_new,
                          uint32_t layout, uint32_t crc_hi, uint32_t crc_lo, uint64_t mul, uint32_t *scratch,
                          DevStatus *st, const LaunchCfg &cfg, hipStream_t s) {
+  drop_stale_error();
   if (log2_new >= log2_old || log2_old > 40 || layout > 1) return hipErrorInvalidValue;
   if (log2_new >= kShrinkLocalLog2) {
     if (!scratch) return hipErrorInvalidValue;

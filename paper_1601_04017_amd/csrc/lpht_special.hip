@@ -167,6 +167,7 @@ __global__ void __launch_bounds__(256) k_special_apply(OpKind op, uint32_t up, c
 hipError_t launch_special(uint32_t layout, OpKind op, uint32_t up, const void *keys, const void *vals, uint64_t n,
                           void *vals_out, uint8_t *flags, SpecialSlots *sp, uint32_t *scratch, bool clear,
                           hipStream_t s) {
+  drop_stale_error();
   if (layout > 1 || !sp || !scratch || (n && !keys)) return hipErrorInvalidValue;
   if (n) {
     u64 blocks = (n + 255) / 256;

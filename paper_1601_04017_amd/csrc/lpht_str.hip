@@ -344,6 +344,7 @@ uint32_t grid_of(u64 items, uint32_t num_cus) {
 }  // namespace
 
 hipError_t launch_str_op(int kind, const StrArgs &a, uint32_t num_cus, hipStream_t s) {
+  drop_stale_error();
   const bool inserting = kind == kStrInsert || kind == kStrUpsert;
   const uint32_t g = grid_of(inserting ? (a.n + kStrGroup - 1) / kStrGroup : a.n, num_cus);
   if (inserting) {
@@ -362,6 +363,7 @@ hipError_t launch_str_op(int kind, const StrArgs &a, uint32_t num_cus, hipStream
 }
 
 hipError_t launch_str_migrate(const StrMigArgs &a, uint32_t num_cus, hipStream_t s) {
+  drop_stale_error();
   hipLaunchKernelGGL(k_str_ctl, dim3(1), dim3(64), 0, s, a.ctl, (u64)8, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -370,6 +372,7 @@ hipError_t launch_str_migrate(const StrMigArgs &a, uint32_t num_cus, hipStream_t
 }
 
 hipError_t launch_str_recount(const void *cells, uint32_t log2c, StrCtl *ctl, uint32_t num_cus, hipStream_t s) {
+  drop_stale_error();
   hipLaunchKernelGGL(k_str_ctl, dim3(1), dim3(64), 0, s, ctl, (u64)0, 1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -379,6 +382,7 @@ hipError_t launch_str_recount(const void *cells, uint32_t log2c, StrCtl *ctl, ui
 }
 
 hipError_t launch_str_init(StrCtl *ctl, hipStream_t s) {
+  drop_stale_error();
   hipLaunchKernelGGL(k_str_ctl, dim3(1), dim3(64), 0, s, ctl, (u64)8, 0);
   return hipGetLastError();
 }

@@ -201,18 +201,22 @@ def load(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise RuntimeError(f"liblpht.so not built ({path}); run python -m paper_1601_04017_amd.build")
+        # torch first: its wheel carries its own HIP runtime (same soname as
+        # the one liblpht.so was linked against), and loaded first it is the
+        # one liblpht.so binds to.  Loaded after liblpht.so, the process would
+        # hold two HIP runtimes, and torch's streams and errors would live in
+        # the other one.  Also, atexit runs its hooks last-registered first,
+        # so the hook below runs before torch's own exit handlers.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(path)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
         _lib = L
-        # atexit runs its hooks last-registered first: importing torch here
-        # first makes this hook run before torch's own exit handlers
-        try:
-            import torch  # noqa: F401
-        except ImportError:
-            pass
         atexit.register(shutdown)
     return _lib
 

@@ -18,6 +18,12 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libroofline.so not built ({LIB_PATH})")
+        # torch's HIP runtime first, so that this library binds to it (see
+        # lpht.load)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, u64 = ctypes.c_void_p, ctypes.c_uint64
         L.rl_gather.argtypes = [vp, u64, ctypes.c_int, u64, u64, vp, vp]

@@ -116,3 +116,21 @@ def test_hash_choice_validated_on_host(lib):
     cfg.reserved0 = 1
     assert lib.lpht_create(ctypes.byref(cfg), None, ctypes.byref(out)) == lpht.ERR_INVALID
     assert not out.value
+
+
+def test_library_binds_to_one_hip_runtime():
+    # torch's wheel carries its own HIP runtime with the soname liblpht.so was
+    # linked against; the binding loads torch first so that the process holds
+    # one runtime (torch's streams and errors must be the library's own)
+    import ast
+    import subprocess
+    import sys
+    code = ("from paper_1601_04017_amd import lpht, roofline\n"
+            "lpht.load()\n"
+            "roofline.load()\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    paths = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(paths) == 1, paths
