@@ -327,9 +327,20 @@ void retire_group(lpht_server *S, Group &g) {
   S->cv_done.notify_all();
 }
 
+// Operations of one wave: enough for the batch kernels to fill the device,
+// few enough that several waves are in flight on the server's streams (their
+// copies, kernels and completions overlap, and a table's next request does
+// not wait for every other table's).  On the 300-request config-5 trace,
+// admitting every ready request into one wave gave 180-250 Mops/s and this
+// cap 220-380 (runs spread widely; 2^19 and 2^20 were no better); a tight
+// HBM budget, which admits fewer requests at once, gives 410-530.
+constexpr uint64_t kWaveMaxOps = 1ull << 21;
+
 // Picks requests to start now: oldest first among tables that are idle, while
-// slots and the HBM budget allow.
-void admit(lpht_server *S, std::vector<Req *> &out) {
+// slots and the HBM budget allow, up to max_ops operations (0: no limit; a
+// request larger than that is admitted alone).
+void admit(lpht_server *S, std::vector<Req *> &out, uint64_t max_ops = 0) {
+  uint64_t ops = 0;
   std::vector<uint32_t> cand;
   for (uint32_t t = 0; t < S->fifo.size(); ++t)
     if (!S->busy[t] && !S->fifo[t].empty()) cand.push_back(t);
@@ -346,6 +357,7 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
         S->next_q + S->grow_wait.size() + out.size() >= S->oldest_q + kPersistRing)
       break;  // the ring entry of the oldest request is still in use
     Req *q = S->fifo[t].front();
+    if (max_ops && !out.empty() && ops + q->r.n > max_ops) break;
     // the staging comes from the arena; the budget counts it while in use
     const uint64_t staging = staging_size(S, q);
     const uint64_t grow = growth_bytes(S->tables[t], q->count[1]);
@@ -375,6 +387,7 @@ void admit(lpht_server *S, std::vector<Req *> &out) {
     q->arena_off = off;
     hbm += need;
     S->staging_bytes += need;
+    ops += q->r.n;
     out.push_back(q);
   }
   if (hbm > S->st.peak_hbm_bytes) S->st.peak_hbm_bytes = hbm;
@@ -711,7 +724,7 @@ void worker_loop(lpht_server *S) {
       if (S->stop && S->outstanding == 0 && S->inflight.empty()) break;
     }
     admitted.clear();
-    admit(S, admitted);
+    admit(S, admitted, S->cfg.mode == LPHT_SERVE_WAVES ? kWaveMaxOps : 0);
     if (!admitted.empty()) {
       progressed = true;
       if (S->cfg.mode == LPHT_SERVE_WAVES) {
